@@ -1,0 +1,202 @@
+/*
+ * ddamg.h - C ABI of the MI355X (gfx950) multi-rhs x multi-shift twisted-mass
+ * DD-alpha-AMG solver.
+ *
+ * Method: Yamamoto, Bacchio, Finkenrath, "Implementation of Simultaneous
+ * Inversion of a Multi-shifted Dirac Matrix for Twisted-Mass Fermions within
+ * DDalphaAMG" (arXiv:2201.03872).  Section 1/3: many right-hand sides and many
+ * twisted-mass values are inverted simultaneously; section 2: the
+ * preconditioner is red-black SAP plus aggregation-based coarse-grid
+ * correction, recursive over levels; section 4: FGMRES at the top level to a
+ * 1e-10 goal residual, FGMRES / (block) GMRES on the coarse levels; Fig. 6
+ * caption: D_TM = D_W + i (delta mu) mu gamma5.
+ *
+ * Operator (every column c has its own twisted mass mu_c):
+ *   D(mu) psi(x) = (4 + m0) psi(x) + i mu gamma5 psi(x)
+ *                  - 1/2 sum_nu [ (1 - gamma_nu) U_nu(x) psi(x+nu)
+ *                               + (1 + gamma_nu) U_nu(x-nu)^dag psi(x-nu) ]
+ *   m0 = 1/(2 kappa) - 4; periodic in x, y, z; antiperiodic in t (the sign
+ *   multiplies the hop across the t boundary and is never folded into links).
+ *   Chiral gamma basis: gamma_k = [[0,-i s_k],[i s_k,0]], gamma_4 = [[0,1],[1,0]],
+ *   gamma5 = diag(1,1,-1,-1).
+ *
+ * Canonical layouts at this boundary (the "one vector after the other"
+ * layout of the paper's Fig. 2, left; the library converts once per call to
+ * its internal column-tiled layout, never per operator application inside a
+ * solve):
+ *   site index      i = x + Lx*(y + Ly*(z + Lz*t)),   mu = 0..3 = x,y,z,t
+ *   gauge           double [V][4 mu][3 row][3 col][re,im]; U[x][mu] links x -> x+mu
+ *   fine vectors    double [col][V][4 spin][3 colour][re,im]
+ *   coarse vectors  double [col][Vc][2N][re,im]    (level l > 0; Vc in the
+ *                   lexicographic order of the coarse lattice, coarse dof
+ *                   index = chirality*N + j, chirality 0 = gamma5 +1)
+ *   coarse blocks   double [Vc][9][2N row][2N col][re,im]; slot 0 = self block
+ *                   (without the twist), 1+nu = hop to a+nu, 5+nu = hop to a-nu
+ *   solve columns   col = r*n_shift + k  for rhs r and shift k.
+ *
+ * Memory: every vector argument (x, y, b, f) is a DEVICE pointer on the
+ * context's HIP stream (e.g. a torch tensor's data_ptr() on torch's current
+ * stream); mu arrays, blocks and test vectors are HOST pointers.  The caller
+ * owns every array; the library copies the gauge field at setup and owns the
+ * context until ddamg_destroy.  One context per host thread.
+ *
+ * Errors: 0 on success; negative values are errors (no exception crosses the
+ * ABI); +1 = DDAMG_NOT_CONVERGED (the solution is written and per-column
+ * residuals are reported).  ddamg_strerror returns a static string.
+ */
+#ifndef DDAMG_H
+#define DDAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDAMG_OK             0
+#define DDAMG_NOT_CONVERGED  1
+#define DDAMG_EINVAL        -1   /* bad dimensions, blocks, levels, NaN input, bad pointer */
+#define DDAMG_ENOMEM        -2   /* device allocation failed                              */
+#define DDAMG_EDEVICE       -3   /* HIP runtime error                                      */
+#define DDAMG_EBREAKDOWN    -4   /* unrecoverable Krylov breakdown                         */
+#define DDAMG_ESTATE        -5   /* requested level / object not built                     */
+
+/* arithmetic of one operator application */
+#define DDAMG_FP64 0
+#define DDAMG_FP32 1
+
+/* solver precision mode */
+#define DDAMG_PLAIN_FP64 0   /* everything in FP64                                            */
+#define DDAMG_MIXED      1   /* FP64 outer FGMRES; FP32 preconditioner (SAP, R/P, coarse)       */
+
+/* fine-level smoother */
+#define DDAMG_SMOOTHER_SAP     0
+#define DDAMG_SMOOTHER_LEARNED 1
+
+typedef struct ddamg_ctx ddamg_ctx;
+
+typedef struct ddamg_params {
+  int    dims[4];            /* Lx, Ly, Lz, Lt                                                  */
+  double kappa;              /* m0 = 1/(2 kappa) - 4                                            */
+  int    n_levels;           /* 1 (SAP-preconditioned FGMRES), 2 or 3                           */
+  int    agg[2][4];          /* aggregate extents of each level transition                      */
+  int    n_tv[2];            /* test vectors N of each level transition (coarse dof = 2N)       */
+  int    sap_block[4];       /* SAP block extents; must equal agg[0] when n_levels > 1          */
+  int    sap_cycles;         /* red-black SAP cycles per smoother call                          */
+  int    sap_mr_iters;       /* MR iterations per block solve                                   */
+  int    setup_rounds;       /* smoothing rounds of the random setup vectors                    */
+  int    setup_coarse_iters; /* fixed GMRES length per coarse setup round                       */
+  double mu_setup;           /* twisted mass used while building the hierarchy                  */
+  double coarse_mu_factor;   /* delta mu on the coarsest level (Fig. 6 caption); 1 = none       */
+  double tol;                /* outer relative residual goal (1e-10)                            */
+  double r_m;                /* middle-level relative tolerance (7e-2)                          */
+  double r_b;                /* bottom relative tolerance (1e-1)                                */
+  int    outer_restart;      /* FGMRES restart length at the top level                          */
+  int    max_outer;          /* cap on outer iterations                                         */
+  int    middle_restart;     /* FGMRES restart on the middle level                              */
+  int    middle_maxit;       /* cap on middle-level iterations per call                         */
+  int    bottom_maxit;       /* cap on bottom iterations per call                               */
+  int    coarse_smooth_iters;/* MR steps of the middle-level post-smoother                      */
+  int    coarsest_block;     /* 1: block GMRES per shift group on the coarsest level            */
+  int    precision;          /* DDAMG_PLAIN_FP64 or DDAMG_MIXED                                 */
+  int    smoother;           /* DDAMG_SMOOTHER_SAP or DDAMG_SMOOTHER_LEARNED                    */
+  int    col_tile;           /* columns per tile of the internal layout (4, 8 or 16; 0 = 8)     */
+  uint64_t seed;             /* counter-based RNG seed of the setup vectors when none are given */
+  int    verbose;            /* 0 = silent                                                      */
+} ddamg_params;
+
+typedef struct ddamg_col_info {
+  int    outer_iters;        /* outer FGMRES iterations this column took                        */
+  int    converged;          /* 1 if the FP64 true residual met tol                             */
+  double true_rel_res;       /* ||b - D(mu) x|| / ||b|| in FP64 on the GPU                      */
+} ddamg_col_info;
+
+typedef struct ddamg_stats {
+  double setup_seconds;      /* wall time of the last hierarchy build                           */
+  double solve_seconds;      /* wall time of the last ddamg_solve                               */
+  int    outer_iters;        /* outer iterations of the last solve (max over columns)           */
+  double avg_middle_iters;   /* average iterations per middle-level solve (last solve)          */
+  double avg_bottom_iters;   /* average iterations per bottom-level solve (last solve)          */
+  long long n_middle_solves;
+  long long n_bottom_solves;
+  long long n_fine_ops;      /* fine-level operator applications of the last solve              */
+  long long n_sap_calls;
+  int    learned_fallbacks;  /* learned-smoother calls replaced by SAP                          */
+} ddamg_stats;
+
+/* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */
+void ddamg_default_params(ddamg_params* p);
+
+/* Build a context: copy the gauge field (host pointer if gauge_on_device == 0,
+ * else device), set up the internal layouts and, for n_levels > 1, run the
+ * adaptive setup (section 2: P and R from approximate low modes, recursively).
+ * tv_init: NULL, or n_levels-1 HOST pointers to the random start vectors of
+ * each level transition in canonical layout ([N][V][4][3] complex for level 0,
+ * [N][Vc][2N_prev] complex for level 1); with NULL the library draws them with
+ * its own counter-based generator from p->seed.  hip_stream: the stream all
+ * work of this context is issued on (NULL = default stream). */
+int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
+                const double* const* tv_init, void* hip_stream, ddamg_ctx** out);
+
+/* Replace the test vectors of level transition `level` (host, canonical
+ * layout as for tv_init) and rebuild P, R and every coarser operator from
+ * them (the test vectors are orthonormalised per aggregate and chirality). */
+int ddamg_set_test_vectors(ddamg_ctx* h, int level, const double* tv);
+
+/* Copy out the orthonormalised test vectors (P) of a level transition, host,
+ * canonical layout [N][V_l][d_l] complex with d_0 = 12. */
+int ddamg_get_test_vectors(ddamg_ctx* h, int level, double* tv);
+
+/* y_c = D_level(mu_c) x_c for n_col columns (device pointers, canonical
+ * layout of that level).  level 0 = fine operator (the paper's batched
+ * operator application, each link loaded once for a tile of columns);
+ * level > 0 = Galerkin coarse operator D_c(0) + i (dmu) mu_c gamma5_c.
+ * precision DDAMG_FP64 or DDAMG_FP32 (FP32 uses 2-row compressed links on the
+ * fine level); the canonical arrays are always FP64. */
+int ddamg_apply_op(ddamg_ctx* h, int level, int precision, const double* mu, int n_col,
+                   const double* x, double* y);
+
+/* x_c = M_SAP(mu_c) f_c: sap_cycles red-black Schwarz cycles from x = 0 with
+ * sap_mr_iters MR steps per block (section 2; fine level, device pointers). */
+int ddamg_apply_sap(ddamg_ctx* h, int precision, const double* mu, int n_col,
+                    const double* f, double* x);
+
+/* Restriction y = P^dag x from level `level` to level+1, and prolongation
+ * y = P x from level+1 to level (device pointers, canonical layouts). */
+int ddamg_restrict(ddamg_ctx* h, int level, int precision, int n_col, const double* x, double* y);
+int ddamg_prolong(ddamg_ctx* h, int level, int precision, int n_col, const double* x, double* y);
+
+/* Copy out the coarse blocks of level `level` (>= 1), host, canonical layout. */
+int ddamg_get_coarse_op(ddamg_ctx* h, int level, double* blocks);
+
+/* Lattice volume and dof per site of a level (dof = 12 on level 0, 2N above). */
+int ddamg_level_info(ddamg_ctx* h, int level, int* volume, int* dof, int dims[4]);
+
+/* Solve D(mu_k) x_{r,k} = b_r for all n_rhs x n_shift columns simultaneously
+ * (sections 3 and 4): FP64 flexible GMRES to relative residual p->tol,
+ * preconditioned by the multigrid cycle.  b: device [n_rhs][V][4][3] complex;
+ * x: device [n_rhs*n_shift][V][4][3] complex, read as initial guess when
+ * use_x0 != 0, else zeros; mu: host [n_shift]; info: host, n_rhs*n_shift
+ * entries or NULL.  Returns DDAMG_NOT_CONVERGED if any column misses tol. */
+int ddamg_solve(ddamg_ctx* h, const double* mu, int n_shift, const double* b, int n_rhs,
+                double* x, int use_x0, ddamg_col_info* info);
+
+/* Statistics of the last setup / solve. */
+int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);
+
+/* Time n_iter back-to-back launches of one kernel family on resident random
+ * internal vectors (n_col columns, given precision) with HIP events recorded
+ * on the context's stream; *sec = mean seconds per launch.  op: 0 = fine
+ * stencil (level 0), 1 = SAP smoother (level 0), 2 = coarse stencil of
+ * `level`, 3 = restriction from `level`, 4 = prolongation to `level`. */
+int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int n_iter, double* sec);
+
+void ddamg_destroy(ddamg_ctx* h);
+const char* ddamg_strerror(int status);
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* ddamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDAMG_H */

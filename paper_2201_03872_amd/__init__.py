@@ -1,0 +1,285 @@
+"""Python binding of libddamg, the gfx950 multi-rhs x multi-shift twisted-mass
+DD-alpha-AMG library (C ABI in include/ddamg.h).
+
+This module only marshals arguments: every step of the computation runs in
+the library's HIP kernels.  Vectors are torch complex128 tensors on the GPU
+(canonical layouts of the C ABI); PyTorch provides device memory and the
+stream, nothing else.  If the compiled library is missing the import of the
+native code fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libddamg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ddamg.h")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN, ESTATE = 0, 1, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+PLAIN_FP64, MIXED = 0, 1
+SMOOTHER_SAP, SMOOTHER_LEARNED = 0, 1
+
+
+class DDAMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ddamg error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int * 4),
+        ("kappa", ctypes.c_double),
+        ("n_levels", ctypes.c_int),
+        ("agg", (ctypes.c_int * 4) * 2),
+        ("n_tv", ctypes.c_int * 2),
+        ("sap_block", ctypes.c_int * 4),
+        ("sap_cycles", ctypes.c_int),
+        ("sap_mr_iters", ctypes.c_int),
+        ("setup_rounds", ctypes.c_int),
+        ("setup_coarse_iters", ctypes.c_int),
+        ("mu_setup", ctypes.c_double),
+        ("coarse_mu_factor", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("r_m", ctypes.c_double),
+        ("r_b", ctypes.c_double),
+        ("outer_restart", ctypes.c_int),
+        ("max_outer", ctypes.c_int),
+        ("middle_restart", ctypes.c_int),
+        ("middle_maxit", ctypes.c_int),
+        ("bottom_maxit", ctypes.c_int),
+        ("coarse_smooth_iters", ctypes.c_int),
+        ("coarsest_block", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("smoother", ctypes.c_int),
+        ("col_tile", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("verbose", ctypes.c_int),
+    ]
+
+
+class ColInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("converged", ctypes.c_int), ("true_rel_res", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("setup_seconds", ctypes.c_double), ("solve_seconds", ctypes.c_double), ("outer_iters", ctypes.c_int),
+        ("avg_middle_iters", ctypes.c_double), ("avg_bottom_iters", ctypes.c_double),
+        ("n_middle_solves", ctypes.c_longlong), ("n_bottom_solves", ctypes.c_longlong),
+        ("n_fine_ops", ctypes.c_longlong), ("n_sap_calls", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def header_symbols() -> list:
+    """Names of every function declared in include/ddamg.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddamg_\w+)\s*\(", txt)))
+
+
+def load():
+    """Load the compiled library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2201_03872_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp, ip = ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int)
+    sig = {
+        "ddamg_default_params": (None, [P(Params)]),
+        "ddamg_setup": (ctypes.c_int, [P(Params), vp, ctypes.c_int, vp, vp, P(vp)]),
+        "ddamg_set_test_vectors": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "ddamg_get_test_vectors": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "ddamg_apply_op": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
+        "ddamg_apply_sap": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
+        "ddamg_restrict": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
+        "ddamg_prolong": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
+        "ddamg_get_coarse_op": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "ddamg_level_info": (ctypes.c_int, [vp, ctypes.c_int, ip, ip, ip]),
+        "ddamg_solve": (ctypes.c_int, [vp, dp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, P(ColInfo)]),
+        "ddamg_get_stats": (ctypes.c_int, [vp, P(Stats)]),
+        "ddamg_time_op": (ctypes.c_int, [vp] + [ctypes.c_int] * 5 + [dp]),
+        "ddamg_destroy": (None, [vp]),
+        "ddamg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "ddamg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, allow=(OK,)):
+    if code not in allow:
+        lib = load()
+        raise DDAMGError(code, f"{lib.ddamg_strerror(code).decode()}: {lib.ddamg_last_error().decode()}")
+    return code
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().ddamg_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("dims", "n_tv", "sap_block"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = int(x)
+        elif k == "agg":
+            for l, a in enumerate(v):
+                for i, x in enumerate(a):
+                    p.agg[l][i] = int(x)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _dptr(t) -> int:
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise TypeError("expected a contiguous complex128 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mu(mu) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Context:
+    """One solver context: gauge field, internal layouts and MG hierarchy."""
+
+    def __init__(self, params: Params, gauge, tv_init: Optional[Sequence[np.ndarray]] = None):
+        import torch
+        lib = load()
+        self.params = params
+        g = np.ascontiguousarray(np.asarray(gauge, dtype=np.complex128))
+        self._tv = None
+        tvp = None
+        if tv_init is not None:
+            self._tv = [np.ascontiguousarray(np.asarray(t, dtype=np.complex128)) for t in tv_init]
+            arr = (ctypes.c_void_p * len(self._tv))(*[t.ctypes.data for t in self._tv])
+            self._tv_arr = arr
+            tvp = ctypes.cast(arr, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        _check(lib.ddamg_setup(ctypes.byref(params), g.ctypes.data, 0, tvp, _stream_handle(), ctypes.byref(h)))
+        self.h = h
+        self.device = torch.device("cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ddamg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        V, d = ctypes.c_int(), ctypes.c_int()
+        dims = (ctypes.c_int * 4)()
+        _check(load().ddamg_level_info(self.h, level, ctypes.byref(V), ctypes.byref(d), dims))
+        return V.value, d.value, tuple(dims)
+
+    def _vec(self, level, ncol):
+        import torch
+        V, d, _ = self.level_info(level)
+        shape = (ncol, V, 4, 3) if level == 0 else (ncol, V, d)
+        return torch.empty(shape, dtype=torch.complex128, device=self.device)
+
+    def apply_op(self, level, precision, mu, x):
+        m, mp = _mu(mu)
+        y = self._vec(level, x.shape[0])
+        _check(load().ddamg_apply_op(self.h, level, precision, mp, x.shape[0], _dptr(x), _dptr(y)))
+        return y
+
+    def apply_sap(self, precision, mu, f):
+        m, mp = _mu(mu)
+        x = self._vec(0, f.shape[0])
+        _check(load().ddamg_apply_sap(self.h, precision, mp, f.shape[0], _dptr(f), _dptr(x)))
+        return x
+
+    def restrict(self, level, precision, x):
+        y = self._vec(level + 1, x.shape[0])
+        _check(load().ddamg_restrict(self.h, level, precision, x.shape[0], _dptr(x), _dptr(y)))
+        return y
+
+    def prolong(self, level, precision, x):
+        y = self._vec(level, x.shape[0])
+        _check(load().ddamg_prolong(self.h, level, precision, x.shape[0], _dptr(x), _dptr(y)))
+        return y
+
+    def coarse_op(self, level) -> np.ndarray:
+        V, d, _ = self.level_info(level)
+        out = np.empty((V, 9, d, d), dtype=np.complex128)
+        _check(load().ddamg_get_coarse_op(self.h, level, out.ctypes.data))
+        return out
+
+    def test_vectors(self, level) -> np.ndarray:
+        V, d, _ = self.level_info(level)
+        N = self.params.n_tv[level]
+        out = np.empty((N, V, d), dtype=np.complex128)
+        _check(load().ddamg_get_test_vectors(self.h, level, out.ctypes.data))
+        return out
+
+    def set_test_vectors(self, level, tv):
+        a = np.ascontiguousarray(np.asarray(tv, dtype=np.complex128))
+        _check(load().ddamg_set_test_vectors(self.h, level, a.ctypes.data))
+
+    def solve(self, mu, b, x0=None):
+        """b: [n_rhs][V][4][3] complex128 CUDA tensor; mu: n_shift shifts.
+        Returns (x [n_rhs*n_shift][V][4][3], info list, status)."""
+        import torch
+        m, mp = _mu(mu)
+        n_rhs = b.shape[0]
+        ncol = n_rhs * len(m)
+        x = x0.clone() if x0 is not None else torch.zeros((ncol,) + tuple(b.shape[1:]), dtype=torch.complex128,
+                                                          device=self.device)
+        info = (ColInfo * ncol)()
+        st = _check(load().ddamg_solve(self.h, mp, len(m), _dptr(b), n_rhs, _dptr(x), int(x0 is not None), info),
+                    allow=(OK, NOT_CONVERGED))
+        return x, [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res)
+                   for i in info], st
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().ddamg_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def time_op(self, op, level, precision, n_col, n_iter) -> float:
+        sec = ctypes.c_double()
+        _check(load().ddamg_time_op(self.h, op, level, precision, n_col, n_iter, ctypes.byref(sec)))
+        return sec.value
+
+
+def params_for_workload(w, **overrides) -> Params:
+    """ddamg_params of a synthetic workload description (see synthetic.Workload)."""
+    kw = dict(dims=w.dims, kappa=w.kappa, n_levels=w.n_levels, sap_block=w.sap_block,
+              mu_setup=float(min(w.mus)))
+    if w.n_levels > 1:
+        agg = [list(a) for a in w.agg] + [[1, 1, 1, 1]] * (2 - len(w.agg))
+        n_tv = list(w.n_tv) + [8] * (2 - len(w.n_tv))
+        kw.update(agg=agg, n_tv=n_tv)
+    kw.update(overrides)
+    return default_params(**kw)

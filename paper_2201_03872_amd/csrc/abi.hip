@@ -1,0 +1,456 @@
+// extern "C" entry points of libddamg (declared in include/ddamg.h).  No
+// exception crosses this boundary: every entry point returns a status code
+// and keeps a thread-local message for ddamg_last_error().
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "common.h"
+
+namespace ddamg {
+void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, int dof, bool fine);
+void build_sap_lists(ddamg_ctx* c);
+void upload_gauge(ddamg_ctx* c, const double* gauge, int on_device);
+void build_hierarchy(ddamg_ctx* c, const double* const* tv_init);
+void rebuild_from_test_vectors(ddamg_ctx* c, int l, const double* tv_host);
+int solve_internal(ddamg_ctx* c, const double* d_mu, const MV& b, const MV& x, bool x_zero, std::vector<int>& iters);
+void free_work(ddamg_ctx* c);
+void random_fill(ddamg_ctx* c, int level, const MV& X, int ncol, uint64_t seed);
+void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2);
+}  // namespace ddamg
+
+using namespace ddamg;
+
+static thread_local std::string g_last_error;
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DDAMG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DDAMG_EDEVICE;
+  }
+}
+
+extern "C" {
+
+const char* ddamg_last_error(void) { return g_last_error.c_str(); }
+
+const char* ddamg_strerror(int s) {
+  switch (s) {
+    case DDAMG_OK: return "ok";
+    case DDAMG_NOT_CONVERGED: return "not converged: solution written, some columns above tolerance";
+    case DDAMG_EINVAL: return "invalid argument";
+    case DDAMG_ENOMEM: return "out of device memory";
+    case DDAMG_EDEVICE: return "HIP runtime error";
+    case DDAMG_EBREAKDOWN: return "unrecoverable Krylov breakdown";
+    case DDAMG_ESTATE: return "object not built";
+    default: return "unknown status";
+  }
+}
+
+void ddamg_default_params(ddamg_params* p) {
+  std::memset(p, 0, sizeof(*p));
+  for (int m = 0; m < 4; ++m) {
+    p->dims[m] = 4;
+    p->agg[0][m] = 2;
+    p->agg[1][m] = 2;
+    p->sap_block[m] = 2;
+  }
+  p->kappa = 0.14;
+  p->n_levels = 2;
+  p->n_tv[0] = 8;
+  p->n_tv[1] = 8;
+  p->sap_cycles = 4;
+  p->sap_mr_iters = 4;
+  p->setup_rounds = 3;
+  p->setup_coarse_iters = 10;
+  p->mu_setup = 0.0;
+  p->coarse_mu_factor = 1.0;
+  p->tol = 1e-10;
+  p->r_m = 7e-2;
+  p->r_b = 1e-1;
+  p->outer_restart = 10;
+  p->max_outer = 500;
+  p->middle_restart = 20;
+  p->middle_maxit = 50;
+  p->bottom_maxit = 50;
+  p->coarse_smooth_iters = 2;
+  p->coarsest_block = 0;
+  p->precision = DDAMG_PLAIN_FP64;
+  p->smoother = DDAMG_SMOOTHER_SAP;
+  p->col_tile = 8;
+  p->seed = 12345;
+  p->verbose = 0;
+}
+
+static void validate(const ddamg_params* p) {
+  DD_CHECK(p, DDAMG_EINVAL, "null params");
+  DD_CHECK(p->n_levels >= 1 && p->n_levels <= 3, DDAMG_EINVAL, "n_levels must be 1, 2 or 3");
+  DD_CHECK(p->kappa > 0, DDAMG_EINVAL, "kappa must be positive");
+  DD_CHECK(p->col_tile == 0 || p->col_tile == 8, DDAMG_EINVAL, "col_tile must be 8");
+  int dims[4];
+  for (int m = 0; m < 4; ++m) {
+    DD_CHECK(p->dims[m] >= 1, DDAMG_EINVAL, "lattice extents must be >= 1");
+    DD_CHECK(p->sap_block[m] >= 1 && p->dims[m] % p->sap_block[m] == 0, DDAMG_EINVAL,
+             "SAP block extents must divide the lattice");
+    dims[m] = p->dims[m];
+  }
+  const int bs = p->sap_block[0] * p->sap_block[1] * p->sap_block[2] * p->sap_block[3];
+  DD_CHECK(bs == 16 || bs == 256, DDAMG_EINVAL, "SAP blocks must have 16 or 256 sites");
+  for (int l = 0; l + 1 < p->n_levels; ++l) {
+    DD_CHECK(p->n_tv[l] >= 2 && p->n_tv[l] % 2 == 0 && p->n_tv[l] <= 64, DDAMG_EINVAL,
+             "test vector counts must be even and in [2, 64]");
+    for (int m = 0; m < 4; ++m) {
+      DD_CHECK(p->agg[l][m] >= 1 && dims[m] % p->agg[l][m] == 0, DDAMG_EINVAL,
+               "aggregate extents must divide the lattice");
+      if (l == 0)
+        DD_CHECK(p->agg[0][m] == p->sap_block[m], DDAMG_EINVAL, "first-level aggregates must equal the SAP blocks");
+      dims[m] /= p->agg[l][m];
+    }
+  }
+  DD_CHECK(p->sap_cycles >= 1 && p->sap_mr_iters >= 1, DDAMG_EINVAL, "SAP cycle counts must be >= 1");
+  DD_CHECK(p->outer_restart >= 1 && p->outer_restart <= 63, DDAMG_EINVAL, "outer_restart in [1, 63]");
+  DD_CHECK(p->middle_restart >= 1 && p->middle_restart <= 63, DDAMG_EINVAL, "middle_restart in [1, 63]");
+  DD_CHECK(p->bottom_maxit >= 1, DDAMG_EINVAL, "bottom_maxit >= 1");
+  DD_CHECK(p->setup_coarse_iters >= 1 && p->setup_coarse_iters <= 63, DDAMG_EINVAL, "setup_coarse_iters in [1, 63]");
+  DD_CHECK(p->tol > 0 && p->r_m > 0 && p->r_b > 0, DDAMG_EINVAL, "tolerances must be positive");
+  DD_CHECK(p->precision == DDAMG_PLAIN_FP64 || p->precision == DDAMG_MIXED, DDAMG_EINVAL, "precision mode");
+  DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP, DDAMG_EINVAL, "smoother: only SAP is available");
+}
+
+int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
+                void* hip_stream, ddamg_ctx** out) {
+  return guarded([&]() -> int {
+    DD_CHECK(out && gauge, DDAMG_EINVAL, "null pointer");
+    *out = nullptr;
+    validate(p);
+    auto t0 = std::chrono::steady_clock::now();
+    ddamg_ctx* c = new ddamg_ctx();
+    try {
+      c->p = *p;
+      if (c->p.col_tile == 0) c->p.col_tile = 8;
+      c->T = 8;
+      c->stream = (hipStream_t)hip_stream;
+      c->nlev = p->n_levels;
+      c->m0 = 1.0 / (2.0 * p->kappa) - 4.0;
+      c->diag = 4.0 + c->m0;
+      int dims[4] = {p->dims[0], p->dims[1], p->dims[2], p->dims[3]};
+      build_geometry(c, 0, dims, p->sap_block, 12, true);
+      for (int l = 1; l < c->nlev; ++l) {
+        int grp[4] = {1, 1, 1, 1};
+        for (int m = 0; m < 4; ++m) {
+          dims[m] /= p->agg[l - 1][m];
+          if (l + 1 < c->nlev) grp[m] = p->agg[l][m];
+        }
+        build_geometry(c, l, dims, grp, 2 * p->n_tv[l - 1], false);
+        c->tr[l - 1].N = p->n_tv[l - 1];
+      }
+      build_sap_lists(c);
+      upload_gauge(c, gauge, gauge_on_device);
+      build_hierarchy(c, tv_init);
+      DD_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      c->pool.clear();
+      delete c;
+      throw;
+    }
+    c->st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = c;
+    return DDAMG_OK;
+  });
+}
+
+void ddamg_destroy(ddamg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_work(c);
+  c->pool.clear();
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  delete c;
+}
+
+int ddamg_level_info(ddamg_ctx* c, int level, int* volume, int* dof, int dims[4]) {
+  return guarded([&]() -> int {
+    DD_CHECK(c, DDAMG_EINVAL, "null context");
+    DD_CHECK(level >= 0 && level < c->nlev, DDAMG_ESTATE, "level not built");
+    const LevelGeom& g = c->geom[level];
+    if (volume) *volume = g.V;
+    if (dof) *dof = g.dof;
+    if (dims)
+      for (int m = 0; m < 4; ++m) dims[m] = g.dims[m];
+    return DDAMG_OK;
+  });
+}
+
+static double* upload_mu(ddamg_ctx* c, const double* mu, int n_col, int ncolp) {
+  std::vector<double> h(ncolp, 0.0);
+  for (int i = 0; i < n_col; ++i) {
+    DD_CHECK(std::isfinite(mu[i]), DDAMG_EINVAL, "mu contains NaN/Inf");
+    h[i] = mu[i];
+  }
+  double* d = (double*)c->pool.alloc(h.size() * sizeof(double));
+  DD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  DD_HIP(hipStreamSynchronize(c->stream));
+  return d;
+}
+
+int ddamg_apply_op(ddamg_ctx* c, int level, int precision, const double* mu, int n_col, const double* x, double* y) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mu && x && y && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    DD_CHECK(level >= 0 && level < c->nlev, DDAMG_ESTATE, "level not built");
+    DD_CHECK(precision == DDAMG_FP64 || precision == DDAMG_FP32, DDAMG_EINVAL, "precision");
+    const int prec = precision == DDAMG_FP64 ? P64 : P32;
+    MV a = mv_alloc(c, level, prec, n_col), b = mv_alloc(c, level, prec, n_col);
+    double* d_mu = upload_mu(c, mu, n_col, a.ncol());
+    to_internal(c, level, x, n_col, a);
+    operator_apply(c, level, a, b, d_mu);
+    from_internal(c, level, b, n_col, y);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    mv_free(c, a);
+    mv_free(c, b);
+    c->pool.release(d_mu);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_apply_sap(ddamg_ctx* c, int precision, const double* mu, int n_col, const double* f, double* x) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mu && f && x && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    const int prec = precision == DDAMG_FP64 ? P64 : P32;
+    MV a = mv_alloc(c, 0, prec, n_col), b = mv_alloc(c, 0, prec, n_col);
+    double* d_mu = upload_mu(c, mu, n_col, a.ncol());
+    to_internal(c, 0, f, n_col, a);
+    sap_apply(c, a, b, d_mu, b);
+    from_internal(c, 0, b, n_col, x);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    mv_free(c, a);
+    mv_free(c, b);
+    c->pool.release(d_mu);
+    return DDAMG_OK;
+  });
+}
+
+static int transfer(ddamg_ctx* c, int level, int precision, int n_col, const double* x, double* y, bool down) {
+  DD_CHECK(c && x && y && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+  DD_CHECK(level >= 0 && level + 1 < c->nlev, DDAMG_ESTATE, "no such level transition");
+  const int prec = precision == DDAMG_FP64 ? P64 : P32;
+  const int from = down ? level : level + 1, to = down ? level + 1 : level;
+  MV a = mv_alloc(c, from, prec, n_col), b = mv_alloc(c, to, prec, n_col);
+  to_internal(c, from, x, n_col, a);
+  if (down) restrict_mv(c, level, a, b);
+  else prolong_mv(c, level, a, b, 0);
+  from_internal(c, to, b, n_col, y);
+  DD_HIP(hipStreamSynchronize(c->stream));
+  mv_free(c, a);
+  mv_free(c, b);
+  return DDAMG_OK;
+}
+
+int ddamg_restrict(ddamg_ctx* c, int level, int precision, int n_col, const double* x, double* y) {
+  return guarded([&]() -> int { return transfer(c, level, precision, n_col, x, y, true); });
+}
+int ddamg_prolong(ddamg_ctx* c, int level, int precision, int n_col, const double* x, double* y) {
+  return guarded([&]() -> int { return transfer(c, level, precision, n_col, x, y, false); });
+}
+
+int ddamg_get_coarse_op(ddamg_ctx* c, int level, double* blocks) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && blocks, DDAMG_EINVAL, "null pointer");
+    DD_CHECK(level >= 1 && level < c->nlev, DDAMG_ESTATE, "no coarse operator on this level");
+    const LevelGeom& g = c->geom[level];
+    const int d = g.dof;
+    std::vector<double> h((size_t)g.V * 9 * d * d * 2);
+    DD_HIP(hipMemcpy(h.data(), c->coarse[level].d_blk64, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int a = 0; a < g.V; ++a) {
+      const int ca = g.int2can[a];
+      for (int slot = 0; slot < 9; ++slot)
+        for (int col = 0; col < d; ++col)
+          for (int row = 0; row < d; ++row) {
+            const double* s = &h[((((size_t)a * 9 + slot) * d + col) * d + row) * 2];
+            double* t = blocks + ((((size_t)ca * 9 + slot) * d + row) * d + col) * 2;
+            t[0] = s[0];
+            t[1] = s[1];
+          }
+    }
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_get_test_vectors(ddamg_ctx* c, int level, double* tv) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && tv, DDAMG_EINVAL, "null pointer");
+    DD_CHECK(level >= 0 && level + 1 < c->nlev, DDAMG_ESTATE, "no such level transition");
+    const LevelGeom& g = c->geom[level];
+    const int N = c->tr[level].N;
+    std::vector<double> h((size_t)g.V * g.dof * N * 2);
+    DD_HIP(hipMemcpy(h.data(), c->tr[level].d_P64, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int s = 0; s < g.V; ++s) {
+      const int cs = g.int2can[s];
+      for (int k = 0; k < g.dof; ++k)
+        for (int j = 0; j < N; ++j) {
+          const double* q = &h[(((size_t)s * g.dof + k) * N + j) * 2];
+          double* t = tv + (((size_t)j * g.V + cs) * g.dof + k) * 2;
+          t[0] = q[0];
+          t[1] = q[1];
+        }
+    }
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_set_test_vectors(ddamg_ctx* c, int level, const double* tv) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && tv, DDAMG_EINVAL, "null pointer");
+    DD_CHECK(level >= 0 && level + 1 < c->nlev, DDAMG_ESTATE, "no such level transition");
+    rebuild_from_test_vectors(c, level, tv);
+    return DDAMG_OK;
+  });
+}
+
+// Expand b ([n_rhs] canonical) to columns col = r*n_shift + k in the internal layout.
+static void load_rhs(ddamg_ctx* c, const double* b, int n_rhs, int n_shift, const MV& B) {
+  const LevelGeom& g = c->geom[0];
+  const size_t colbytes = (size_t)g.V * 12 * 2 * sizeof(double);
+  const int ncol = n_rhs * n_shift;
+  double* tmp = (double*)c->pool.alloc(colbytes * ncol);
+  for (int r = 0; r < n_rhs; ++r)
+    for (int k = 0; k < n_shift; ++k)
+      DD_HIP(hipMemcpyAsync((char*)tmp + colbytes * (r * n_shift + k), (const char*)b + colbytes * r, colbytes,
+                            hipMemcpyDeviceToDevice, c->stream));
+  to_internal(c, 0, tmp, ncol, B);
+  DD_HIP(hipStreamSynchronize(c->stream));
+  c->pool.release(tmp);
+}
+
+int ddamg_solve(ddamg_ctx* c, const double* mu, int n_shift, const double* b, int n_rhs, double* x, int use_x0,
+                ddamg_col_info* info) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mu && b && x && n_shift >= 1 && n_rhs >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    auto t0 = std::chrono::steady_clock::now();
+    c->st.middle_calls = c->st.middle_iters = c->st.bottom_calls = c->st.bottom_iters = 0;
+    c->st.fine_ops = c->st.sap_calls = 0;
+    const int ncol = n_rhs * n_shift;
+    std::vector<double> hmu(ncol);
+    for (int r = 0; r < n_rhs; ++r)
+      for (int k = 0; k < n_shift; ++k) hmu[r * n_shift + k] = mu[k];
+    MV B = mv_alloc(c, 0, P64, ncol), X = mv_alloc(c, 0, P64, ncol);
+    double* d_mu = upload_mu(c, hmu.data(), ncol, B.ncol());
+    load_rhs(c, b, n_rhs, n_shift, B);
+    // NaN guard on the right-hand sides
+    double* d_n2 = (double*)c->pool.alloc(B.ncol() * sizeof(double));
+    mv_norm2(c, B, d_n2);
+    std::vector<double> bn(B.ncol());
+    copy_to_host(c, d_n2, bn.data(), bn.size() * sizeof(double));
+    for (int i = 0; i < ncol; ++i) DD_CHECK(std::isfinite(bn[i]), DDAMG_EINVAL, "right-hand side contains NaN/Inf");
+    if (use_x0) to_internal(c, 0, x, ncol, X);
+    std::vector<int> iters;
+    solve_internal(c, d_mu, B, X, !use_x0, iters);
+    // final FP64 true residual
+    MV R = mv_alloc(c, 0, P64, ncol);
+    fine_residual(c, B, X, R, d_mu);
+    mv_norm2(c, R, d_n2);
+    std::vector<double> rn(B.ncol());
+    copy_to_host(c, d_n2, rn.data(), rn.size() * sizeof(double));
+    from_internal(c, 0, X, ncol, x);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    int status = DDAMG_OK;
+    for (int i = 0; i < ncol; ++i) {
+      const double rel = bn[i] > 0 ? std::sqrt(rn[i] / bn[i]) : 0.0;
+      const int conv = rel <= c->p.tol;
+      if (!conv) status = DDAMG_NOT_CONVERGED;
+      if (info) {
+        info[i].outer_iters = i < (int)iters.size() ? iters[i] : 0;
+        info[i].converged = conv;
+        info[i].true_rel_res = rel;
+      }
+    }
+    mv_free(c, B);
+    mv_free(c, X);
+    mv_free(c, R);
+    c->pool.release(d_mu);
+    c->pool.release(d_n2);
+    c->st.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+  });
+}
+
+int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && s, DDAMG_EINVAL, "null pointer");
+    std::memset(s, 0, sizeof(*s));
+    s->setup_seconds = c->st.setup_seconds;
+    s->solve_seconds = c->st.solve_seconds;
+    s->outer_iters = c->st.outer_iters;
+    s->n_middle_solves = c->st.middle_calls;
+    s->n_bottom_solves = c->st.bottom_calls;
+    s->avg_middle_iters = c->st.middle_calls ? (double)c->st.middle_iters / c->st.middle_calls : 0.0;
+    s->avg_bottom_iters = c->st.bottom_calls ? (double)c->st.bottom_iters / c->st.bottom_calls : 0.0;
+    s->n_fine_ops = c->st.fine_ops;
+    s->n_sap_calls = c->st.sap_calls;
+    s->learned_fallbacks = c->st.learned_fallbacks;
+    return DDAMG_OK;
+  });
+}
+
+// Time `n_iter` back-to-back launches of one operator on resident internal
+// vectors with HIP events on the context's stream (the stream the kernels are
+// launched on).  op: 0 = fine stencil, 1 = SAP smoother, 2 = coarse stencil of
+// `level`, 3 = restriction from `level`, 4 = prolongation to `level`.
+// Returns the mean seconds per launch in *sec.
+int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int n_iter, double* sec) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && sec && n_col >= 1 && n_iter >= 1, DDAMG_EINVAL, "bad arguments");
+    DD_CHECK(level >= 0 && level < c->nlev, DDAMG_ESTATE, "level not built");
+    const int prec = precision == DDAMG_FP64 ? P64 : P32;
+    const int lin = (op == 4) ? level + 1 : level;
+    const int lout = (op == 3) ? level + 1 : level;
+    DD_CHECK(!(op == 3 || op == 4) || level + 1 < c->nlev, DDAMG_ESTATE, "no such transition");
+    DD_CHECK(!(op == 2) || level >= 1, DDAMG_EINVAL, "coarse stencil needs level >= 1");
+    MV a64 = mv_alloc(c, lin, P64, n_col);
+    random_fill(c, lin, a64, a64.ncol(), 99);
+    MV a = (prec == P64) ? a64 : mv_like(c, a64, P32);
+    if (prec != P64) mv_copy(c, a64, a);
+    MV b = mv_alloc(c, lout, prec, n_col);
+    std::vector<double> hm(a.ncol(), 0.01);
+    double* d_mu = upload_mu(c, hm.data(), a.ncol(), a.ncol());
+    auto run = [&]() {
+      switch (op) {
+        case 0: fine_dslash(c, a, b, d_mu); break;
+        case 1: sap_apply(c, a, b, d_mu, b); break;
+        case 2: coarse_apply(c, level, a, b, d_mu); break;
+        case 3: restrict_mv(c, level, a, b); break;
+        default: prolong_mv(c, level, a, b, 0); break;
+      }
+    };
+    run();
+    DD_HIP(hipStreamSynchronize(c->stream));
+    hipEvent_t e0, e1;
+    DD_HIP(hipEventCreate(&e0));
+    DD_HIP(hipEventCreate(&e1));
+    DD_HIP(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < n_iter; ++i) run();
+    DD_HIP(hipEventRecord(e1, c->stream));
+    DD_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *sec = (double)ms * 1e-3 / n_iter;
+    if (prec != P64) mv_free(c, a);
+    mv_free(c, a64);
+    mv_free(c, b);
+    c->pool.release(d_mu);
+    return DDAMG_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,519 @@
+// Multivector management, layout conversion and per-column BLAS on the
+// column-tiled layout [tile][m][T][RW] (m runs over chunk x site).
+//
+// Inner products are reduced in a fixed order (per-thread partials, wavefront
+// shuffles, one partial per workgroup, a second pass over the partials), with
+// FP64 accumulation for both precisions: results are bitwise reproducible and
+// no atomics are used.  This is the single-GPU analogue of the paper's global
+// reductions (section 4: they dominate block-solver overhead); every
+// orthogonalisation step issues one fused multi-dot instead of one reduction
+// per inner product.
+#include "common.h"
+#include "device.h"
+
+namespace ddamg {
+
+constexpr int TTB = 8;
+constexpr int MAXK = 64;
+
+// ------------------------------------------------------------- pool ---
+void* DevPool::alloc(size_t bytes) {
+  void* p = nullptr;
+  DD_HIP(hipMalloc(&p, bytes ? bytes : 16));
+  blocks.push_back(p);
+  return p;
+}
+void DevPool::release(void* p) {
+  for (size_t i = 0; i < blocks.size(); ++i)
+    if (blocks[i] == p) {
+      (void)hipFree(p);
+      blocks.erase(blocks.begin() + i);
+      return;
+    }
+}
+void DevPool::clear() {
+  for (void* p : blocks) (void)hipFree(p);
+  blocks.clear();
+}
+
+MV mv_alloc(ddamg_ctx* c, int level, int prec, int ncol_min) {
+  MV a;
+  a.prec = prec;
+  a.T = c->T;
+  a.ntiles = (ncol_min + a.T - 1) / a.T;
+  if (a.ntiles < 1) a.ntiles = 1;
+  a.dof = c->geom[level].dof;
+  a.nsites = c->geom[level].V;
+  a.nchunk = 2 * a.dof / reals_per_chunk(prec);
+  a.p = c->pool.alloc(a.bytes());
+  a.owned = true;
+  mv_zero(c, a);
+  return a;
+}
+
+MV mv_like(ddamg_ctx* c, const MV& a, int prec) {
+  MV b = a;
+  b.prec = prec;
+  b.nchunk = 2 * a.dof / reals_per_chunk(prec);
+  b.p = c->pool.alloc(b.bytes());
+  b.owned = true;
+  mv_zero(c, b);
+  return b;
+}
+
+void mv_free(ddamg_ctx* c, MV& a) {
+  if (a.owned && a.p) c->pool.release(a.p);
+  a.p = nullptr;
+}
+
+// ----------------------------------------------------------- kernels ---
+__global__ void k_fill(uint4* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = uint4{0, 0, 0, 0};
+}
+
+static inline dim3 grid_for(size_t n) {
+  size_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+void mv_zero(ddamg_ctx* c, const MV& a) {
+  const size_t n = a.bytes() / 16;
+  hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, c->stream, (uint4*)a.p, n);
+  DD_HIP(hipGetLastError());
+}
+
+// canonical [col][site][dof] complex  ->  tiled internal (either precision)
+template <typename R>
+__global__ void k_to_internal(const double* __restrict__ src, R* __restrict__ dst, const int* __restrict__ int2can,
+                              int n_col, int ncolp, int V, int dof, int T) {
+  constexpr int RW = Chunk<R>::RW, CPC = RW / 2;
+  const int nchunk = 2 * dof / RW;
+  const size_t total = (size_t)ncolp * V * dof;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    // i = ((col * V) + s) * dof + k  with s the internal site
+    const int k = (int)(i % dof);
+    const size_t cs = i / dof;
+    const int s = (int)(cs % V);
+    const int col = (int)(cs / V);
+    double re = 0, im = 0;
+    if (col < n_col) {
+      const double* q = src + (((size_t)col * V + int2can[s]) * dof + k) * 2;
+      re = q[0]; im = q[1];
+    }
+    const int tile = col / T, t = col % T;
+    R* d = dst + (size_t)tile * nchunk * V * T * RW + (((size_t)(k / CPC) * V + s) * T + t) * RW + (k % CPC) * 2;
+    d[0] = (R)re; d[1] = (R)im;
+  }
+}
+
+template <typename R>
+__global__ void k_from_internal(const R* __restrict__ src, double* __restrict__ dst, const int* __restrict__ int2can,
+                                int n_col, int V, int dof, int T) {
+  constexpr int RW = Chunk<R>::RW, CPC = RW / 2;
+  const int nchunk = 2 * dof / RW;
+  const size_t total = (size_t)n_col * V * dof;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % dof);
+    const size_t cs = i / dof;
+    const int s = (int)(cs % V);
+    const int col = (int)(cs / V);
+    const int tile = col / T, t = col % T;
+    const R* q = src + (size_t)tile * nchunk * V * T * RW + (((size_t)(k / CPC) * V + s) * T + t) * RW + (k % CPC) * 2;
+    double* d = dst + (((size_t)col * V + int2can[s]) * dof + k) * 2;
+    d[0] = (double)q[0]; d[1] = (double)q[1];
+  }
+}
+
+void to_internal(ddamg_ctx* c, int level, const double* canon, int n_col, const MV& out) {
+  const LevelGeom& g = c->geom[level];
+  DD_CHECK(out.nsites == g.V && out.dof == g.dof && out.ncol() >= n_col, DDAMG_EINVAL, "to_internal: shape");
+  const size_t n = (size_t)out.ncol() * g.V * g.dof;
+  if (out.prec == P64)
+    hipLaunchKernelGGL(k_to_internal<double>, grid_for(n), dim3(256), 0, c->stream, canon, out.as<double>(),
+                       g.d_int2can, n_col, out.ncol(), g.V, g.dof, out.T);
+  else
+    hipLaunchKernelGGL(k_to_internal<float>, grid_for(n), dim3(256), 0, c->stream, canon, out.as<float>(),
+                       g.d_int2can, n_col, out.ncol(), g.V, g.dof, out.T);
+  DD_HIP(hipGetLastError());
+}
+
+void from_internal(ddamg_ctx* c, int level, const MV& in, int n_col, double* canon) {
+  const LevelGeom& g = c->geom[level];
+  DD_CHECK(in.nsites == g.V && in.dof == g.dof && in.ncol() >= n_col, DDAMG_EINVAL, "from_internal: shape");
+  const size_t n = (size_t)n_col * g.V * g.dof;
+  if (in.prec == P64)
+    hipLaunchKernelGGL(k_from_internal<double>, grid_for(n), dim3(256), 0, c->stream, in.as<double>(), canon,
+                       g.d_int2can, n_col, g.V, g.dof, in.T);
+  else
+    hipLaunchKernelGGL(k_from_internal<float>, grid_for(n), dim3(256), 0, c->stream, in.as<float>(), canon,
+                       g.d_int2can, n_col, g.V, g.dof, in.T);
+  DD_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------- elementwise ops ---
+// Every lane handles one real pair (complex) of one column; column index of
+// real i in a tile: t = (i / RW) % T.
+template <typename RS, typename RD>
+__global__ void k_copy(const RS* __restrict__ a, RD* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (RD)a[i];
+}
+
+void mv_copy(ddamg_ctx* c, const MV& s, const MV& d) {
+  DD_CHECK(s.nsites == d.nsites && s.dof == d.dof && s.ntiles == d.ntiles, DDAMG_EINVAL, "mv_copy: shape");
+  if (s.prec == d.prec) {
+    DD_HIP(hipMemcpyAsync(d.p, s.p, s.bytes(), hipMemcpyDeviceToDevice, c->stream));
+    return;
+  }
+  // chunk widths differ between precisions: convert through the complex index
+  mv_convert(c, s, d);
+}
+
+template <typename RS, typename RD>
+__global__ void k_convert(const RS* __restrict__ a, RD* __restrict__ b, int ntiles, int nsites, int dof, int T) {
+  constexpr int RWS = Chunk<RS>::RW, RWD = Chunk<RD>::RW;
+  const int ncs = 2 * dof / RWS, ncd = 2 * dof / RWD;
+  const size_t total = (size_t)ntiles * nsites * dof * T;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(i % T);
+    size_t r = i / T;
+    const int s = (int)(r % nsites);
+    r /= nsites;
+    const int k = (int)(r % dof);
+    const int tile = (int)(r / dof);
+    const RS* p = a + (size_t)tile * ncs * nsites * T * RWS + (((size_t)(k / (RWS / 2)) * nsites + s) * T + t) * RWS +
+                  (k % (RWS / 2)) * 2;
+    RD* q = b + (size_t)tile * ncd * nsites * T * RWD + (((size_t)(k / (RWD / 2)) * nsites + s) * T + t) * RWD +
+            (k % (RWD / 2)) * 2;
+    q[0] = (RD)p[0];
+    q[1] = (RD)p[1];
+  }
+}
+
+void mv_convert(ddamg_ctx* c, const MV& s, const MV& d) {
+  const size_t n = (size_t)s.ntiles * s.nsites * s.dof * s.T;
+  if (s.prec == P64 && d.prec == P32)
+    hipLaunchKernelGGL((k_convert<double, float>), grid_for(n), dim3(256), 0, c->stream, s.as<double>(),
+                       d.as<float>(), s.ntiles, s.nsites, s.dof, s.T);
+  else if (s.prec == P32 && d.prec == P64)
+    hipLaunchKernelGGL((k_convert<float, double>), grid_for(n), dim3(256), 0, c->stream, s.as<float>(),
+                       d.as<double>(), s.ntiles, s.nsites, s.dof, s.T);
+  else
+    throw Error{DDAMG_EINVAL, "mv_convert: precisions"};
+  DD_HIP(hipGetLastError());
+}
+
+// y += sign * alpha_col x  (complex alpha per column; same precision)
+template <typename R>
+__global__ void k_axpy(const double* __restrict__ alpha, const R* __restrict__ x, R* __restrict__ y, size_t npairs,
+                       int T, int RWp, size_t tile_pairs, double sign) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs);
+    const int t = (int)((i / RWp) % T);
+    const int col = tile * T + t;
+    const double ar = sign * alpha[2 * col], ai = sign * alpha[2 * col + 1];
+    const R xr = x[2 * i], xi = x[2 * i + 1];
+    y[2 * i] += (R)(ar * xr - ai * xi);
+    y[2 * i + 1] += (R)(ar * xi + ai * xr);
+  }
+}
+
+// y = x + alpha_col y
+template <typename R>
+__global__ void k_xpay(const R* __restrict__ x, const double* __restrict__ alpha, R* __restrict__ y, size_t npairs,
+                       int T, int RWp, size_t tile_pairs) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs);
+    const int t = (int)((i / RWp) % T);
+    const int col = tile * T + t;
+    const double ar = alpha[2 * col], ai = alpha[2 * col + 1];
+    const R yr = y[2 * i], yi = y[2 * i + 1];
+    y[2 * i] = x[2 * i] + (R)(ar * yr - ai * yi);
+    y[2 * i + 1] = x[2 * i + 1] + (R)(ar * yi + ai * yr);
+  }
+}
+
+template <typename R>
+__global__ void k_scale(const double* __restrict__ alpha, R* __restrict__ x, size_t npairs, int T, int RWp,
+                        size_t tile_pairs) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs);
+    const int t = (int)((i / RWp) % T);
+    const int col = tile * T + t;
+    const double ar = alpha[2 * col], ai = alpha[2 * col + 1];
+    const R xr = x[2 * i], xi = x[2 * i + 1];
+    x[2 * i] = (R)(ar * xr - ai * xi);
+    x[2 * i + 1] = (R)(ar * xi + ai * xr);
+  }
+}
+
+template <typename R>
+__global__ void k_sub(const R* __restrict__ a, const R* __restrict__ b, R* __restrict__ o, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    o[i] = a[i] - b[i];
+}
+
+template <typename R>
+__global__ void k_add(const R* __restrict__ a, R* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] += a[i];
+}
+
+void mv_add(ddamg_ctx* c, const MV& x, const MV& y) {
+  DD_CHECK(x.prec == y.prec && x.reals() == y.reals(), DDAMG_EINVAL, "mv_add: shape");
+  const size_t n = x.reals();
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_add<double>, grid_for(n), dim3(256), 0, c->stream, x.as<double>(), y.as<double>(), n);
+  else
+    hipLaunchKernelGGL(k_add<float>, grid_for(n), dim3(256), 0, c->stream, x.as<float>(), y.as<float>(), n);
+  DD_HIP(hipGetLastError());
+}
+
+static inline size_t npairs_of(const MV& a) { return a.reals() / 2; }
+static inline size_t tile_pairs_of(const MV& a) { return a.tile_reals() / 2; }
+
+void mv_axpy(ddamg_ctx* c, const double* d_alpha, const MV& x, const MV& y, int sign) {
+  DD_CHECK(x.prec == y.prec && x.reals() == y.reals(), DDAMG_EINVAL, "mv_axpy: shape");
+  const size_t n = npairs_of(x);
+  const int RWp = reals_per_chunk(x.prec) / 2;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_axpy<double>, grid_for(n), dim3(256), 0, c->stream, d_alpha, x.as<double>(), y.as<double>(),
+                       n, x.T, RWp, tile_pairs_of(x), (double)sign);
+  else
+    hipLaunchKernelGGL(k_axpy<float>, grid_for(n), dim3(256), 0, c->stream, d_alpha, x.as<float>(), y.as<float>(), n,
+                       x.T, RWp, tile_pairs_of(x), (double)sign);
+  DD_HIP(hipGetLastError());
+}
+
+void mv_xpay(ddamg_ctx* c, const MV& x, const double* d_alpha, const MV& y) {
+  DD_CHECK(x.prec == y.prec && x.reals() == y.reals(), DDAMG_EINVAL, "mv_xpay: shape");
+  const size_t n = npairs_of(x);
+  const int RWp = reals_per_chunk(x.prec) / 2;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_xpay<double>, grid_for(n), dim3(256), 0, c->stream, x.as<double>(), d_alpha, y.as<double>(),
+                       n, x.T, RWp, tile_pairs_of(x));
+  else
+    hipLaunchKernelGGL(k_xpay<float>, grid_for(n), dim3(256), 0, c->stream, x.as<float>(), d_alpha, y.as<float>(), n,
+                       x.T, RWp, tile_pairs_of(x));
+  DD_HIP(hipGetLastError());
+}
+
+void mv_scale(ddamg_ctx* c, const double* d_alpha, const MV& x) {
+  const size_t n = npairs_of(x);
+  const int RWp = reals_per_chunk(x.prec) / 2;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_scale<double>, grid_for(n), dim3(256), 0, c->stream, d_alpha, x.as<double>(), n, x.T, RWp,
+                       tile_pairs_of(x));
+  else
+    hipLaunchKernelGGL(k_scale<float>, grid_for(n), dim3(256), 0, c->stream, d_alpha, x.as<float>(), n, x.T, RWp,
+                       tile_pairs_of(x));
+  DD_HIP(hipGetLastError());
+}
+
+void mv_sub(ddamg_ctx* c, const MV& a, const MV& b, const MV& o) {
+  DD_CHECK(a.prec == b.prec && a.prec == o.prec && a.reals() == b.reals(), DDAMG_EINVAL, "mv_sub: shape");
+  const size_t n = a.reals();
+  if (a.prec == P64)
+    hipLaunchKernelGGL(k_sub<double>, grid_for(n), dim3(256), 0, c->stream, a.as<double>(), b.as<double>(),
+                       o.as<double>(), n);
+  else
+    hipLaunchKernelGGL(k_sub<float>, grid_for(n), dim3(256), 0, c->stream, a.as<float>(), b.as<float>(), o.as<float>(),
+                       n);
+  DD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ multi-dot ---
+struct PtrPack {
+  const void* p[MAXK];
+};
+
+// Stage 1: partial[bM][j][col] = sum over this workgroup's rows of conj(V_j) w.
+// A workgroup is 256 lanes = 32 rows x T columns... with T = 8: lane = row*8 + t.
+template <typename R>
+__global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* __restrict__ w, double* __restrict__ part,
+                                                   size_t M, int ntiles, int ncol) {
+  constexpr int RW = Chunk<R>::RW;
+  constexpr int T = TTB;
+  const int t = threadIdx.x % T, row = threadIdx.x / T;
+  const int tile = blockIdx.y;
+  const int nbM = gridDim.x;
+  const size_t tile_reals = M * T * RW;
+  double accr[MAXK / 2], acci[MAXK / 2];
+  // two passes over k if k > MAXK/2
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  __shared__ double red[4][T][MAXK / 2][2];
+  for (int j0 = 0; j0 < k; j0 += MAXK / 2) {
+    const int kk = min(MAXK / 2, k - j0);
+#pragma unroll
+    for (int j = 0; j < MAXK / 2; ++j) { accr[j] = 0; acci[j] = 0; }
+    for (size_t m = (size_t)blockIdx.x * 32 + row; m < M; m += (size_t)nbM * 32) {
+      const size_t off = (size_t)tile * tile_reals + (m * T + t) * RW;
+      R wv[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) wv[r] = w[off + r];
+#pragma unroll 4
+      for (int j = 0; j < kk; ++j) {
+        const R* v = reinterpret_cast<const R*>(Vs.p[j0 + j]) + off;
+#pragma unroll
+        for (int r = 0; r < RW; r += 2) {
+          const double vr = v[r], vi = v[r + 1], xr = wv[r], xi = wv[r + 1];
+          accr[j] += vr * xr + vi * xi;
+          acci[j] += vr * xi - vi * xr;
+        }
+      }
+    }
+    // reduce the 8 rows of this wave that share t
+    for (int j = 0; j < kk; ++j) {
+      double a = accr[j], b = acci[j];
+#pragma unroll
+      for (int off = T; off < 64; off <<= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+      }
+      if (lane < T) { red[wave][lane][j][0] = a; red[wave][lane][j][1] = b; }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kk * T; idx += 256) {
+      const int j = idx / T, tt = idx % T;
+      double a = 0, b = 0;
+#pragma unroll
+      for (int w4 = 0; w4 < 4; ++w4) { a += red[w4][tt][j][0]; b += red[w4][tt][j][1]; }
+      const int col = tile * T + tt;
+      double* pp = part + (((size_t)blockIdx.x * k + j0 + j) * ncol + col) * 2;
+      pp[0] = a; pp[1] = b;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_multidot2(const double* __restrict__ part, double* __restrict__ out, int nbM, int k, int ncol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;   // i = j*ncol + col
+  if (i >= k * ncol) return;
+  double a = 0, b = 0;
+  for (int q = 0; q < nbM; ++q) {
+    a += part[((size_t)q * k * ncol + i) * 2];
+    b += part[((size_t)q * k * ncol + i) * 2 + 1];
+  }
+  out[2 * i] = a;
+  out[2 * i + 1] = b;
+}
+
+void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out) {
+  DD_CHECK(k >= 1 && k <= MAXK, DDAMG_EINVAL, "mv_multidot: k");
+  DD_CHECK(w.T == TTB, DDAMG_EINVAL, "mv_multidot: tile width");
+  PtrPack pk;
+  for (int j = 0; j < k; ++j) {
+    DD_CHECK(Vs[j].prec == w.prec && Vs[j].reals() == w.reals(), DDAMG_EINVAL, "mv_multidot: shape");
+    pk.p[j] = Vs[j].p;
+  }
+  const size_t M = (size_t)w.nchunk * w.nsites;
+  int nbM = (int)std::min<size_t>((M + 31) / 32, 2048 / (size_t)w.ntiles + 1);
+  if (nbM < 1) nbM = 1;
+  const int ncol = w.ncol();
+  double* part = scratch(c, (size_t)nbM * k * ncol * 2 * sizeof(double));
+  dim3 grid(nbM, w.ntiles);
+  if (w.prec == P64)
+    hipLaunchKernelGGL(k_multidot1<double>, grid, dim3(256), 0, c->stream, pk, k, w.as<double>(), part, M, w.ntiles,
+                       ncol);
+  else
+    hipLaunchKernelGGL(k_multidot1<float>, grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M, w.ntiles,
+                       ncol);
+  DD_HIP(hipGetLastError());
+  const int n = k * ncol;
+  hipLaunchKernelGGL(k_multidot2, dim3((n + 255) / 256), dim3(256), 0, c->stream, part, d_out, nbM, k, ncol);
+  DD_HIP(hipGetLastError());
+}
+
+void mv_dot(ddamg_ctx* c, const MV& a, const MV& b, double* d_out) { mv_multidot(c, &a, 1, b, d_out); }
+
+__global__ void k_re_only(const double* in, double* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[2 * i];
+}
+
+void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out) {
+  double* cbuf = small_buffer(c, 2 * a.ncol());
+  mv_multidot(c, &a, 1, a, cbuf);
+  hipLaunchKernelGGL(k_re_only, dim3((a.ncol() + 255) / 256), dim3(256), 0, c->stream, cbuf, d_out, a.ncol());
+  DD_HIP(hipGetLastError());
+}
+
+// w += sign * sum_j coef[j][col] V_j   (coef complex, V_j precision RV, w precision RW_)
+template <typename RV, typename RWt>
+__global__ void k_multiaxpy(PtrPack Vs, int k, const double* __restrict__ coef, RWt* __restrict__ w, size_t npairs,
+                            int T, int RWp, size_t tile_pairs, int ncol, double sign) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs);
+    const int t = (int)((i / RWp) % T);
+    const int col = tile * T + t;
+    double ar = 0, ai = 0;
+    for (int j = 0; j < k; ++j) {
+      const RV* v = reinterpret_cast<const RV*>(Vs.p[j]);
+      const double cr = coef[((size_t)j * ncol + col) * 2], ci = coef[((size_t)j * ncol + col) * 2 + 1];
+      const double vr = v[2 * i], vi = v[2 * i + 1];
+      ar += cr * vr - ci * vi;
+      ai += cr * vi + ci * vr;
+    }
+    w[2 * i] = (RWt)((double)w[2 * i] + sign * ar);
+    w[2 * i + 1] = (RWt)((double)w[2 * i + 1] + sign * ai);
+  }
+}
+
+// FP64 w += sign * sum_j coef V_j with FP32 V_j (one complex per FP64 chunk,
+// two per FP32 chunk: the FP32 position is recomputed from the complex index)
+__global__ void k_multiaxpy_mixed(PtrPack Vs, int k, const double* __restrict__ coef, double* __restrict__ w,
+                                  size_t npairs, int T, int nsites, size_t tile_pairs_w, size_t tile_pairs_v, int ncol,
+                                  double sign) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs_w);
+    size_t r = i % tile_pairs_w;       // ((kc * nsites + s) * T + t)   (one complex per FP64 chunk)
+    const int t = (int)(r % T);
+    r /= T;
+    const int s = (int)(r % nsites);
+    const int kc = (int)(r / nsites);
+    const size_t iv = (size_t)tile * tile_pairs_v + (((size_t)(kc / 2) * nsites + s) * T + t) * 2 + (kc % 2);
+    const int col = tile * T + t;
+    double ar = 0, ai = 0;
+    for (int j = 0; j < k; ++j) {
+      const float* v = reinterpret_cast<const float*>(Vs.p[j]);
+      const double cr = coef[((size_t)j * ncol + col) * 2], ci = coef[((size_t)j * ncol + col) * 2 + 1];
+      const double vr = v[2 * iv], vi = v[2 * iv + 1];
+      ar += cr * vr - ci * vi;
+      ai += cr * vi + ci * vr;
+    }
+    w[2 * i] += sign * ar;
+    w[2 * i + 1] += sign * ai;
+  }
+}
+
+void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign) {
+  DD_CHECK(k >= 0 && k <= MAXK, DDAMG_EINVAL, "mv_multiaxpy: k");
+  if (k == 0) return;
+  PtrPack pk;
+  for (int j = 0; j < k; ++j) {
+    DD_CHECK(Vs[j].nsites == w.nsites && Vs[j].dof == w.dof && Vs[j].ntiles == w.ntiles && Vs[j].prec == Vs[0].prec,
+             DDAMG_EINVAL, "mv_multiaxpy: shape");
+    pk.p[j] = Vs[j].p;
+  }
+  const size_t n = npairs_of(w);
+  if (Vs[0].prec != w.prec) {
+    DD_CHECK(Vs[0].prec == P32 && w.prec == P64, DDAMG_EINVAL, "mv_multiaxpy: precisions");
+    hipLaunchKernelGGL(k_multiaxpy_mixed, grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<double>(), n,
+                       w.T, w.nsites, tile_pairs_of(w), tile_pairs_of(Vs[0]), w.ncol(), (double)sign);
+    DD_HIP(hipGetLastError());
+    return;
+  }
+  const int RWp = reals_per_chunk(w.prec) / 2;
+  if (w.prec == P64)
+    hipLaunchKernelGGL((k_multiaxpy<double, double>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<double>(), n, w.T, RWp, tile_pairs_of(w), w.ncol(), (double)sign);
+  else
+    hipLaunchKernelGGL((k_multiaxpy<float, float>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<float>(),
+                       n, w.T, RWp, tile_pairs_of(w), w.ncol(), (double)sign);
+  DD_HIP(hipGetLastError());
+}
+
+}  // namespace ddamg

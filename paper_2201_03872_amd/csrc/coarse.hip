@@ -1,0 +1,347 @@
+// Coarse-level kernels: restriction R = P^dag and prolongation P (paper
+// section 2: built from approximate low modes, chirality preserving), the
+// batched coarse stencil, and the pieces of the Galerkin setup.
+//
+// Coarse operator on level l+1 (blocks d x d, d = 2N):
+//   y(a) = A0(a) x(a) + i dmu mu gamma5_c x(a) + sum_nu [F_nu(a) x(a+nu) + B_nu(a) x(a-nu)]
+// Blocks are stored column-major, [site][slot][col j][row i], slot 0 = A0,
+// 1+nu = F_nu, 5+nu = B_nu, so the lanes of one column j that own
+// consecutive rows i read consecutive addresses, and one block element serves
+// all T columns of the tile.
+#include "common.h"
+#include "device.h"
+
+namespace ddamg {
+
+constexpr int TC = 8;
+
+static inline dim3 grid1(size_t n) {
+  size_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+template <typename R>
+__device__ __forceinline__ void store_one(R* __restrict__ tile, int nsites, int T, int s, int t, int k, cx<R> v) {
+  constexpr int RW = Chunk<R>::RW;
+  constexpr int CPC = RW / 2;
+  R* q = tile + (((size_t)(k / CPC) * nsites + s) * T + t) * RW + (k % CPC) * 2;
+  q[0] = v.re;
+  q[1] = v.im;
+}
+
+// ------------------------------------------------------- coarse stencil ---
+// MODE 0: full operator with twist; MODE 1: self block + hops internal to the
+// grouping of this level (no twist); MODE 2: single hop `hopi` if it leaves
+// the group of the site.
+template <typename R, int MODE>
+__global__ void k_coarse(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ blk,
+                         const int* __restrict__ nbr, const double* __restrict__ mu, double muf, int V, int d,
+                         size_t tile_reals, int gsize, int hopi) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = wg % V;
+  const int tile = wg / V;
+  const int i = threadIdx.x / TC, t = threadIdx.x % TC;
+  const R* xt = x + (size_t)tile * tile_reals;
+  cx<R> acc = {0, 0};
+  const int g = s / gsize;
+  for (int slot = 0; slot < 9; ++slot) {
+    int nb = s;
+    if (slot > 0) nb = nbr[(size_t)(slot - 1) * V + s];
+    if constexpr (MODE == 1) {
+      if (slot > 0 && nb / gsize != g) continue;
+    } else if constexpr (MODE == 2) {
+      if (slot != 1 + hopi || nb / gsize == g) continue;
+    }
+    const cx<R>* A = reinterpret_cast<const cx<R>*>(blk) + ((size_t)s * 9 + slot) * d * d + i;
+    for (int j = 0; j < d; ++j) cmac(acc, A[(size_t)j * d], load_one(xt, V, TC, nb, t, j));
+  }
+  if constexpr (MODE == 0) {
+    const cx<R> xs = load_one(xt, V, TC, s, t, i);
+    const R m = (R)(muf * mu[tile * TC + t]) * (i < d / 2 ? (R)1 : (R)-1);
+    acc.re -= m * xs.im;
+    acc.im += m * xs.re;
+  }
+  store_one(y + (size_t)tile * tile_reals, V, TC, s, t, i, acc);
+}
+
+void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
+  const LevelGeom& g = c->geom[level];
+  const int d = g.dof;
+  dim3 grid(g.V * x.ntiles), blk(d * TC);
+  if (x.prec == P64)
+    hipLaunchKernelGGL((k_coarse<double, 0>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
+                       c->coarse[level].d_blk64, g.d_nbr, d_mu, c->coarse[level].mu_factor, g.V, d, x.tile_reals(),
+                       g.gsize, 0);
+  else
+    hipLaunchKernelGGL((k_coarse<float, 0>), grid, blk, 0, c->stream, x.as<float>(), y.as<float>(),
+                       c->coarse[level].d_blk32, g.d_nbr, d_mu, c->coarse[level].mu_factor, g.V, d, x.tile_reals(),
+                       g.gsize, 0);
+  DD_HIP(hipGetLastError());
+}
+
+void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, int hopi) {
+  DD_CHECK(x.prec == P64, DDAMG_EINVAL, "masked coarse stencil is FP64 only");
+  const LevelGeom& g = c->geom[level];
+  const int d = g.dof;
+  dim3 grid(g.V * x.ntiles), blk(d * TC);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_coarse<double, 1>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
+                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, 0);
+  else
+    hipLaunchKernelGGL((k_coarse<double, 2>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
+                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, hopi);
+  DD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ restrict ---
+// y(a)[s*N + j] = sum_{x in A_a} sum_{k of chirality s} conj(P[x][k][j]) x(x)[k]
+// One workgroup per (coarse site, tile); lane = (row, column).
+template <typename R>
+__global__ void k_restrict(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ P,
+                           const int* __restrict__ c_int2can, int Vf, int dof, int N, int gs, int Vc,
+                           size_t tile_f, size_t tile_c) {
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = wg % Vc, tile = wg / Vc;
+  const int r = threadIdx.x / TC, t = threadIdx.x % TC;
+  const int sig = r / N, j = r % N;
+  const int h = dof / 2;
+  const int b = c_int2can[a];
+  const R* xt = x + (size_t)tile * tile_f;
+  const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
+  cx<R> acc = {0, 0};
+  for (int q = 0; q < gs; ++q) {
+    const int s = b * gs + q;
+    for (int kk = 0; kk < h; ++kk) {
+      const int k = sig * h + kk;
+      cmac_conj(acc, Pc[((size_t)s * dof + k) * N + j], load_one(xt, Vf, TC, s, t, k));
+    }
+  }
+  store_one(y + (size_t)tile * tile_c, Vc, TC, a, t, r, acc);
+}
+
+void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
+  const LevelGeom& gf = c->geom[level];
+  const LevelGeom& gc = c->geom[level + 1];
+  const int N = c->tr[level].N;
+  DD_CHECK(x.prec == y.prec && x.ntiles == y.ntiles && x.nsites == gf.V && y.nsites == gc.V, DDAMG_EINVAL,
+           "restrict: shape");
+  dim3 grid(gc.V * x.ntiles), blk(2 * N * TC);
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_restrict<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
+                       gc.d_int2can, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
+  else
+    hipLaunchKernelGGL(k_restrict<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
+                       gc.d_int2can, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
+  DD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- prolong ---
+// y(x)[k] (+)= sum_j P[x][k][j] xc(a(x))[s(k)*N + j];  lane = (fine site, column)
+template <typename R>
+__global__ void __launch_bounds__(256) k_prolong(const R* __restrict__ xc, R* __restrict__ y, const R* __restrict__ P,
+                                                 const int* __restrict__ c_can2int, int Vf, int dof, int N, int gs,
+                                                 int Vc, size_t tile_f, size_t tile_c, int accumulate, int nsb) {
+  constexpr int SP = 256 / TC;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = wg / nsb;
+  const int s = (wg % nsb) * SP + threadIdx.x / TC;
+  const int t = threadIdx.x % TC;
+  if (s >= Vf) return;
+  const int a = c_can2int[s / gs];
+  const R* ct = xc + (size_t)tile * tile_c;
+  R* yt = y + (size_t)tile * tile_f;
+  const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
+  const int h = dof / 2;
+  for (int k = 0; k < dof; ++k) {
+    const int sig = k / h;
+    cx<R> acc = {0, 0};
+    const cx<R>* Pr = Pc + ((size_t)s * dof + k) * N;
+    for (int j = 0; j < N; ++j) cmac(acc, Pr[j], load_one(ct, Vc, TC, a, t, sig * N + j));
+    if (accumulate) acc = acc + load_one(yt, Vf, TC, s, t, k);
+    store_one(yt, Vf, TC, s, t, k, acc);
+  }
+}
+
+void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulate) {
+  const LevelGeom& gf = c->geom[level];
+  const LevelGeom& gc = c->geom[level + 1];
+  const int N = c->tr[level].N;
+  DD_CHECK(x.prec == y.prec && x.ntiles == y.ntiles && y.nsites == gf.V && x.nsites == gc.V, DDAMG_EINVAL,
+           "prolong: shape");
+  const int nsb = (gf.V + 256 / TC - 1) / (256 / TC);
+  dim3 grid(nsb * x.ntiles), blk(256);
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_prolong<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
+                       gc.d_can2int, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+  else
+    hipLaunchKernelGGL(k_prolong<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
+                       gc.d_can2int, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+  DD_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- setup ---
+// X[col = s*N + j](x)[k] = P[x][k][j] if chirality(k) == s else 0   (FP64)
+__global__ void k_basis_field(const double* __restrict__ P, double* __restrict__ X, int V, int dof, int N,
+                              size_t tile_reals) {
+  const size_t total = (size_t)2 * N * V * dof;
+  const int h = dof / 2;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % dof);
+    const size_t r = i / dof;
+    const int s = (int)(r % V);
+    const int col = (int)(r / V);
+    const int sig = col / N, j = col % N;
+    cx<double> v = {0, 0};
+    if (k / h == sig) {
+      const double* p = P + (((size_t)s * dof + k) * N + j) * 2;
+      v = {p[0], p[1]};
+    }
+    store_one(X + (size_t)(col / TC) * tile_reals, V, TC, s, col % TC, k, v);
+  }
+}
+
+void build_basis_field(ddamg_ctx* c, int level, const MV& X) {
+  const LevelGeom& g = c->geom[level];
+  const int N = c->tr[level].N;
+  DD_CHECK(X.prec == P64 && X.ncol() >= 2 * N && X.nsites == g.V, DDAMG_EINVAL, "basis field: shape");
+  const size_t n = (size_t)2 * N * g.V * g.dof;
+  hipLaunchKernelGGL(k_basis_field, grid1(n), dim3(256), 0, c->stream, c->tr[level].d_P64, X.as<double>(), g.V, g.dof,
+                     N, X.tile_reals());
+  DD_HIP(hipGetLastError());
+}
+
+// P[s][k][j] = tv_j(s)[k]
+__global__ void k_gather_tv(const double* __restrict__ tv, double* __restrict__ P, int V, int dof, int N,
+                            size_t tile_reals) {
+  const size_t total = (size_t)V * dof * N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i % N);
+    const size_t r = i / N;
+    const int k = (int)(r % dof);
+    const int s = (int)(r / dof);
+    const cx<double> v = load_one(tv + (size_t)(j / TC) * tile_reals, V, TC, s, j % TC, k);
+    P[2 * i] = v.re;
+    P[2 * i + 1] = v.im;
+  }
+}
+
+void gather_test_vectors(ddamg_ctx* c, int level, const MV& tv, double* d_P) {
+  const LevelGeom& g = c->geom[level];
+  const int N = c->tr[level].N;
+  DD_CHECK(tv.prec == P64 && tv.ncol() >= N && tv.nsites == g.V, DDAMG_EINVAL, "gather tv: shape");
+  const size_t n = (size_t)g.V * g.dof * N;
+  hipLaunchKernelGGL(k_gather_tv, grid1(n), dim3(256), 0, c->stream, tv.as<double>(), d_P, g.V, g.dof, N,
+                     tv.tile_reals());
+  DD_HIP(hipGetLastError());
+}
+
+// Block reduction of a complex value over 256 threads (result in every thread).
+__device__ __forceinline__ cx<double> block_sum(cx<double> v, cx<double>* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  const int w = threadIdx.x / 64;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  cx<double> r = red[0];
+  for (int q = 1; q < (int)(blockDim.x / 64); ++q) r = r + red[q];
+  return r;
+}
+
+// Orthonormalise, per (group of gs sites, chirality), the N columns of the
+// (gs * dof/2) x N matrix P by modified Gram-Schmidt applied twice; the
+// diagonal of R comes out real and positive, so the result equals any other
+// QR of full-rank input with that convention.
+__global__ void __launch_bounds__(256) k_orthonormalise(double* __restrict__ P, int dof, int N, int gs) {
+  __shared__ cx<double> red[4];
+  const int b = blockIdx.x / 2, sig = blockIdx.x % 2;
+  const int h = dof / 2;
+  const int nrows = gs * h;
+  cx<double>* Pc = reinterpret_cast<cx<double>*>(P);
+  auto at = [&](int row, int j) -> cx<double>& {
+    const int s = b * gs + row / h, k = sig * h + row % h;
+    return Pc[((size_t)s * dof + k) * N + j];
+  };
+  for (int j = 0; j < N; ++j) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < j; ++i) {
+        cx<double> part = {0, 0};
+        for (int row = threadIdx.x; row < nrows; row += blockDim.x) cmac_conj(part, at(row, i), at(row, j));
+        const cx<double> rij = block_sum(part, red);
+        for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
+          cx<double>& q = at(row, j);
+          q = q - rij * at(row, i);
+        }
+        __syncthreads();
+      }
+    cx<double> part = {0, 0};
+    for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
+      const cx<double> q = at(row, j);
+      part.re += q.re * q.re + q.im * q.im;
+    }
+    const double nrm = sqrt(block_sum(part, red).re);
+    const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+    for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
+      cx<double>& q = at(row, j);
+      q = inv * q;
+    }
+    __syncthreads();
+  }
+}
+
+void orthonormalise_P(ddamg_ctx* c, int level, double* d_P) {
+  const LevelGeom& g = c->geom[level];
+  const int nblk = g.V / g.gsize;
+  hipLaunchKernelGGL(k_orthonormalise, dim3(2 * nblk), dim3(256), 0, c->stream, d_P, g.dof, c->tr[level].N, g.gsize);
+  DD_HIP(hipGetLastError());
+}
+
+// blocks(level+1)[a][slot][col][row] = Rc[col](a)[row]
+__global__ void k_scatter_blocks(const double* __restrict__ Rc, double* __restrict__ blk, int Vc, int d,
+                                 size_t tile_reals, int slot) {
+  const size_t total = (size_t)Vc * d * d;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(i % d);
+    const size_t r = i / d;
+    const int col = (int)(r % d);
+    const int a = (int)(r / d);
+    const cx<double> v = load_one(Rc + (size_t)(col / TC) * tile_reals, Vc, TC, a, col % TC, row);
+    double* q = blk + ((((size_t)a * 9 + slot) * d + col) * d + row) * 2;
+    q[0] = v.re;
+    q[1] = v.im;
+  }
+}
+
+void scatter_blocks(ddamg_ctx* c, int level, const MV& Rc, int slot) {
+  const LevelGeom& gc = c->geom[level + 1];
+  const int d = gc.dof;
+  const size_t n = (size_t)gc.V * d * d;
+  hipLaunchKernelGGL(k_scatter_blocks, grid1(n), dim3(256), 0, c->stream, Rc.as<double>(),
+                     c->coarse[level + 1].d_blk64, gc.V, d, Rc.tile_reals(), slot);
+  DD_HIP(hipGetLastError());
+}
+
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+void convert_P32(ddamg_ctx* c, int level) {
+  const LevelGeom& g = c->geom[level];
+  const size_t n = (size_t)g.V * g.dof * c->tr[level].N * 2;
+  hipLaunchKernelGGL(k_d2f, grid1(n), dim3(256), 0, c->stream, c->tr[level].d_P64, c->tr[level].d_P32, n);
+  DD_HIP(hipGetLastError());
+}
+
+void convert_blocks32(ddamg_ctx* c, int level) {
+  const LevelGeom& g = c->geom[level];
+  const size_t n = (size_t)g.V * 9 * g.dof * g.dof * 2;
+  hipLaunchKernelGGL(k_d2f, grid1(n), dim3(256), 0, c->stream, c->coarse[level].d_blk64, c->coarse[level].d_blk32, n);
+  DD_HIP(hipGetLastError());
+}
+
+}  // namespace ddamg

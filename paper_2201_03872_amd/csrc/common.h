@@ -1,0 +1,200 @@
+// Internal declarations of the gfx950 multigrid library.
+//
+// Internal vector layout ("column-tiled SoA"): a multivector of n columns on a
+// lattice level with `dof` complex components per site is stored as
+//     [tile][chunk][site][T][RW]
+// with T columns per tile, RW reals per 16-byte lane chunk (2 for FP64 = one
+// complex, 4 for FP32 = two complexes) and nchunk = 2*dof/RW chunks per site.
+// A wavefront lane handles one (site, column); a row of T lanes of one site
+// reads T*16 contiguous bytes, consecutive sites are contiguous, and a link
+// or coarse block loaded once serves all T columns of the tile.  This is the
+// GPU form of the paper's vector bundle with the vector index running fastest
+// (section 3, Fig. 2 right), chunked by the tile width as the paper chunks by
+// num_loop.
+//
+// Sites are stored in block-major order: the lattice is cut into the blocks
+// of the level's grouping (SAP blocks = first-level aggregates on the fine
+// level, the next aggregates on a coarse level), blocks in lexicographic
+// order, sites lexicographic inside a block.  SAP blocks, aggregates and
+// restriction/prolongation therefore touch contiguous site ranges.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/ddamg.h"
+
+namespace ddamg {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define DD_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::ddamg::Error{e_ == hipErrorOutOfMemory ? DDAMG_ENOMEM : DDAMG_EDEVICE,  \
+                           std::string(#call) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+#define DD_CHECK(cond, code, msg)                        \
+  do {                                                   \
+    if (!(cond)) throw ::ddamg::Error{(code), (msg)};    \
+  } while (0)
+
+enum Prec { P64 = 0, P32 = 1 };
+
+inline int reals_per_chunk(int prec) { return prec == P64 ? 2 : 4; }
+inline size_t real_size(int prec) { return prec == P64 ? 8 : 4; }
+
+// One multivector in the column-tiled layout.
+struct MV {
+  void* p = nullptr;
+  int prec = P64;
+  int ntiles = 0;
+  int T = 8;
+  int nchunk = 0;   // 2*dof / RW
+  int nsites = 0;
+  int dof = 0;      // complex components per site
+  bool owned = false;
+
+  int ncol() const { return ntiles * T; }
+  size_t tile_reals() const { return (size_t)nchunk * nsites * T * reals_per_chunk(prec); }
+  size_t reals() const { return tile_reals() * ntiles; }
+  size_t bytes() const { return reals() * real_size(prec); }
+  template <typename R> R* as() const { return static_cast<R*>(p); }
+  // view of tiles [t0, t0+nt)
+  MV tiles(int t0, int nt) const {
+    MV v = *this;
+    v.p = (char*)p + (size_t)t0 * tile_reals() * real_size(prec);
+    v.ntiles = nt;
+    v.owned = false;
+    return v;
+  }
+};
+
+// Geometry of one lattice level in the internal ordering.
+struct LevelGeom {
+  int dims[4] = {0, 0, 0, 0};
+  int V = 0;
+  int dof = 0;
+  int grp[4] = {1, 1, 1, 1};   // grouping block of the internal order
+  int gsize = 1;
+  std::vector<int> int2can, can2int;   // host permutations
+  int* d_nbr = nullptr;                // [8][V]; fine level: bit 31 = boundary sign
+  int* d_int2can = nullptr;            // [V]
+  int* d_can2int = nullptr;            // [V]
+};
+
+// Transfer between level l and l+1.
+struct Transfer {
+  int N = 0;                 // test vectors; coarse dof = 2N
+  double* d_P64 = nullptr;   // [V_l][dof_l][N] complex, orthonormal per (aggregate, chirality)
+  float* d_P32 = nullptr;
+};
+
+struct Coarse {
+  double* d_blk64 = nullptr;  // [V][9][d col][d row] complex (column-major blocks)
+  float* d_blk32 = nullptr;
+  double mu_factor = 1.0;
+};
+
+// Simple device allocation pool: every buffer is released at context destruction.
+struct DevPool {
+  std::vector<void*> blocks;
+  void* alloc(size_t bytes);
+  void release(void* p);
+  void clear();
+};
+
+struct Stats {
+  double setup_seconds = 0, solve_seconds = 0;
+  int outer_iters = 0;
+  long long middle_calls = 0, middle_iters = 0, bottom_calls = 0, bottom_iters = 0;
+  long long fine_ops = 0, sap_calls = 0;
+  int learned_fallbacks = 0;
+};
+
+}  // namespace ddamg
+
+struct ddamg_ctx {
+  ddamg_params p;
+  hipStream_t stream = nullptr;
+  int T = 8;
+  int nlev = 1;
+  double m0 = 0, diag = 0;
+  ddamg::LevelGeom geom[3];
+  ddamg::Transfer tr[2];
+  ddamg::Coarse coarse[3];
+  double* d_U64 = nullptr;    // [4 mu][9 chunk][V] double2
+  float* d_U32 = nullptr;     // [4 mu][3 chunk][V] float4, rows 0 and 1
+  int* d_sap_list[2] = {nullptr, nullptr};   // block ids of each colour
+  int n_sap[2] = {0, 0};
+  double* d_scratch = nullptr;  // reduction partials
+  size_t scratch_bytes = 0;
+  double* d_small = nullptr;    // small temporary results
+  int small_n = 0;
+  double* h_pinned = nullptr;   // pinned host staging of small results
+  size_t pinned_bytes = 0;
+  ddamg::DevPool pool;
+  ddamg::Stats st;
+  void* work = nullptr;         // solver workspaces (solve.hip)
+};
+
+namespace ddamg {
+
+// ---- multivector management (blas.hip) ----
+MV mv_alloc(ddamg_ctx* c, int level, int prec, int ncol_min);
+MV mv_like(ddamg_ctx* c, const MV& a, int prec);
+void mv_free(ddamg_ctx* c, MV& a);
+void mv_zero(ddamg_ctx* c, const MV& a);
+void mv_copy(ddamg_ctx* c, const MV& src, const MV& dst);          // any precisions
+void mv_axpy(ddamg_ctx* c, const double* d_alpha, const MV& x, const MV& y, int sign);  // y += sign*alpha_c x_c
+void mv_xpay(ddamg_ctx* c, const MV& x, const double* d_alpha, const MV& y);  // y = x + alpha_c y
+void mv_scale(ddamg_ctx* c, const double* d_alpha, const MV& x);  // x *= alpha_c (complex)
+void mv_sub(ddamg_ctx* c, const MV& a, const MV& b, const MV& out);   // out = a - b
+void mv_add(ddamg_ctx* c, const MV& x, const MV& y);                  // y += x
+// per-column complex dots <V_j, w> for j < k, written to d_out[j*ncol + c] (complex)
+void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out);
+// w -= sum_j coef[j*ncol+c] V_j   (coef complex, device)
+void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign);
+void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out);          // per column, real
+void mv_dot(ddamg_ctx* c, const MV& a, const MV& b, double* d_out);  // per column complex
+// masked scaling: columns with mask==0 are zeroed
+// canonical <-> internal conversion (fine or coarse level)
+void to_internal(ddamg_ctx* c, int level, const double* canon, int n_col, const MV& out);
+void from_internal(ddamg_ctx* c, int level, const MV& in, int n_col, double* canon);
+
+// ---- fine-level kernels (fine.hip) ----
+void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu);
+void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu);
+void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hop);
+void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV& work);
+
+// ---- coarse kernels (coarse.hip) ----
+void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);
+void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, int hop);
+void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y);
+void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulate);
+void build_basis_field(ddamg_ctx* c, int level, const MV& X);   // X[s*N+j] = P restricted to chirality s
+void gather_test_vectors(ddamg_ctx* c, int level, const MV& tv, double* d_P);   // tv -> [V][d][N]
+void orthonormalise_P(ddamg_ctx* c, int level, double* d_P);
+void scatter_blocks(ddamg_ctx* c, int level, const MV& R, int slot);  // coarse level = level+1
+void convert_P32(ddamg_ctx* c, int level);
+void convert_blocks32(ddamg_ctx* c, int level);
+
+// ---- host helpers ----
+void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);
+double* scratch(ddamg_ctx* c, size_t bytes);          // reduction partials (grows)
+double* small_buffer(ddamg_ctx* c, int n_doubles);    // short-lived small device results (grows)
+void mv_convert(ddamg_ctx* c, const MV& s, const MV& d);
+void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_norm2);   // x_c /= sqrt(norm2_c)
+void copy_to_host(ddamg_ctx* c, const void* d, void* h, size_t bytes);
+
+}  // namespace ddamg

@@ -1,0 +1,501 @@
+// Solver orchestration on the host: batched (F)GMRES, the multigrid cycle,
+// the adaptive setup and the outer FP64 solve.
+//
+// Paper section 4: FGMRES at the top level (goal residual 1e-10), a
+// (non-block) FGMRES on the middle level to r_m ~ 7e-2 preconditioned by the
+// next level, GMRES on the bottom level to r_b ~ 1e-1; orthogonalisation by
+// classical Gram-Schmidt without re-orthogonalisation.  Section 2: the
+// preconditioner combines the coarse-grid correction with SAP smoothing.
+//
+// Every column (one rhs x one twisted mass) runs its own Arnoldi process; all
+// columns advance together through batched kernels, and each column's
+// solution uses exactly the iterations up to the one at which it met its own
+// tolerance.  The small Hessenberg least-squares problems are solved on the
+// host after one device->host copy per iteration.
+#include <chrono>
+#include <complex>
+#include <functional>
+#include <map>
+
+#include "common.h"
+#include "device.h"
+
+namespace ddamg {
+
+void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, int dof, bool fine);
+void random_fill(ddamg_ctx* c, int level, const MV& X, int ncol, uint64_t seed);
+
+using cd = std::complex<double>;
+using Precond = std::function<void(const MV& v, const MV& z)>;
+constexpr int KMAX = 64;
+
+// ------------------------------------------------------------ kernels ---
+__global__ void k_normalize(double* __restrict__ dummy, const double* __restrict__ n2, void* x, int prec, size_t npairs,
+                            int T, int RWp, size_t tile_pairs) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(i / tile_pairs);
+    const int t = (int)((i / RWp) % T);
+    const double v = n2[tile * T + t];
+    const double s = v > 0 ? 1.0 / sqrt(v) : 0.0;
+    if (prec == 0) {
+      double* p = (double*)x;
+      p[2 * i] *= s;
+      p[2 * i + 1] *= s;
+    } else {
+      float* p = (float*)x;
+      p[2 * i] = (float)(p[2 * i] * s);
+      p[2 * i + 1] = (float)(p[2 * i + 1] * s);
+    }
+  }
+}
+
+void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2) {
+  const size_t np = x.reals() / 2;
+  size_t g = (np + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_normalize, dim3((unsigned)g), dim3(256), 0, c->stream, nullptr, d_n2, x.p, x.prec, np, x.T,
+                     reals_per_chunk(x.prec) / 2, x.tile_reals() / 2);
+  DD_HIP(hipGetLastError());
+}
+
+// alpha = <q, r> / <q, q> per column (MR step), 0 where <q,q> = 0
+__global__ void k_mr_alpha(const double* __restrict__ qr, const double* __restrict__ qq, double* __restrict__ a,
+                           int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = qq[i];
+  a[2 * i] = d > 0 ? qr[2 * i] / d : 0.0;
+  a[2 * i + 1] = d > 0 ? qr[2 * i + 1] / d : 0.0;
+}
+
+// -------------------------------------------------------- workspaces ---
+struct LW {
+  int cap = 0;                   // tiles
+  int prec = 0;
+  std::vector<MV> V, Z;
+  MV zt, rc, ec, res, s, q, rho;
+  double* d_h = nullptr;         // [KMAX][ncol] complex dots + [ncol] norm
+  double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
+};
+
+struct Work {
+  std::map<std::pair<int, int>, LW> lw;
+};
+
+static Work& work(ddamg_ctx* c) {
+  if (!c->work) c->work = new Work();
+  return *static_cast<Work*>(c->work);
+}
+
+void free_work(ddamg_ctx* c) {
+  delete static_cast<Work*>(c->work);
+  c->work = nullptr;
+}
+
+static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles) {
+  LW& w = work(c).lw[{level, prec}];
+  if (ntiles > w.cap) {
+    for (auto& m : w.V) mv_free(c, m);
+    for (auto& m : w.Z) mv_free(c, m);
+    MV* all[] = {&w.zt, &w.rc, &w.ec, &w.res, &w.s, &w.q, &w.rho};
+    for (MV* m : all) mv_free(c, *m);
+    w.V.clear();
+    w.Z.clear();
+    if (w.d_h) c->pool.release(w.d_h);
+    if (w.d_aux) c->pool.release(w.d_aux);
+    w.cap = ntiles;
+    w.prec = prec;
+    const int ncol = ntiles * c->T;
+    w.d_h = (double*)c->pool.alloc(((size_t)KMAX * ncol * 2 + ncol) * sizeof(double));
+    w.d_aux = (double*)c->pool.alloc((size_t)KMAX * ncol * 2 * sizeof(double));
+  }
+  return w;
+}
+
+static MV get(ddamg_ctx* c, MV& slot, int level, int prec, int cap, int nt) {
+  if (!slot.p) slot = mv_alloc(c, level, prec, cap * c->T);
+  return slot.tiles(0, nt);
+}
+
+static MV basis(ddamg_ctx* c, std::vector<MV>& vec, int j, int level, int prec, int cap, int nt) {
+  while ((int)vec.size() <= j) vec.push_back(MV{});
+  return get(c, vec[j], level, prec, cap, nt);
+}
+
+// ------------------------------------------------------------ Krylov ---
+struct KrylovOut {
+  std::vector<int> iters;
+  std::vector<double> relres;   // Arnoldi estimate / ||b|| at exit
+  int total = 0;
+};
+
+static double host_norm_guard(double v) { return v > 0 ? std::sqrt(v) : 0.0; }
+
+// (F)GMRES(m) on level `level` for all columns of b (precision of b/x);
+// preconditioner output precision zprec.  x holds the initial guess unless
+// x_zero.  fixed: run exactly maxit iterations without a convergence test.
+void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero, double tol, int m,
+            int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out) {
+  const int nt = b.ntiles, ncol = b.ncol(), prec = b.prec;
+  DD_CHECK(m >= 1 && m < KMAX, DDAMG_EINVAL, "Krylov restart length must be in [1, 63]");
+  LW& w = lw(c, level, prec, nt);
+  const int cap = w.cap;
+  std::vector<double> hbuf((size_t)KMAX * ncol * 2 + ncol);
+  std::vector<double> bn(ncol), tol_abs(ncol), est(ncol);
+  double* d_n2 = w.d_h + (size_t)KMAX * ncol * 2;
+  mv_norm2(c, b, d_n2);
+  copy_to_host(c, d_n2, bn.data(), ncol * sizeof(double));
+  std::vector<char> done(ncol, 0);
+  for (int i = 0; i < ncol; ++i) {
+    bn[i] = host_norm_guard(bn[i]);
+    tol_abs[i] = tol * bn[i];
+    if (bn[i] == 0) done[i] = 1;
+    est[i] = bn[i];
+  }
+  std::vector<int> iters(ncol, 0);
+  std::vector<cd> H((size_t)ncol * (m + 1) * m), g((size_t)ncol * (m + 1)), sn((size_t)ncol * m);
+  std::vector<double> cs((size_t)ncol * m);
+  std::vector<int> kc(ncol);
+  std::vector<double> coef;
+  int total = 0;
+  bool first = true;
+  if (x_zero) mv_zero(c, x);
+  while (true) {
+    MV r = basis(c, w.V, 0, level, prec, cap, nt);
+    if (x_zero && first) {
+      mv_copy(c, b, r);
+    } else {
+      MV t = get(c, w.res, level, prec, cap, nt);
+      if (level == 0 && prec == b.prec) fine_residual(c, b, x, r, d_mu);
+      else {
+        operator_apply(c, level, x, t, d_mu);
+        mv_sub(c, b, t, r);
+      }
+    }
+    first = false;
+    std::vector<double> beta(ncol);
+    mv_norm2(c, r, d_n2);
+    copy_to_host(c, d_n2, beta.data(), ncol * sizeof(double));
+    bool all = true;
+    for (int i = 0; i < ncol; ++i) {
+      beta[i] = host_norm_guard(beta[i]);
+      est[i] = beta[i];
+      if (!fixed && beta[i] <= tol_abs[i]) done[i] = 1;
+      if (bn[i] == 0) done[i] = 1;
+      if (!done[i]) all = false;
+    }
+    if ((all && !fixed) || total >= maxit) break;
+    mv_normalize(c, r, d_n2);
+    for (int i = 0; i < ncol; ++i) {
+      kc[i] = done[i] ? 0 : -1;
+      for (int j = 0; j <= m; ++j) g[(size_t)i * (m + 1) + j] = 0;
+      g[(size_t)i * (m + 1)] = beta[i];
+    }
+    int jj = 0;
+    for (int j = 0; j < m && total < maxit; ++j) {
+      MV vj = basis(c, w.V, j, level, prec, cap, nt);
+      MV z = vj;
+      if (pc) {
+        z = basis(c, w.Z, j, level, zprec, cap, nt);
+        (*pc)(vj, z);
+      }
+      MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
+      if (z.prec != prec) {
+        MV zt = get(c, w.zt, level, prec, cap, nt);
+        mv_copy(c, z, zt);
+        operator_apply(c, level, zt, vn, d_mu);
+      } else {
+        operator_apply(c, level, z, vn, d_mu);
+      }
+      std::vector<MV> Vs(j + 1);
+      for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
+      mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
+      mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
+      mv_norm2(c, vn, d_n2);
+      // one copy of the dots and the norm
+      const size_t nh = (size_t)(j + 1) * ncol * 2;
+      copy_to_host(c, w.d_h, hbuf.data(), nh * sizeof(double));
+      copy_to_host(c, d_n2, hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
+      mv_normalize(c, vn, d_n2);
+      ++total;
+      jj = j + 1;
+      bool alld = true;
+      for (int i = 0; i < ncol; ++i) {
+        cd* Hc = &H[(size_t)i * (m + 1) * m];
+        for (int q = 0; q <= j; ++q)
+          Hc[(size_t)q * m + j] = cd(hbuf[((size_t)q * ncol + i) * 2], hbuf[((size_t)q * ncol + i) * 2 + 1]);
+        const double hn = host_norm_guard(hbuf[(size_t)KMAX * ncol * 2 + i]);
+        Hc[(size_t)(j + 1) * m + j] = hn;
+        if (done[i] && kc[i] >= 0) continue;
+        // apply the previous rotations to column j
+        for (int q = 0; q < j; ++q) {
+          const cd a = Hc[(size_t)q * m + j], bb = Hc[(size_t)(q + 1) * m + j];
+          const double cq = cs[(size_t)i * m + q];
+          const cd sq = sn[(size_t)i * m + q];
+          Hc[(size_t)q * m + j] = cq * a + sq * bb;
+          Hc[(size_t)(q + 1) * m + j] = -std::conj(sq) * a + cq * bb;
+        }
+        const cd a = Hc[(size_t)j * m + j], bb = Hc[(size_t)(j + 1) * m + j];
+        double cc;
+        cd ss, rr;
+        if (std::abs(bb) == 0) { cc = 1; ss = 0; rr = a; }
+        else if (std::abs(a) == 0) { cc = 0; ss = std::conj(bb) / std::abs(bb); rr = std::abs(bb); }
+        else {
+          const double na = std::abs(a), nr = std::hypot(na, std::abs(bb));
+          cc = na / nr;
+          ss = (a / na) * std::conj(bb) / nr;
+          rr = (a / na) * nr;
+        }
+        cs[(size_t)i * m + j] = cc;
+        sn[(size_t)i * m + j] = ss;
+        Hc[(size_t)j * m + j] = rr;
+        Hc[(size_t)(j + 1) * m + j] = 0;
+        cd* gc = &g[(size_t)i * (m + 1)];
+        const cd gj = gc[j];
+        gc[j] = cc * gj;
+        gc[j + 1] = -std::conj(ss) * gj;
+        est[i] = std::abs(gc[j + 1]);
+        if (!fixed && (est[i] <= tol_abs[i] || hn == 0)) {
+          done[i] = 1;
+          kc[i] = j + 1;
+        }
+        if (!done[i]) alld = false;
+      }
+      if (!fixed && alld) break;
+    }
+    // per-column least squares and the update x += basis * y
+    coef.assign((size_t)jj * ncol * 2, 0.0);
+    for (int i = 0; i < ncol; ++i) {
+      const int k = kc[i] >= 0 ? kc[i] : jj;
+      if (k == 0) continue;
+      const cd* Hc = &H[(size_t)i * (m + 1) * m];
+      const cd* gc = &g[(size_t)i * (m + 1)];
+      std::vector<cd> y(k);
+      for (int q = k - 1; q >= 0; --q) {
+        cd acc = gc[q];
+        for (int p = q + 1; p < k; ++p) acc -= Hc[(size_t)q * m + p] * y[p];
+        const cd d = Hc[(size_t)q * m + q];
+        y[q] = std::abs(d) > 0 ? acc / d : cd(0);
+      }
+      for (int q = 0; q < k; ++q) {
+        coef[((size_t)q * ncol + i) * 2] = y[q].real();
+        coef[((size_t)q * ncol + i) * 2 + 1] = y[q].imag();
+      }
+      iters[i] += k;
+      if (kc[i] < 0) kc[i] = jj;
+    }
+    if (jj > 0) {
+      DD_HIP(hipMemcpyAsync(w.d_aux, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      std::vector<MV> B(jj);
+      for (int q = 0; q < jj; ++q) B[q] = pc ? basis(c, w.Z, q, level, zprec, cap, nt) : basis(c, w.V, q, level, prec, cap, nt);
+      mv_multiaxpy(c, B.data(), jj, w.d_aux, x, +1);
+      DD_HIP(hipStreamSynchronize(c->stream));   // coef is a host vector reused next cycle
+    }
+    bool all2 = true;
+    for (int i = 0; i < ncol; ++i)
+      if (!done[i]) all2 = false;
+    if (fixed || all2 || total >= maxit) break;
+  }
+  if (out) {
+    out->iters = iters;
+    out->relres.resize(ncol);
+    for (int i = 0; i < ncol; ++i) out->relres[i] = bn[i] > 0 ? est[i] / bn[i] : 0.0;
+    out->total = total;
+  }
+}
+
+// --------------------------------------------------------------- MG ---
+static void mr_smooth(ddamg_ctx* c, int level, const double* d_mu, const MV& f, const MV& xo, int iters) {
+  const int nt = f.ntiles, ncol = f.ncol();
+  LW& w = lw(c, level, f.prec, nt);
+  MV rho = get(c, w.rho, level, f.prec, w.cap, nt);
+  MV q = get(c, w.q, level, f.prec, w.cap, nt);
+  mv_copy(c, f, rho);
+  mv_zero(c, xo);
+  double* qr = w.d_aux;
+  double* qq = w.d_aux + 2 * ncol;
+  double* al = w.d_aux + 4 * ncol;
+  for (int k = 0; k < iters; ++k) {
+    operator_apply(c, level, rho, q, d_mu);
+    mv_dot(c, q, rho, qr);
+    mv_norm2(c, q, qq);
+    hipLaunchKernelGGL(k_mr_alpha, dim3((ncol + 255) / 256), dim3(256), 0, c->stream, qr, qq, al, ncol);
+    DD_HIP(hipGetLastError());
+    mv_axpy(c, al, rho, xo, +1);
+    mv_axpy(c, al, q, rho, -1);
+  }
+}
+
+// e = MG_l(r): restrict, solve the next level, prolong, post-smooth.
+void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e) {
+  const int nt = r.ntiles, prec = r.prec;
+  LW& w = lw(c, l, prec, nt);
+  MV rc = get(c, w.rc, l + 1, prec, w.cap, nt);
+  MV ec = get(c, w.ec, l + 1, prec, w.cap, nt);
+  restrict_mv(c, l, r, rc);
+  KrylovOut ko;
+  const bool bottom = (l + 2 == c->nlev);
+  if (bottom) {
+    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1),
+           std::min(c->p.bottom_maxit, KMAX - 1), nullptr, prec, false, &ko);
+    c->st.bottom_calls++;
+    int mx = 0;
+    for (int i : ko.iters) mx = std::max(mx, i);
+    c->st.bottom_iters += ko.total;
+  } else {
+    Precond pc = [&](const MV& v, const MV& z) { mg_cycle(c, l + 1, d_mu, v, z); };
+    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_m, std::min(c->p.middle_restart, KMAX - 1), c->p.middle_maxit, &pc,
+           prec, false, &ko);
+    c->st.middle_calls++;
+    c->st.middle_iters += ko.total;
+  }
+  prolong_mv(c, l, ec, e, 0);
+  MV res = get(c, w.res, l, prec, w.cap, nt);
+  MV s = get(c, w.s, l, prec, w.cap, nt);
+  if (l == 0) {
+    fine_residual(c, r, e, res, d_mu);
+    sap_apply(c, res, s, d_mu, s);
+  } else {
+    MV t = get(c, w.q, l, prec, w.cap, nt);
+    operator_apply(c, l, e, t, d_mu);
+    mv_sub(c, r, t, res);
+    mr_smooth(c, l, d_mu, res, s, c->p.coarse_smooth_iters);
+  }
+  mv_add(c, s, e);
+}
+
+// ------------------------------------------------------------- setup ---
+void galerkin(ddamg_ctx* c, int l) {
+  const int N = c->tr[l].N;
+  MV X = mv_alloc(c, l, P64, 2 * N);
+  MV Y = mv_alloc(c, l, P64, 2 * N);
+  MV Rc = mv_alloc(c, l + 1, P64, 2 * N);
+  build_basis_field(c, l, X);
+  for (int slot = 0; slot < 9; ++slot) {
+    const int mode = slot == 0 ? 0 : 1;
+    if (l == 0) fine_masked(c, X, Y, mode, slot - 1);
+    else coarse_masked(c, l, X, Y, mode, slot - 1);
+    restrict_mv(c, l, Y, Rc);
+    scatter_blocks(c, l, Rc, slot);
+  }
+  DD_HIP(hipStreamSynchronize(c->stream));
+  mv_free(c, X);
+  mv_free(c, Y);
+  mv_free(c, Rc);
+}
+
+// Build P (orthonormalised test vectors) of transition l and every operator
+// below it.  tv: FP64 multivector of N columns on level l.
+void build_transition(ddamg_ctx* c, int l, const MV& tv) {
+  const LevelGeom& g = c->geom[l];
+  const int N = c->tr[l].N;
+  const size_t nP = (size_t)g.V * g.dof * N * 2;
+  if (!c->tr[l].d_P64) {
+    c->tr[l].d_P64 = (double*)c->pool.alloc(nP * sizeof(double));
+    c->tr[l].d_P32 = (float*)c->pool.alloc(nP * sizeof(float));
+  }
+  gather_test_vectors(c, l, tv, c->tr[l].d_P64);
+  orthonormalise_P(c, l, c->tr[l].d_P64);
+  convert_P32(c, l);
+  const LevelGeom& gc = c->geom[l + 1];
+  const size_t nb = (size_t)gc.V * 9 * gc.dof * gc.dof * 2;
+  if (!c->coarse[l + 1].d_blk64) {
+    c->coarse[l + 1].d_blk64 = (double*)c->pool.alloc(nb * sizeof(double));
+    c->coarse[l + 1].d_blk32 = (float*)c->pool.alloc(nb * sizeof(float));
+  }
+  c->coarse[l + 1].mu_factor = (l + 2 == c->nlev) ? c->p.coarse_mu_factor : 1.0;
+  galerkin(c, l);
+  convert_blocks32(c, l + 1);
+  DD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Test-vector generation of transition l: random start vectors, then
+// setup_rounds smoothing rounds (SAP on the fine level, fixed-length GMRES on
+// a coarse level) each followed by normalisation (section 2: P from a few
+// approximate low modes).
+void setup_transition(ddamg_ctx* c, int l, const double* tv_init_host) {
+  const LevelGeom& g = c->geom[l];
+  const int N = c->tr[l].N;
+  MV tv = mv_alloc(c, l, P64, N);
+  MV tmp = mv_alloc(c, l, P64, N);
+  if (tv_init_host) {
+    const size_t n = (size_t)N * g.V * g.dof * 2;
+    double* d = (double*)c->pool.alloc(n * sizeof(double));
+    DD_HIP(hipMemcpy(d, tv_init_host, n * sizeof(double), hipMemcpyHostToDevice));
+    to_internal(c, l, d, N, tv);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    c->pool.release(d);
+  } else {
+    random_fill(c, l, tv, N, c->p.seed + 7919ULL * (l + 1));
+  }
+  std::vector<double> hmu(tv.ncol(), 0.0);
+  for (int i = 0; i < N; ++i) hmu[i] = c->p.mu_setup;
+  double* d_mu = (double*)c->pool.alloc(hmu.size() * sizeof(double));
+  DD_HIP(hipMemcpy(d_mu, hmu.data(), hmu.size() * sizeof(double), hipMemcpyHostToDevice));
+  double* d_n2 = (double*)c->pool.alloc(tv.ncol() * sizeof(double));
+  for (int r = 0; r < c->p.setup_rounds; ++r) {
+    if (l == 0) {
+      sap_apply(c, tv, tmp, d_mu, tmp);
+    } else {
+      krylov(c, l, d_mu, tv, tmp, true, 0.0, c->p.setup_coarse_iters, c->p.setup_coarse_iters, nullptr, P64, true,
+             nullptr);
+    }
+    mv_norm2(c, tmp, d_n2);
+    mv_normalize(c, tmp, d_n2);
+    mv_copy(c, tmp, tv);
+  }
+  build_transition(c, l, tv);
+  c->pool.release(d_mu);
+  c->pool.release(d_n2);
+  mv_free(c, tv);
+  mv_free(c, tmp);
+}
+
+void build_hierarchy(ddamg_ctx* c, const double* const* tv_init) {
+  for (int l = 0; l + 1 < c->nlev; ++l) setup_transition(c, l, tv_init ? tv_init[l] : nullptr);
+}
+
+// Rebuild from host test vectors (canonical layout) of transition l.
+void rebuild_from_test_vectors(ddamg_ctx* c, int l, const double* tv_host) {
+  const LevelGeom& g = c->geom[l];
+  const int N = c->tr[l].N;
+  MV tv = mv_alloc(c, l, P64, N);
+  const size_t n = (size_t)N * g.V * g.dof * 2;
+  double* d = (double*)c->pool.alloc(n * sizeof(double));
+  DD_HIP(hipMemcpy(d, tv_host, n * sizeof(double), hipMemcpyHostToDevice));
+  to_internal(c, l, d, N, tv);
+  build_transition(c, l, tv);
+  c->pool.release(d);
+  mv_free(c, tv);
+  // every coarser transition is rebuilt from its current P (coarse operators changed)
+  for (int q = l + 1; q + 1 < c->nlev; ++q) {
+    c->coarse[q + 1].mu_factor = (q + 2 == c->nlev) ? c->p.coarse_mu_factor : 1.0;
+    galerkin(c, q);
+    convert_blocks32(c, q + 1);
+  }
+  DD_HIP(hipStreamSynchronize(c->stream));
+}
+
+// ------------------------------------------------------------- solve ---
+// Outer FP64 FGMRES over all columns, preconditioned by the MG cycle in the
+// precision of the chosen mode.
+int solve_internal(ddamg_ctx* c, const double* d_mu, const MV& b, const MV& x, bool x_zero, std::vector<int>& iters) {
+  const int prec = c->p.precision == DDAMG_MIXED ? P32 : P64;
+  const int nt = b.ntiles;
+  LW& w0 = lw(c, 0, prec, nt);   // preconditioner-precision temporaries on level 0
+  MV vin = get(c, w0.rho, 0, prec, w0.cap, nt);
+  Precond pc = [&](const MV& v, const MV& z) {
+    const MV& in = (prec == v.prec) ? v : vin;
+    if (prec != v.prec) mv_copy(c, v, vin);
+    if (c->nlev == 1) sap_apply(c, in, z, d_mu, z);
+    else mg_cycle(c, 0, d_mu, in, z);
+  };
+  KrylovOut ko;
+  krylov(c, 0, d_mu, b, x, x_zero, c->p.tol, std::min(c->p.outer_restart, KMAX - 1), c->p.max_outer, &pc, prec, false,
+         &ko);
+  iters = ko.iters;
+  c->st.outer_iters = ko.total;
+  return 0;
+}
+
+}  // namespace ddamg

@@ -1,0 +1,76 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function the
+header declares, and the Python structure layouts match the C ones (the
+layout is measured by compiling a small C probe of include/ddamg.h with gcc).
+No compute call is made here: those need the GPU."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_2201_03872_amd as dd
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dd.load()
+    names = dd.header_symbols()
+    assert "ddamg_setup" in names and "ddamg_solve" in names and "ddamg_apply_op" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_is_static_and_host_only():
+    lib = dd.load()
+    for code in (dd.OK, dd.NOT_CONVERGED, dd.EINVAL, dd.ENOMEM, dd.EDEVICE, dd.EBREAKDOWN, dd.ESTATE, 1234):
+        assert lib.ddamg_strerror(code)
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ddamg.h"
+#define F(s, f) printf(#s "." #f " %zu %zu\n", offsetof(s, f), sizeof(((s*)0)->f));
+int main(void) {
+  printf("ddamg_params %zu\n", sizeof(ddamg_params));
+  printf("ddamg_col_info %zu\n", sizeof(ddamg_col_info));
+  printf("ddamg_stats %zu\n", sizeof(ddamg_stats));
+%s
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header():
+    fields = []
+    for sname, cls in (("ddamg_params", dd.Params), ("ddamg_col_info", dd.ColInfo), ("ddamg_stats", dd.Stats)):
+        for f, _ in cls._fields_:
+            fields.append(f"  F({sname}, {f})")
+    src = PROBE.replace("%s", "\n".join(fields))
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(dd.HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 2:
+            got[parts[0]] = int(parts[1])
+        elif len(parts) == 3:
+            got[parts[0]] = (int(parts[1]), int(parts[2]))
+    assert got["ddamg_params"] == ctypes.sizeof(dd.Params)
+    assert got["ddamg_col_info"] == ctypes.sizeof(dd.ColInfo)
+    assert got["ddamg_stats"] == ctypes.sizeof(dd.Stats)
+    for sname, cls in (("ddamg_params", dd.Params), ("ddamg_col_info", dd.ColInfo), ("ddamg_stats", dd.Stats)):
+        for f, _ in cls._fields_:
+            d = getattr(cls, f)
+            assert got[f"{sname}.{f}"] == (d.offset, d.size), (sname, f)
+
+
+def test_default_params_are_the_papers_tolerances():
+    p = dd.default_params()
+    assert p.tol == 1e-10
+    assert abs(p.r_m - 7e-2) < 1e-15 and abs(p.r_b - 1e-1) < 1e-15
+    assert p.coarse_mu_factor == 1.0

@@ -1,0 +1,314 @@
+"""GPU parity of every step of the hot path against the FP64 oracle, through
+the C ABI (device pointers from torch, which only provides memory/streams).
+
+Bars: FP64 operator applications (fine stencil, SAP, R, P, coarse stencil)
+match the oracle to 1e-13 relative per column (1e-12 for SAP, whose MR
+coefficients are reductions summed in a different order); FP32 forms are
+reported against a bound derived from single-precision rounding; solves
+reach a true FP64 residual <= 1e-10 per column, evaluated by the oracle's
+operator on the host.  Sizes span several column tiles (tile = 8 columns)
+with a ragged tail, and the full 16^3x32 lattice is checked on sampled sites
+and through properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as S
+import oracle as O
+from oracle.multigrid import Blocking, FineLevel, build_prolongator, restrict, prolong, galerkin
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2201_03872_amd as m
+    m.load()
+    return m
+
+
+def relerr_cols(a, b):
+    n = a.shape[0]
+    a = a.reshape(n, -1)
+    b = b.reshape(n, -1)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def ctx_for(dd, dims, kappa, sap_block, n_levels=1, agg=None, n_tv=None, eps=0.3, seed=41, tv_init=None, **kw):
+    U = S.gauge_field(dims, eps, seed)
+    kwargs = dict(dims=dims, kappa=kappa, n_levels=n_levels, sap_block=sap_block)
+    if agg is not None:
+        kwargs["agg"] = agg
+    if n_tv is not None:
+        kwargs["n_tv"] = n_tv
+    kwargs.update(kw)
+    p = dd.default_params(**kwargs)
+    return dd.Context(p, U, tv_init=tv_init), U
+
+
+@pytest.mark.parametrize("dims,blk,ncol", [((4, 4, 4, 4), (2, 2, 2, 2), 13), ((8, 4, 4, 8), (4, 4, 4, 4), 6),
+                                           ((4, 4, 2, 8), (2, 2, 2, 2), 17)])
+def test_fine_operator_fp64_and_fp32(torch_cuda, dd, dims, blk, ncol):
+    torch = torch_cuda
+    say("fine operator", dims, blk, ncol)
+    ctx, U = ctx_for(dd, dims, 0.15, blk)
+    V = S.volume(dims)
+    x = S.gaussian_spinors(ncol, V, 5)
+    mus = np.linspace(-0.3, 0.5, ncol)
+    ref = O.WilsonTM(U, dims, kappa=0.15).apply(x, mus)
+    xg = torch.from_numpy(x).cuda()
+    y64 = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
+    assert np.max(relerr_cols(y64, ref)) < 1e-13
+    y32 = ctx.apply_op(0, dd.FP32, mus, xg).cpu().numpy()
+    e32 = np.max(relerr_cols(y32, ref))
+    say("  fp32 relative error", e32)
+    assert e32 < 2e-6
+    ctx.close()
+
+
+def test_fine_operator_full_lattice_sampled(torch_cuda, dd):
+    """16^3x32, 48 columns (the precision-study shape): sampled sites against
+    the oracle's site-by-site formula, gamma5-hermiticity on full vectors."""
+    torch = torch_cuda
+    dims = (16, 16, 16, 32)
+    V = S.volume(dims)
+    say("fine operator full lattice", dims)
+    ctx, U = ctx_for(dd, dims, 0.15, (4, 4, 4, 4), seed=102)
+    ncol = 48
+    mus = np.tile(np.array([0.002, 0.01, 0.03, 0.1]), 12)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.complex(torch.randn((ncol, V, 4, 3), dtype=torch.float64, device="cuda", generator=gen),
+                      torch.randn((ncol, V, 4, 3), dtype=torch.float64, device="cuda", generator=gen))
+    y = ctx.apply_op(0, dd.FP64, mus, x)
+    op = O.WilsonTM(U, dims, kappa=0.15)
+    rng = np.random.default_rng(7)
+    sites = sorted(set([0, V - 1, 16 * 16 * 16 * 31, 15] + list(rng.integers(0, V, 60))))
+    xs = x.cpu().numpy()
+    ref = op.apply_site(xs, mus, sites)
+    got = y.cpu().numpy()[:, sites]
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-13
+    # gamma5-hermiticity: <phi, g5 D(mu) g5 psi> = <D(-mu) phi, psi>
+    g5 = torch.tensor([1, 1, -1, -1], dtype=torch.float64, device="cuda").view(1, 1, 4, 1)
+    phi = x.roll(1, dims=0)
+    lhs = torch.sum(phi.conj() * g5 * ctx.apply_op(0, dd.FP64, mus, (g5 * x).contiguous()), dim=(1, 2, 3))
+    rhs = torch.sum(ctx.apply_op(0, dd.FP64, -mus, phi.contiguous()).conj() * x, dim=(1, 2, 3))
+    assert torch.max(torch.abs(lhs - rhs) / torch.abs(lhs)).item() < 1e-12
+    ctx.close()
+
+
+def test_fine_operator_free_field_full_lattice(torch_cuda, dd):
+    """Unit links: a plane wave is mapped to M(p) + i sum gamma sin p + i mu gamma5
+    times itself, at the 16^3x32 production shape (closed form)."""
+    torch = torch_cuda
+    dims = (16, 16, 16, 32)
+    V = S.volume(dims)
+    say("free field full lattice")
+    U = np.broadcast_to(np.eye(3, dtype=np.complex128), (V, 4, 3, 3)).copy()
+    p = dd.default_params(dims=dims, kappa=0.15, n_levels=1, sap_block=(4, 4, 4, 4))
+    ctx = dd.Context(p, U)
+    m0 = 1 / 0.3 - 4
+    i = np.arange(V)
+    x, y, z, t = S.site_coords(i, dims)
+    g = O.gammas()
+    rng = np.random.default_rng(11)
+    cols, expect = [], []
+    mus = np.array([0.0, 0.05, 0.3, 0.002, 0.1, 0.7, 0.01, 0.2, 0.4])
+    for c in range(len(mus)):
+        n = [int(rng.integers(0, d)) for d in dims]
+        pm = [2 * np.pi * n[k] / dims[k] for k in range(3)] + [(2 * n[3] + 1) * np.pi / dims[3]]
+        u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        ph = np.exp(1j * (pm[0] * x + pm[1] * y + pm[2] * z + pm[3] * t))
+        M = m0 + sum(1 - np.cos(q) for q in pm)
+        K = M * np.eye(4) + 1j * sum(g[k] * np.sin(pm[k]) for k in range(4)) + 1j * mus[c] * O.gamma5()
+        cols.append(ph[:, None, None] * u[None])
+        expect.append(ph[:, None, None] * (K @ u)[None])
+    xg = torch.from_numpy(np.array(cols)).cuda()
+    out = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
+    assert np.max(np.abs(out - np.array(expect))) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("dims,blk,kappa", [((4, 4, 4, 4), (2, 2, 2, 2), 0.14), ((8, 8, 4, 8), (4, 4, 4, 4), 0.15)])
+def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
+    torch = torch_cuda
+    say("SAP", dims, blk)
+    ctx, U = ctx_for(dd, dims, kappa, blk, sap_cycles=2, sap_mr_iters=3)
+    V = S.volume(dims)
+    ncol = 11
+    f = S.gaussian_spinors(ncol, V, 8)
+    mus = np.linspace(0.001, 0.2, ncol)
+    lev = FineLevel(O.WilsonTM(U, dims, kappa=kappa))
+    ref = O.sap(lev, Blocking(dims, blk), f.reshape(ncol, V, 12), mus, 2, 3).reshape(ncol, V, 4, 3)
+    fg = torch.from_numpy(f).cuda()
+    x64 = ctx.apply_sap(dd.FP64, mus, fg).cpu().numpy()
+    assert np.max(relerr_cols(x64, ref)) < 1e-12
+    x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
+    e = np.max(relerr_cols(x32, ref))
+    say("  fp32 SAP relative error", e)
+    assert e < 1e-4
+    ctx.close()
+
+
+def _two_level_case(dd, dims, agg, N, n_levels=2, agg2=(2, 2, 2, 2), N2=8):
+    U = S.gauge_field(dims, 0.3, 61)
+    V = S.volume(dims)
+    tv = S.gaussian_spinors(N, V, 62)
+    kw = dict(dims=dims, kappa=0.15, n_levels=n_levels, sap_block=agg, agg=[agg, agg2], n_tv=[N, N2],
+              setup_rounds=1)
+    p = dd.default_params(**kw)
+    tv_init = [tv]
+    if n_levels == 3:
+        cdims = tuple(d // a for d, a in zip(dims, agg))
+        tv_init.append(S.gaussian_coarse(N2, S.volume(cdims), 2 * N, 63))
+    ctx = dd.Context(p, U, tv_init=tv_init)
+    return ctx, U, V
+
+
+def test_transfer_and_coarse_operator_parity(torch_cuda, dd):
+    """Oracle test vectors fed to the GPU: P, R, P^dag, the Galerkin blocks and
+    the coarse stencil all match the oracle in FP64."""
+    torch = torch_cuda
+    dims, agg, N = (8, 4, 4, 8), (2, 2, 2, 2), 8
+    say("transfer / coarse", dims, agg, N)
+    ctx, U, V = _two_level_case(dd, dims, agg, N)
+    tv = S.gaussian_spinors(N, V, 64).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv.reshape(N, V, 12))
+    blk = Blocking(dims, agg)
+    P = build_prolongator(tv, blk)
+    Pg = ctx.test_vectors(0)                     # [N][V][12]
+    assert np.max(np.abs(np.transpose(Pg, (1, 2, 0)) - P)) < 1e-13
+    lev = FineLevel(O.WilsonTM(U, dims, kappa=0.15))
+    coarse = galerkin(lev, P, blk)
+    Bg = ctx.coarse_op(1)
+    assert np.max(np.abs(Bg - coarse.blocks)) < 1e-13 * np.max(np.abs(coarse.blocks))
+    ncol = 10
+    x = S.gaussian_spinors(ncol, V, 65)
+    rc_ref = restrict(P, blk, x.reshape(ncol, V, 12))
+    rc = ctx.restrict(0, dd.FP64, torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(rc, rc_ref)) < 1e-13
+    xc = S.gaussian_coarse(ncol, blk.nblocks, 2 * N, 66)
+    pr_ref = prolong(P, blk, xc).reshape(ncol, V, 4, 3)
+    pr = ctx.prolong(0, dd.FP64, torch.from_numpy(xc).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(pr, pr_ref)) < 1e-13
+    mus = np.linspace(0.001, 0.3, ncol)
+    yc_ref = coarse.apply(xc, mus)
+    yc = ctx.apply_op(1, dd.FP64, mus, torch.from_numpy(xc).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(yc, yc_ref)) < 1e-13
+    yc32 = ctx.apply_op(1, dd.FP32, mus, torch.from_numpy(xc).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(yc32, yc_ref)) < 1e-5
+    ctx.close()
+
+
+def test_three_level_coarse_parity(torch_cuda, dd):
+    torch = torch_cuda
+    dims, agg, N, N2 = (8, 8, 4, 8), (2, 2, 2, 2), 6, 8
+    say("three-level coarse", dims)
+    ctx, U, V = _two_level_case(dd, dims, agg, N, n_levels=3, agg2=(2, 2, 2, 2), N2=N2)
+    tv = S.gaussian_spinors(N, V, 71).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv)
+    blk = Blocking(dims, agg)
+    P = build_prolongator(tv, blk)
+    c2 = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), P, blk)
+    tv2 = S.gaussian_coarse(N2, blk.nblocks, 2 * N, 72)
+    ctx.set_test_vectors(1, tv2)
+    blk2 = Blocking(blk.cdims, (2, 2, 2, 2))
+    P2 = build_prolongator(tv2, blk2)
+    c3 = galerkin(c2, P2, blk2)
+    B3 = ctx.coarse_op(2)
+    assert np.max(np.abs(B3 - c3.blocks)) < 1e-12 * np.max(np.abs(c3.blocks))
+    ncol = 9
+    x = S.gaussian_coarse(ncol, blk.nblocks, 2 * N, 73)
+    r_ref = restrict(P2, blk2, x)
+    r = ctx.restrict(1, dd.FP64, torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(r, r_ref)) < 1e-13
+    mus = np.linspace(0.002, 0.1, ncol)
+    xc3 = S.gaussian_coarse(ncol, blk2.nblocks, 2 * N2, 74)
+    y = ctx.apply_op(2, dd.FP64, mus, torch.from_numpy(xc3).cuda()).cpu().numpy()
+    assert np.max(relerr_cols(y, c3.apply(xc3, mus))) < 1e-13
+    ctx.close()
+
+
+def test_setup_parity_plain_fp64(torch_cuda, dd):
+    """The whole adaptive setup from the same random start vectors: SAP
+    smoothing rounds, orthonormalisation and Galerkin products agree with the
+    oracle up to accumulated rounding."""
+    w = S.workload("tm_4x4x4x4_2rhs_3shift")
+    say("setup parity", w.name)
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    starts = S.setup_start_vectors(w)
+    p = dd.params_for_workload(w)
+    ctx = dd.Context(p, U, tv_init=starts)
+    om = O.OracleMG(U, w.dims, w.kappa, O.MGParams(agg=w.agg, n_tv=w.n_tv, sap_block=w.sap_block,
+                                                   mu_setup=min(w.mus))).setup(starts)
+    B = ctx.coarse_op(1)
+    ref = om.levels[1].blocks
+    assert np.max(np.abs(B - ref)) < 1e-10 * np.max(np.abs(ref))
+    ctx.close()
+
+
+def _solve_and_check(torch, dd, w, precision, **over):
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    p = dd.params_for_workload(w, precision=precision, **over)
+    ctx = dd.Context(p, U, tv_init=S.setup_start_vectors(w))
+    b = S.rhs_for(w)
+    mus = np.array(w.mus)
+    x, info, st = ctx.solve(mus, torch.from_numpy(b).cuda())
+    xs = x.cpu().numpy()
+    op = O.WilsonTM(U, w.dims, kappa=w.kappa)
+    bb = np.repeat(b, len(mus), axis=0)
+    mm = np.tile(mus, w.n_rhs)
+    rel = O.col_norm(bb - op.apply(xs, mm)) / O.col_norm(bb)
+    say("  true residuals (oracle operator)", rel.max(), "iters", [i["outer_iters"] for i in info], ctx.stats())
+    ctx.close()
+    return rel, info, st
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_two_level(torch_cuda, dd, precision):
+    w = S.workload("tm_4x4x4x4_2rhs_3shift")
+    say("solve", w.name, "precision", precision)
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision)
+    assert st == dd.OK
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+    assert all(i["converged"] for i in info)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_three_level(torch_cuda, dd, precision):
+    w = S.workload("tm_8x8x8x8_3level")
+    say("solve", w.name, "precision", precision)
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision)
+    assert st == dd.OK
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+
+
+def test_error_paths(torch_cuda, dd):
+    torch = torch_cuda
+    say("error paths")
+    U = S.gauge_field((4, 4, 4, 4), 0.3, 1)
+    with pytest.raises(dd.DDAMGError) as e:
+        dd.Context(dd.default_params(dims=(4, 4, 4, 6), n_levels=1, sap_block=(2, 2, 2, 4)), S.gauge_field((4, 4, 4, 6), 0.3, 1))
+    assert e.value.code == dd.EINVAL
+    ctx = dd.Context(dd.default_params(dims=(4, 4, 4, 4), n_levels=1, sap_block=(2, 2, 2, 2), max_outer=1), U)
+    b = S.gaussian_spinors(1, 256, 2)
+    x, info, st = ctx.solve([0.01], torch.from_numpy(b).cuda())
+    assert st == dd.NOT_CONVERGED and not info[0]["converged"]
+    b[0, 3, 1, 2] = np.nan
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.solve([0.01], torch.from_numpy(b).cuda())
+    assert e.value.code == dd.EINVAL
+    ctx.close()
