@@ -86,6 +86,9 @@ typedef struct ddamg_params {
   int    sap_mr_iters;       /* MR iterations per block solve                                   */
   int    setup_rounds;       /* smoothing rounds of the random setup vectors                    */
   int    setup_coarse_iters; /* fixed GMRES length per coarse setup round                       */
+  int    setup_boot;         /* bootstrap rounds: fine test vectors <- MG cycle(test vectors)   */
+  int    setup_fine_iters;   /* 0: fine setup rounds are SAP calls; k > 0: k steps of           */
+                             /* SAP-preconditioned FGMRES (inverse iteration)                   */
   double mu_setup;           /* twisted mass used while building the hierarchy                  */
   double coarse_mu_factor;   /* delta mu on the coarsest level (Fig. 6 caption); 1 = none       */
   double tol;                /* outer relative residual goal (1e-10)                            */
@@ -188,8 +191,31 @@ int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);
  * internal vectors (n_col columns, given precision) with HIP events recorded
  * on the context's stream; *sec = mean seconds per launch.  op: 0 = fine
  * stencil (level 0), 1 = SAP smoother (level 0), 2 = coarse stencil of
- * `level`, 3 = restriction from `level`, 4 = prolongation to `level`. */
+ * `level`, 3 = restriction from `level`, 4 = prolongation to `level`,
+ * 5 = plain device copy of the multivector (reads and writes its size; a
+ * kernel of known traffic for calibrating memory counters). */
 int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int n_iter, double* sec);
+
+/* Tile-shape knobs.  DDAMG_KNOB_DSLASH_SITES_FP64: lattice sites per
+ * workgroup of the FP64 fine stencil (16, 32 or 64; each workgroup stages its
+ * sites x 8 columns in LDS); DDAMG_KNOB_DSLASH_SITES_FP32: the same for FP32
+ * (32, 64 or 128); DDAMG_KNOB_FP32_LINKS: storage of the FP32 links read by
+ * the fine stencil (0 = full 3x3 with the boundary sign folded in, 1 = 2-row
+ * compressed, third row rebuilt, sign from the neighbour table).  Unknown
+ * knobs or inadmissible values give DDAMG_EINVAL. */
+#define DDAMG_KNOB_DSLASH_SITES_FP64 0
+#define DDAMG_KNOB_DSLASH_SITES_FP32 1
+#define DDAMG_KNOB_FP32_LINKS        2   /* 0: full 3x3 FP32 links; 1: 2-row compressed */
+#define DDAMG_N_KNOBS 3
+int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
+int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
+
+/* Autotuner: for every knob, time each admissible value on resident random
+ * vectors of n_col columns (HIP events on the context's stream, 10 launches
+ * each), keep the fastest, and write the chosen values to values[knob]
+ * (values may be NULL).  Results depend on (lattice, n_col, device) and can be
+ * stored by the caller and restored with ddamg_set_tuning. */
+int ddamg_autotune(ddamg_ctx* h, int n_col, int* values);
 
 void ddamg_destroy(ddamg_ctx* h);
 const char* ddamg_strerror(int status);

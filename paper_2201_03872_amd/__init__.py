@@ -44,6 +44,8 @@ class Params(ctypes.Structure):
         ("sap_mr_iters", ctypes.c_int),
         ("setup_rounds", ctypes.c_int),
         ("setup_coarse_iters", ctypes.c_int),
+        ("setup_boot", ctypes.c_int),
+        ("setup_fine_iters", ctypes.c_int),
         ("mu_setup", ctypes.c_double),
         ("coarse_mu_factor", ctypes.c_double),
         ("tol", ctypes.c_double),
@@ -111,6 +113,9 @@ def load():
         "ddamg_solve": (ctypes.c_int, [vp, dp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, P(ColInfo)]),
         "ddamg_get_stats": (ctypes.c_int, [vp, P(Stats)]),
         "ddamg_time_op": (ctypes.c_int, [vp] + [ctypes.c_int] * 5 + [dp]),
+        "ddamg_set_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "ddamg_get_tuning": (ctypes.c_int, [vp, ctypes.c_int, ip]),
+        "ddamg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "ddamg_destroy": (None, [vp]),
         "ddamg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ddamg_last_error": (ctypes.c_char_p, []),
@@ -266,6 +271,21 @@ class Context:
         s = Stats()
         _check(load().ddamg_get_stats(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2}
+
+    def set_tuning(self, knob, value):
+        _check(load().ddamg_set_tuning(self.h, self.KNOBS.get(knob, knob), int(value)))
+
+    def get_tuning(self, knob) -> int:
+        v = ctypes.c_int()
+        _check(load().ddamg_get_tuning(self.h, self.KNOBS.get(knob, knob), ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, n_col) -> dict:
+        vals = (ctypes.c_int * len(self.KNOBS))()
+        _check(load().ddamg_autotune(self.h, int(n_col), vals))
+        return {k: vals[i] for k, i in self.KNOBS.items()}
 
     def time_op(self, op, level, precision, n_col, n_iter) -> float:
         sec = ctypes.c_double()

@@ -73,6 +73,8 @@ void ddamg_default_params(ddamg_params* p) {
   p->sap_mr_iters = 4;
   p->setup_rounds = 3;
   p->setup_coarse_iters = 10;
+  p->setup_boot = 0;
+  p->setup_fine_iters = 0;
   p->mu_setup = 0.0;
   p->coarse_mu_factor = 1.0;
   p->tol = 1e-10;
@@ -121,6 +123,8 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->outer_restart >= 1 && p->outer_restart <= 63, DDAMG_EINVAL, "outer_restart in [1, 63]");
   DD_CHECK(p->middle_restart >= 1 && p->middle_restart <= 63, DDAMG_EINVAL, "middle_restart in [1, 63]");
   DD_CHECK(p->bottom_maxit >= 1, DDAMG_EINVAL, "bottom_maxit >= 1");
+  DD_CHECK(p->setup_fine_iters >= 0 && p->setup_fine_iters <= 63, DDAMG_EINVAL, "setup_fine_iters in [0, 63]");
+  DD_CHECK(p->setup_boot >= 0 && p->setup_boot <= 16, DDAMG_EINVAL, "setup_boot in [0, 16]");
   DD_CHECK(p->setup_coarse_iters >= 1 && p->setup_coarse_iters <= 63, DDAMG_EINVAL, "setup_coarse_iters in [1, 63]");
   DD_CHECK(p->tol > 0 && p->r_m > 0 && p->r_b > 0, DDAMG_EINVAL, "tolerances must be positive");
   DD_CHECK(p->precision == DDAMG_PLAIN_FP64 || p->precision == DDAMG_MIXED, DDAMG_EINVAL, "precision mode");
@@ -415,6 +419,7 @@ int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int
     const int lout = (op == 3) ? level + 1 : level;
     DD_CHECK(!(op == 3 || op == 4) || level + 1 < c->nlev, DDAMG_ESTATE, "no such transition");
     DD_CHECK(!(op == 2) || level >= 1, DDAMG_EINVAL, "coarse stencil needs level >= 1");
+    DD_CHECK(op >= 0 && op <= 5, DDAMG_EINVAL, "unknown op");
     MV a64 = mv_alloc(c, lin, P64, n_col);
     random_fill(c, lin, a64, a64.ncol(), 99);
     MV a = (prec == P64) ? a64 : mv_like(c, a64, P32);
@@ -428,7 +433,8 @@ int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int
         case 1: sap_apply(c, a, b, d_mu, b); break;
         case 2: coarse_apply(c, level, a, b, d_mu); break;
         case 3: restrict_mv(c, level, a, b); break;
-        default: prolong_mv(c, level, a, b, 0); break;
+        case 4: prolong_mv(c, level, a, b, 0); break;
+        default: mv_copy_kernel(c, a, b); break;
       }
     };
     run();
@@ -449,6 +455,80 @@ int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int
     mv_free(c, a64);
     mv_free(c, b);
     c->pool.release(d_mu);
+    return DDAMG_OK;
+  });
+}
+
+static int* knob_slot(ddamg_ctx* c, int knob) {
+  switch (knob) {
+    case DDAMG_KNOB_DSLASH_SITES_FP64: return &c->dslash_rs[P64];
+    case DDAMG_KNOB_DSLASH_SITES_FP32: return &c->dslash_rs[P32];
+    case DDAMG_KNOB_FP32_LINKS: return &c->fp32_links;
+    default: throw Error{DDAMG_EINVAL, "unknown knob"};
+  }
+}
+
+static bool knob_valid(int knob, int value) {
+  switch (knob) {
+    case DDAMG_KNOB_DSLASH_SITES_FP64: return dslash_rs_valid(P64, value);
+    case DDAMG_KNOB_DSLASH_SITES_FP32: return dslash_rs_valid(P32, value);
+    case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
+    default: return false;
+  }
+}
+
+int ddamg_set_tuning(ddamg_ctx* c, int knob, int value) {
+  return guarded([&]() -> int {
+    DD_CHECK(c, DDAMG_EINVAL, "null context");
+    int* slot = knob_slot(c, knob);
+    DD_CHECK(knob_valid(knob, value), DDAMG_EINVAL, "inadmissible knob value");
+    *slot = value;
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_get_tuning(ddamg_ctx* c, int knob, int* value) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && value, DDAMG_EINVAL, "null pointer");
+    *value = *knob_slot(c, knob);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && n_col >= 1, DDAMG_EINVAL, "bad arguments");
+    // FP64 stencil: sites per workgroup
+    {
+      double best = 1e30;
+      int bestv = c->dslash_rs[P64];
+      for (int v : {16, 32, 64}) {
+        c->dslash_rs[P64] = v;
+        double sec = 0;
+        const int st = ddamg_time_op(c, 0, 0, DDAMG_FP64, n_col, 10, &sec);
+        if (st != DDAMG_OK) return st;
+        if (sec < best) { best = sec; bestv = v; }
+      }
+      c->dslash_rs[P64] = bestv;
+    }
+    // FP32 stencil: link storage x sites per workgroup
+    {
+      double best = 1e30;
+      int bl = c->fp32_links, bs = c->dslash_rs[P32];
+      for (int lk : {0, 1})
+        for (int v : {32, 64, 128}) {
+          c->fp32_links = lk;
+          c->dslash_rs[P32] = v;
+          double sec = 0;
+          const int st = ddamg_time_op(c, 0, 0, DDAMG_FP32, n_col, 10, &sec);
+          if (st != DDAMG_OK) return st;
+          if (sec < best) { best = sec; bl = lk; bs = v; }
+        }
+      c->fp32_links = bl;
+      c->dslash_rs[P32] = bs;
+    }
+    if (values)
+      for (int k = 0; k < DDAMG_N_KNOBS; ++k) values[k] = *knob_slot(c, k);
     return DDAMG_OK;
   });
 }

@@ -162,6 +162,15 @@ __global__ void k_copy(const RS* __restrict__ a, RD* __restrict__ b, size_t n) {
     b[i] = (RD)a[i];
 }
 
+// Plain device copy kernel (reads and writes a.bytes()); calibrates the
+// memory-traffic counters against a kernel of known traffic.
+void mv_copy_kernel(ddamg_ctx* c, const MV& s, const MV& d) {
+  DD_CHECK(s.bytes() == d.bytes(), DDAMG_EINVAL, "copy: sizes");
+  const size_t n = s.bytes() / sizeof(double);
+  hipLaunchKernelGGL((k_copy<double, double>), grid_for(n), dim3(256), 0, c->stream, (const double*)s.p, (double*)d.p, n);
+  DD_HIP(hipGetLastError());
+}
+
 void mv_copy(ddamg_ctx* c, const MV& s, const MV& d) {
   DD_CHECK(s.nsites == d.nsites && s.dof == d.dof && s.ntiles == d.ntiles, DDAMG_EINVAL, "mv_copy: shape");
   if (s.prec == d.prec) {
@@ -331,7 +340,10 @@ struct PtrPack {
 };
 
 // Stage 1: partial[bM][j][col] = sum over this workgroup's rows of conj(V_j) w.
-// A workgroup is 256 lanes = 32 rows x T columns... with T = 8: lane = row*8 + t.
+// A workgroup is 256 lanes = 32 rows x 8 columns (lane = row*8 + t) and
+// handles one group of KB basis vectors (blockIdx.z): the KB accumulators
+// are statically indexed registers; w is re-read once per group.
+constexpr int KB = 8;
 template <typename R>
 __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* __restrict__ w, double* __restrict__ part,
                                                    size_t M, int ntiles, int ncol) {
@@ -339,24 +351,25 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
   constexpr int T = TTB;
   const int t = threadIdx.x % T, row = threadIdx.x / T;
   const int tile = blockIdx.y;
+  const int j0 = blockIdx.z * KB;
+  const int kk = min(KB, k - j0);
   const int nbM = gridDim.x;
   const size_t tile_reals = M * T * RW;
-  double accr[MAXK / 2], acci[MAXK / 2];
-  // two passes over k if k > MAXK/2
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  __shared__ double red[4][T][MAXK / 2][2];
-  for (int j0 = 0; j0 < k; j0 += MAXK / 2) {
-    const int kk = min(MAXK / 2, k - j0);
+  double accr[KB], acci[KB];
 #pragma unroll
-    for (int j = 0; j < MAXK / 2; ++j) { accr[j] = 0; acci[j] = 0; }
-    for (size_t m = (size_t)blockIdx.x * 32 + row; m < M; m += (size_t)nbM * 32) {
-      const size_t off = (size_t)tile * tile_reals + (m * T + t) * RW;
-      R wv[RW];
+  for (int j = 0; j < KB; ++j) { accr[j] = 0; acci[j] = 0; }
+  const R* vp[KB];
 #pragma unroll
-      for (int r = 0; r < RW; ++r) wv[r] = w[off + r];
-#pragma unroll 4
-      for (int j = 0; j < kk; ++j) {
-        const R* v = reinterpret_cast<const R*>(Vs.p[j0 + j]) + off;
+  for (int j = 0; j < KB; ++j) vp[j] = reinterpret_cast<const R*>(Vs.p[j0 + (j < kk ? j : 0)]);
+  for (size_t m = (size_t)blockIdx.x * 32 + row; m < M; m += (size_t)nbM * 32) {
+    const size_t off = (size_t)tile * tile_reals + (m * T + t) * RW;
+    R wv[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) wv[r] = w[off + r];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (j < kk) {
+        const R* v = vp[j] + off;
 #pragma unroll
         for (int r = 0; r < RW; r += 2) {
           const double vr = v[r], vi = v[r + 1], xr = wv[r], xi = wv[r + 1];
@@ -365,27 +378,30 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
         }
       }
     }
-    // reduce the 8 rows of this wave that share t
-    for (int j = 0; j < kk; ++j) {
-      double a = accr[j], b = acci[j];
+  }
+  // reduce the 8 rows of a wave that share t, then the 4 waves
+  __shared__ double red[4][T][KB][2];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
-      for (int off = T; off < 64; off <<= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-      }
-      if (lane < T) { red[wave][lane][j][0] = a; red[wave][lane][j][1] = b; }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kk * T; idx += 256) {
-      const int j = idx / T, tt = idx % T;
-      double a = 0, b = 0;
+  for (int j = 0; j < KB; ++j) {
+    double a = accr[j], b = acci[j];
 #pragma unroll
-      for (int w4 = 0; w4 < 4; ++w4) { a += red[w4][tt][j][0]; b += red[w4][tt][j][1]; }
-      const int col = tile * T + tt;
-      double* pp = part + (((size_t)blockIdx.x * k + j0 + j) * ncol + col) * 2;
-      pp[0] = a; pp[1] = b;
+    for (int off = T; off < 64; off <<= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
     }
-    __syncthreads();
+    if (lane < T) { red[wave][lane][j][0] = a; red[wave][lane][j][1] = b; }
+  }
+  __syncthreads();
+  if (threadIdx.x < kk * T) {
+    const int j = threadIdx.x / T, tt = threadIdx.x % T;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int w4 = 0; w4 < 4; ++w4) { a += red[w4][tt][j][0]; b += red[w4][tt][j][1]; }
+    const int col = tile * T + tt;
+    double* pp = part + (((size_t)blockIdx.x * k + j0 + j) * ncol + col) * 2;
+    pp[0] = a;
+    pp[1] = b;
   }
 }
 
@@ -410,11 +426,12 @@ void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out) 
     pk.p[j] = Vs[j].p;
   }
   const size_t M = (size_t)w.nchunk * w.nsites;
-  int nbM = (int)std::min<size_t>((M + 31) / 32, 2048 / (size_t)w.ntiles + 1);
+  const int ngroups = (k + KB - 1) / KB;
+  int nbM = (int)std::min<size_t>((M + 31) / 32, 4096 / ((size_t)w.ntiles * ngroups) + 1);
   if (nbM < 1) nbM = 1;
   const int ncol = w.ncol();
   double* part = scratch(c, (size_t)nbM * k * ncol * 2 * sizeof(double));
-  dim3 grid(nbM, w.ntiles);
+  dim3 grid(nbM, w.ntiles, ngroups);
   if (w.prec == P64)
     hipLaunchKernelGGL(k_multidot1<double>, grid, dim3(256), 0, c->stream, pk, k, w.as<double>(), part, M, w.ntiles,
                        ncol);

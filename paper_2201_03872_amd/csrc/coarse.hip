@@ -100,14 +100,14 @@ void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, 
 // One workgroup per (coarse site, tile); lane = (row, column).
 template <typename R>
 __global__ void k_restrict(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ P,
-                           const int* __restrict__ c_int2can, int Vf, int dof, int N, int gs, int Vc,
+                           const int* __restrict__ blk_of_coarse, int Vf, int dof, int N, int gs, int Vc,
                            size_t tile_f, size_t tile_c) {
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int a = wg % Vc, tile = wg / Vc;
   const int r = threadIdx.x / TC, t = threadIdx.x % TC;
   const int sig = r / N, j = r % N;
   const int h = dof / 2;
-  const int b = c_int2can[a];
+  const int b = blk_of_coarse[a];
   const R* xt = x + (size_t)tile * tile_f;
   const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
   cx<R> acc = {0, 0};
@@ -130,10 +130,10 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
   dim3 grid(gc.V * x.ntiles), blk(2 * N * TC);
   if (x.prec == P64)
     hipLaunchKernelGGL(k_restrict<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
-                       gc.d_int2can, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
+                       gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
   else
     hipLaunchKernelGGL(k_restrict<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
-                       gc.d_int2can, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
+                       gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
   DD_HIP(hipGetLastError());
 }
 
@@ -141,7 +141,7 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
 // y(x)[k] (+)= sum_j P[x][k][j] xc(a(x))[s(k)*N + j];  lane = (fine site, column)
 template <typename R>
 __global__ void __launch_bounds__(256) k_prolong(const R* __restrict__ xc, R* __restrict__ y, const R* __restrict__ P,
-                                                 const int* __restrict__ c_can2int, int Vf, int dof, int N, int gs,
+                                                 const int* __restrict__ coarse_of_blk, int Vf, int dof, int N, int gs,
                                                  int Vc, size_t tile_f, size_t tile_c, int accumulate, int nsb) {
   constexpr int SP = 256 / TC;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) k_prolong(const R* __restrict__ xc, R* __
   const int s = (wg % nsb) * SP + threadIdx.x / TC;
   const int t = threadIdx.x % TC;
   if (s >= Vf) return;
-  const int a = c_can2int[s / gs];
+  const int a = coarse_of_blk[s / gs];
   const R* ct = xc + (size_t)tile * tile_c;
   R* yt = y + (size_t)tile * tile_f;
   const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
@@ -174,10 +174,10 @@ void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulat
   dim3 grid(nsb * x.ntiles), blk(256);
   if (x.prec == P64)
     hipLaunchKernelGGL(k_prolong<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
-                       gc.d_can2int, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+                       gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
   else
     hipLaunchKernelGGL(k_prolong<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
-                       gc.d_can2int, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+                       gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
   DD_HIP(hipGetLastError());
 }
 

@@ -90,6 +90,9 @@ struct LevelGeom {
   int* d_nbr = nullptr;                // [8][V]; fine level: bit 31 = boundary sign
   int* d_int2can = nullptr;            // [V]
   int* d_can2int = nullptr;            // [V]
+  std::vector<int> blk_num, blk_lex;   // lexicographic block index <-> block number (Morton rank)
+  int* d_coarse_of_blk = nullptr;      // [V/gsize] internal site on the next level of each block
+  int* d_blk_of_coarse = nullptr;      // [V] block number on the previous level (coarse levels)
 };
 
 // Transfer between level l and l+1.
@@ -133,7 +136,8 @@ struct ddamg_ctx {
   ddamg::Transfer tr[2];
   ddamg::Coarse coarse[3];
   double* d_U64 = nullptr;    // [4 mu][9 chunk][V] double2
-  float* d_U32 = nullptr;     // [4 mu][3 chunk][V] float4, rows 0 and 1
+  float* d_U32 = nullptr;     // [4 mu][3 chunk][V] float4, rows 0 and 1 (no boundary sign)
+  float* d_U32f = nullptr;    // [4 mu][5 chunk][V] float4, full links, boundary sign folded in
   int* d_sap_list[2] = {nullptr, nullptr};   // block ids of each colour
   int n_sap[2] = {0, 0};
   double* d_scratch = nullptr;  // reduction partials
@@ -145,6 +149,9 @@ struct ddamg_ctx {
   ddamg::DevPool pool;
   ddamg::Stats st;
   void* work = nullptr;         // solver workspaces (solve.hip)
+  ddamg::MV tvk[2];             // smoothed (not orthonormalised) test vectors of each transition
+  int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
+  int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
 };
 
 namespace ddamg {
@@ -160,6 +167,7 @@ void mv_xpay(ddamg_ctx* c, const MV& x, const double* d_alpha, const MV& y);  //
 void mv_scale(ddamg_ctx* c, const double* d_alpha, const MV& x);  // x *= alpha_c (complex)
 void mv_sub(ddamg_ctx* c, const MV& a, const MV& b, const MV& out);   // out = a - b
 void mv_add(ddamg_ctx* c, const MV& x, const MV& y);                  // y += x
+void mv_copy_kernel(ddamg_ctx* c, const MV& s, const MV& d);          // plain copy kernel
 // per-column complex dots <V_j, w> for j < k, written to d_out[j*ncol + c] (complex)
 void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out);
 // w -= sum_j coef[j*ncol+c] V_j   (coef complex, device)
@@ -176,6 +184,7 @@ void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu);
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu);
 void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hop);
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV& work);
+bool dslash_rs_valid(int prec, int rs);
 
 // ---- coarse kernels (coarse.hip) ----
 void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);

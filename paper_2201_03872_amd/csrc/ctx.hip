@@ -3,6 +3,7 @@
 // FP32 2-row compressed links), SAP colour lists, counter-based random setup
 // vectors and the small device/host staging buffers.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "common.h"
@@ -20,8 +21,19 @@ static void coords(int i, const int* L, int* x) {
 }
 static int lex(const int* x, const int* L) { return x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3])); }
 
-// Internal order of a level: blocks of extent grp in lexicographic order,
-// sites lexicographic inside the block.
+// 4-d Morton key of block coordinates (bits interleaved, x lowest).
+static uint64_t morton4(const int* b) {
+  uint64_t k = 0;
+  for (int bit = 0; bit < 16; ++bit)
+    for (int m = 0; m < 4; ++m) k |= (uint64_t)((b[m] >> bit) & 1) << (4 * bit + m);
+  return k;
+}
+
+// Internal order of a level: the lattice is cut into blocks of extent grp;
+// blocks are numbered along a 4-d Morton (Z-order) curve, so that blocks
+// adjacent in any direction are usually close in memory (their spinors are
+// still in L2 when a neighbouring block is processed); sites are
+// lexicographic inside a block.
 void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, int dof, bool fine) {
   LevelGeom& g = c->geom[level];
   int B[4];
@@ -35,13 +47,27 @@ void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, in
   g.V = dims[0] * dims[1] * dims[2] * dims[3];
   g.gsize = grp[0] * grp[1] * grp[2] * grp[3];
   g.dof = dof;
+  const int nblk = B[0] * B[1] * B[2] * B[3];
+  std::vector<std::pair<uint64_t, int>> keys(nblk);
+  for (int L = 0; L < nblk; ++L) {
+    int b[4];
+    coords(L, B, b);
+    keys[L] = {morton4(b), L};
+  }
+  std::sort(keys.begin(), keys.end());
+  g.blk_num.assign(nblk, 0);
+  g.blk_lex.assign(nblk, 0);
+  for (int r = 0; r < nblk; ++r) {
+    g.blk_lex[r] = keys[r].second;
+    g.blk_num[keys[r].second] = r;
+  }
   g.int2can.assign(g.V, 0);
   g.can2int.assign(g.V, 0);
   for (int i = 0; i < g.V; ++i) {
     int x[4], b[4], l[4];
     coords(i, dims, x);
     for (int m = 0; m < 4; ++m) { b[m] = x[m] / grp[m]; l[m] = x[m] % grp[m]; }
-    const int s = lex(b, B) * g.gsize + lex(l, grp);
+    const int s = g.blk_num[lex(b, B)] * g.gsize + lex(l, grp);
     g.can2int[i] = s;
     g.int2can[s] = i;
   }
@@ -66,6 +92,21 @@ void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, in
   DD_HIP(hipMemcpy(g.d_nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
   DD_HIP(hipMemcpy(g.d_int2can, g.int2can.data(), (size_t)g.V * sizeof(int), hipMemcpyHostToDevice));
   DD_HIP(hipMemcpy(g.d_can2int, g.can2int.data(), (size_t)g.V * sizeof(int), hipMemcpyHostToDevice));
+  if (level > 0) {
+    // a coarse site is a block of the previous level: its lexicographic block
+    // index equals the coarse canonical site index
+    LevelGeom& gf = c->geom[level - 1];
+    std::vector<int> blk_of(g.V), coarse_of(g.V);
+    for (int a = 0; a < g.V; ++a) {
+      const int b = gf.blk_num[g.int2can[a]];
+      blk_of[a] = b;
+      coarse_of[b] = a;
+    }
+    g.d_blk_of_coarse = (int*)c->pool.alloc((size_t)g.V * sizeof(int));
+    gf.d_coarse_of_blk = (int*)c->pool.alloc((size_t)g.V * sizeof(int));
+    DD_HIP(hipMemcpy(g.d_blk_of_coarse, blk_of.data(), (size_t)g.V * sizeof(int), hipMemcpyHostToDevice));
+    DD_HIP(hipMemcpy(gf.d_coarse_of_blk, coarse_of.data(), (size_t)g.V * sizeof(int), hipMemcpyHostToDevice));
+  }
 }
 
 // SAP colour lists (chessboard over blocks).
@@ -79,11 +120,12 @@ void build_sap_lists(ddamg_ctx* c) {
   }
   std::vector<int> lists[2];
   const int nb = B[0] * B[1] * B[2] * B[3];
-  for (int b = 0; b < nb; ++b) {
+  for (int L = 0; L < nb; ++L) {
     int x[4];
-    coords(b, B, x);
-    lists[(x[0] + x[1] + x[2] + x[3]) % 2].push_back(b);
+    coords(L, B, x);
+    lists[(x[0] + x[1] + x[2] + x[3]) % 2].push_back(g.blk_num[L]);
   }
+  for (auto& l : lists) std::sort(l.begin(), l.end());
   for (int col = 0; col < 2; ++col) {
     c->n_sap[col] = (int)lists[col].size();
     c->d_sap_list[col] = (int*)c->pool.alloc(std::max<size_t>(1, lists[col].size()) * sizeof(int));
@@ -107,14 +149,21 @@ void upload_gauge(ddamg_ctx* c, const double* gauge, int on_device) {
   for (size_t i = 0; i < V * 4 * 9 * 2; ++i)
     DD_CHECK(std::isfinite(G[i]), DDAMG_EINVAL, "gauge field contains NaN/Inf");
   std::vector<double> u64(V * 4 * 9 * 2);
-  std::vector<float> u32(V * 4 * 3 * 4);
+  std::vector<float> u32(V * 4 * 3 * 4), u32f(V * 4 * 5 * 4, 0.0f);
+  const int Lt = g.dims[3];
+  const size_t V3 = (size_t)g.dims[0] * g.dims[1] * g.dims[2];
   for (size_t s = 0; s < V; ++s) {
     const size_t cs = g.int2can[s];
+    const bool tedge = (cs / V3) == (size_t)(Lt - 1);
     for (int mu = 0; mu < 4; ++mu) {
       const double* src = G + ((cs * 4 + mu) * 9) * 2;
+      // antiperiodic time: the t-link leaving the last time slice carries the sign
+      const double sg = (mu == 3 && tedge) ? -1.0 : 1.0;
       for (int k = 0; k < 9; ++k) {
-        u64[(((size_t)mu * 9 + k) * V + s) * 2] = src[2 * k];
-        u64[(((size_t)mu * 9 + k) * V + s) * 2 + 1] = src[2 * k + 1];
+        u64[(((size_t)mu * 9 + k) * V + s) * 2] = sg * src[2 * k];
+        u64[(((size_t)mu * 9 + k) * V + s) * 2 + 1] = sg * src[2 * k + 1];
+        u32f[(((size_t)mu * 5 + k / 2) * V + s) * 4 + (k % 2) * 2] = (float)(sg * src[2 * k]);
+        u32f[(((size_t)mu * 5 + k / 2) * V + s) * 4 + (k % 2) * 2 + 1] = (float)(sg * src[2 * k + 1]);
       }
       for (int q = 0; q < 3; ++q)
         for (int r = 0; r < 4; ++r) u32[(((size_t)mu * 3 + q) * V + s) * 4 + r] = (float)src[4 * q + r];
@@ -122,8 +171,10 @@ void upload_gauge(ddamg_ctx* c, const double* gauge, int on_device) {
   }
   c->d_U64 = (double*)c->pool.alloc(u64.size() * sizeof(double));
   c->d_U32 = (float*)c->pool.alloc(u32.size() * sizeof(float));
+  c->d_U32f = (float*)c->pool.alloc(u32f.size() * sizeof(float));
   DD_HIP(hipMemcpy(c->d_U64, u64.data(), u64.size() * sizeof(double), hipMemcpyHostToDevice));
   DD_HIP(hipMemcpy(c->d_U32, u32.data(), u32.size() * sizeof(float), hipMemcpyHostToDevice));
+  DD_HIP(hipMemcpy(c->d_U32f, u32f.data(), u32f.size() * sizeof(float), hipMemcpyHostToDevice));
 }
 
 // Counter-based Gaussian numbers: splitmix64 of (seed, stream, index), Box-Muller.

@@ -22,24 +22,45 @@ constexpr int TT = 8;                 // columns per tile
 constexpr int SPW = 256 / TT;         // sites per 256-lane workgroup
 
 // ---------------------------------------------------------------- links ---
-template <typename R, bool C2>
+// Link storage kinds:
+//   LK_D  FP64 full 3x3, [mu][9][V] double2, boundary sign folded into the
+//         t-links that cross the boundary;
+//   LK_F  FP32 full 3x3, [mu][5][V] float4 (last half chunk unused), sign folded;
+//   LK_C  FP32 2-row, [mu][3][V] float4, no sign (row 3 = conj(row1 x row2)
+//         cannot carry one): the sign comes from bit 31 of the neighbour table.
+constexpr int LK_D = 0, LK_F = 1, LK_C = 2;
+
+template <typename R>
+__device__ __forceinline__ void unpack_2row(float4 a, float4 b, float4 c, cx<R> (&u)[9]) {
+  u[0] = {(R)a.x, (R)a.y}; u[1] = {(R)a.z, (R)a.w}; u[2] = {(R)b.x, (R)b.y};
+  u[3] = {(R)b.z, (R)b.w}; u[4] = {(R)c.x, (R)c.y}; u[5] = {(R)c.z, (R)c.w};
+  u[6] = conj_(u[1] * u[5] - u[2] * u[4]);
+  u[7] = conj_(u[2] * u[3] - u[0] * u[5]);
+  u[8] = conj_(u[0] * u[4] - u[1] * u[3]);
+}
+
+template <typename R, int LK>
 __device__ __forceinline__ void load_link(const void* __restrict__ Uv, int mu, int s, int V, cx<R> (&u)[9]) {
-  if constexpr (!C2) {
+  if constexpr (LK == LK_D) {
     const double2* U = reinterpret_cast<const double2*>(Uv) + (size_t)mu * 9 * V;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       double2 c = U[(size_t)k * V + s];
       u[k] = {(R)c.x, (R)c.y};
     }
+  } else if constexpr (LK == LK_F) {
+    const float4* U = reinterpret_cast<const float4*>(Uv) + (size_t)mu * 5 * V;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float4 c = U[(size_t)k * V + s];
+      u[2 * k] = {(R)c.x, (R)c.y};
+      u[2 * k + 1] = {(R)c.z, (R)c.w};
+    }
+    float4 c = U[4 * (size_t)V + s];
+    u[8] = {(R)c.x, (R)c.y};
   } else {
     const float4* U = reinterpret_cast<const float4*>(Uv) + (size_t)mu * 3 * V;
-    float4 a = U[s], b = U[(size_t)V + s], c = U[2 * (size_t)V + s];
-    u[0] = {(R)a.x, (R)a.y}; u[1] = {(R)a.z, (R)a.w}; u[2] = {(R)b.x, (R)b.y};
-    u[3] = {(R)b.z, (R)b.w}; u[4] = {(R)c.x, (R)c.y}; u[5] = {(R)c.z, (R)c.w};
-    // row 2 = conj(row 0 x row 1)  (det U = 1)
-    u[6] = conj_(u[1] * u[5] - u[2] * u[4]);
-    u[7] = conj_(u[2] * u[3] - u[0] * u[5]);
-    u[8] = conj_(u[0] * u[4] - u[1] * u[3]);
+    unpack_2row(U[s], U[(size_t)V + s], U[2 * (size_t)V + s], u);
   }
 }
 
@@ -92,49 +113,91 @@ __device__ __forceinline__ void colour(const cx<R> (&u)[9], const cx<R> (&h)[6],
     }
 }
 
-// One hop term accumulated into acc (without the -1/2).  `ld(h, nb, p)` loads
-// the neighbour spinor of hop h (0..3 forward, 4..7 backward) and returns
-// false to drop the hop.
-template <int MU, bool FWD, typename R, bool C2, typename Loader>
-__device__ __forceinline__ void hop(cx<R> (&acc)[12], const void* __restrict__ U, const int* __restrict__ nbr,
-                                    int V, int s, Loader&& ld) {
-  constexpr int H = FWD ? MU : 4 + MU;
-  const int e = nbr[(size_t)H * V + s];
-  const int nb = e & 0x7fffffff;
-  cx<R> p[12];
-  if (!ld(H, nb, p)) return;
+// Accumulate one hop term into acc (without the -1/2) from a loaded
+// neighbour spinor p and link u; e is the neighbour-table entry (bit 31 =
+// boundary sign).
+template <int MU, bool FWD, bool TSIGN, typename R>
+__device__ __forceinline__ void hop_apply(cx<R> (&acc)[12], const cx<R> (&p)[12], const cx<R> (&u)[9], int e) {
   cx<R> h[6];
   project<MU, FWD>(p, h);
-  if (e < 0) {
+  if (TSIGN && e < 0) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) h[k] = (R)-1 * h[k];
   }
-  cx<R> u[9];
-  load_link<R, C2>(U, MU, FWD ? s : nb, V, u);
   cx<R> g[6];
   colour<FWD>(u, h, g);
   reconstruct<MU, FWD>(acc, g);
 }
 
+// One hop: the neighbour spinor and the link are requested together (the
+// neighbour index is already in a register), so each hop costs one memory
+// round trip.  `ld(h, nb, p)` loads the neighbour spinor of hop h (0..3
+// forward, 4..7 backward) and returns false to drop the hop.
+template <int MU, bool FWD, typename R, typename Loader, typename LinkLoader>
+__device__ __forceinline__ void hop_one(cx<R> (&acc)[12], const LinkLoader& ll, const int (&e)[8], int s,
+                                        Loader&& ld) {
+  constexpr int H = FWD ? MU : 4 + MU;
+  const int eh = e[H];
+  int nb = eh & 0x7fffffff;
+  int ls = FWD ? s : nb;
+  // opaque to the optimiser: address arithmetic stays inside this hop instead
+  // of being hoisted (64-bit addresses of all hops would not fit in registers)
+  asm volatile("" : "+v"(nb), "+v"(ls));
+  cx<R> p[12], u[9];
+  if (!ld(H, nb, p)) return;
+  ll(MU, ls, u);
+  hop_apply<MU, FWD, LinkLoader::table_sign>(acc, p, u, eh);
+}
+
+template <typename R, int LK>
+struct GlobalLinks {
+  static constexpr bool table_sign = (LK == LK_C);
+  const void* U;
+  int V;
+  __device__ __forceinline__ void operator()(int mu, int site, cx<R> (&u)[9]) const { load_link<R, LK>(U, mu, site, V, u); }
+};
+
+__device__ __forceinline__ void load_nbrs(const int* __restrict__ nbr, int V, int s, int (&e)[8]) {
+#pragma unroll
+  for (int h = 0; h < 8; ++h) e[h] = nbr[(size_t)h * V + s];
+}
+
 // The eight hops one after the other: a non-unrolled loop over a uniform
-// switch keeps only one neighbour spinor and one link live at a time.
-template <typename R, bool C2, typename Loader>
-__device__ __forceinline__ void all_hops(cx<R> (&acc)[12], const void* U, const int* nbr, int V, int s, Loader&& ld) {
+// switch keeps one neighbour spinor and one link live at a time.
+template <typename R, int LK, typename Loader, typename LinkLoader>
+__device__ __forceinline__ void all_hops_e(cx<R> (&acc)[12], const LinkLoader& U, const int (&e)[8], int s,
+                                           Loader&& ld) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
 #pragma unroll 1
   for (int h = 0; h < 8; ++h) {
+    // keeps the compiler from hoisting the loads of later hops (which would
+    // hold all eight neighbour spinors in registers at once)
+    asm volatile("" ::: "memory");
     switch (h) {
-      case 0: hop<0, true, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 1: hop<1, true, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 2: hop<2, true, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 3: hop<3, true, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 4: hop<0, false, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 5: hop<1, false, R, C2>(acc, U, nbr, V, s, ld); break;
-      case 6: hop<2, false, R, C2>(acc, U, nbr, V, s, ld); break;
-      default: hop<3, false, R, C2>(acc, U, nbr, V, s, ld); break;
+      case 0: hop_one<0, true, R>(acc, U, e, s, ld); break;
+      case 1: hop_one<1, true, R>(acc, U, e, s, ld); break;
+      case 2: hop_one<2, true, R>(acc, U, e, s, ld); break;
+      case 3: hop_one<3, true, R>(acc, U, e, s, ld); break;
+      case 4: hop_one<0, false, R>(acc, U, e, s, ld); break;
+      case 5: hop_one<1, false, R>(acc, U, e, s, ld); break;
+      case 6: hop_one<2, false, R>(acc, U, e, s, ld); break;
+      default: hop_one<3, false, R>(acc, U, e, s, ld); break;
     }
   }
+}
+
+template <typename R, int LK, typename Loader, typename LinkLoader>
+__device__ __forceinline__ void all_hops_ll(cx<R> (&acc)[12], const LinkLoader& U, const int* nbr, int V, int s,
+                                            Loader&& ld) {
+  int e[8];
+  load_nbrs(nbr, V, s, e);
+  all_hops_e<R, LK>(acc, U, e, s, ld);
+}
+
+template <typename R, int LK, typename Loader>
+__device__ __forceinline__ void all_hops(cx<R> (&acc)[12], const void* U, const int* nbr, int V, int s, Loader&& ld) {
+  all_hops_ll<R, LK>(acc, GlobalLinks<R, LK>{U, V}, nbr, V, s, ld);
 }
 
 // out = diag x + i mu gamma5 x - 1/2 acc
@@ -150,7 +213,7 @@ __device__ __forceinline__ void site_diag(cx<R> (&out)[12], const cx<R> (&x)[12]
 
 // ------------------------------------------------------------ dslash ---
 // MODE 0: y = D x ; MODE 1: y = b - D x
-template <typename R, bool C2, int MODE>
+template <typename R, int LK, int MODE>
 __global__ void __launch_bounds__(256) k_dslash(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ b,
                                                 const void* __restrict__ U, const int* __restrict__ nbr,
                                                 const double* __restrict__ mu, int V, size_t tile_reals, R diag,
@@ -166,9 +229,64 @@ __global__ void __launch_bounds__(256) k_dslash(const R* __restrict__ x, R* __re
     return true;
   };
   cx<R> acc[12];
-  all_hops<R, C2>(acc, U, nbr, V, s, ld);
+  all_hops<R, LK>(acc, U, nbr, V, s, ld);
   cx<R> xs[12], out[12];
   load_cx<R, 12>(xt, V, TT, s, t, xs);
+  site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
+  if constexpr (MODE == 1) {
+    cx<R> bs[12];
+    load_cx<R, 12>(b + (size_t)tile * tile_reals, V, TT, s, t, bs);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = bs[k] - out[k];
+  }
+  store_cx<R, 12>(y + (size_t)tile * tile_reals, V, TT, s, t, out);
+}
+
+// Same operator with LDS staging: a workgroup owns RS consecutive sites of the
+// internal (block-major) order for one column tile, copies their spinors
+// into LDS once, and reads every neighbour that falls inside its range from
+// LDS; only the neighbours outside the range go through L1/L2.  A site's
+// spinor is then fetched from the cache hierarchy about 3.5 times instead of
+// 9, which is what lets the kernel run at HBM speed rather than L2 speed.
+template <typename R, int LK, int MODE, int RS>
+__global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x, R* __restrict__ y,
+                                                        const R* __restrict__ b, const void* __restrict__ U,
+                                                        const int* __restrict__ nbr, const double* __restrict__ mu,
+                                                        int V, size_t tile_reals, R diag, int nsb) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW, NCH = 24 / RW;
+  __shared__ C lds[NCH * RS * TT];
+  const int t = threadIdx.x % TT, sl = threadIdx.x / TT;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = wg / nsb;
+  const int r0 = (wg % nsb) * RS;
+  const int s = r0 + sl;
+  const bool active = s < V;
+  const R* xt = x + (size_t)tile * tile_reals;
+  const C* xc = reinterpret_cast<const C*>(xt);
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) lds[(k * RS + sl) * TT + t] = xc[((size_t)k * V + s) * TT + t];
+  }
+  __syncthreads();
+  if (!active) return;
+  auto from_lds = [&](int l, cx<R>(&p)[12]) {
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      const C v = lds[(k * RS + l) * TT + t];
+      if constexpr (RW == 2) p[k] = {v.x, v.y};
+      else { p[2 * k] = {v.x, v.y}; p[2 * k + 1] = {v.z, v.w}; }
+    }
+  };
+  auto ld = [&](int, int nb, cx<R>(&p)[12]) {
+    const unsigned l = (unsigned)(nb - r0);
+    if (l < (unsigned)RS) from_lds((int)l, p);
+    else load_cx<R, 12>(xt, V, TT, nb, t, p);
+    return true;
+  };
+  cx<R> acc[12], out[12], xs[12];
+  all_hops<R, LK>(acc, U, nbr, V, s, ld);
+  from_lds(sl, xs);
   site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
   if constexpr (MODE == 1) {
     cx<R> bs[12];
@@ -204,7 +322,7 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
     load_cx<R, 12>(xt, V, TT, nb, t, p);
     return true;
   };
-  all_hops<R, false>(acc, U, nbr, V, s, ld);
+  all_hops<R, LK_D>(acc, U, nbr, V, s, ld);
   cx<R> out[12];
   cx<R> xs[12];
   load_cx<R, 12>(xt, V, TT, s, t, xs);
@@ -215,6 +333,25 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
 }
 
 // ---------------------------------------------------------------- SAP ---
+// Links of the in-block MR steps: FP32 2-row links staged in LDS (sign from
+// the neighbour table), or FP64 full links from global memory.
+template <typename R, int LK, int BS>
+struct SapLinks {
+  static constexpr bool table_sign = (LK == LK_C);
+  const float4* ulds;
+  const void* U;
+  int V;
+  int base;
+  __device__ __forceinline__ void operator()(int mu, int site, cx<R> (&u)[9]) const {
+    if constexpr (LK == LK_C) {
+      const int l = site - base;
+      unpack_2row(ulds[(mu * 3) * BS + l], ulds[(mu * 3 + 1) * BS + l], ulds[(mu * 3 + 2) * BS + l], u);
+    } else {
+      load_link<R, LK>(U, mu, site, V, u);
+    }
+  }
+};
+
 // One colour half-sweep of red-black SAP (paper section 2): every workgroup
 // owns one block of that colour and K columns of a tile.
 //   1. r = f - D x on the block's sites (full stencil, neighbours in global memory);
@@ -224,7 +361,7 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
 //   3. x += delta on the block.
 // Blocks of one colour never neighbour each other, so the in-place update of
 // x is race free.
-template <typename R, bool C2, int K, int BS>
+template <typename R, int LK, int K, int BS>
 __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
@@ -238,8 +375,11 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   constexpr int WL = NT >= 64 ? 64 : NT;    // lanes per wave actually used
   __shared__ C lds[NCH * BS * K];
   __shared__ R red[NW][K][3];
+  __shared__ float4 ulds[LK == LK_C ? 12 * BS : 1];
 
-  int wg = blockIdx.x;
+  // the NSUB workgroups of one block read the same 128-byte rows: keep them
+  // on one XCD (shared L2) by numbering workgroups XCD-contiguously
+  int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int sub = wg % NSUB;
   wg /= NSUB;
   const int tile = wg % ntiles;
@@ -253,6 +393,8 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   const R m = (R)mu[tile * TT + t];
 
   // 1. block residual
+  int e8[8];
+  load_nbrs(nbr, V, s, e8);
   cx<R> rho[12], dl[12], q[12];
   {
     auto ldg = [&](int, int nb, cx<R>(&p)[12]) {
@@ -260,13 +402,24 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
       return true;
     };
     cx<R> acc[12], xs[12], fs[12];
-    all_hops<R, C2>(acc, U, nbr, V, s, ldg);
+    all_hops_e<R, LK>(acc, GlobalLinks<R, LK>{U, V}, e8, s, ldg);
     load_cx<R, 12>(xt, V, TT, s, t, xs);
     load_cx<R, 12>(ft, V, TT, s, t, fs);
     site_diag(q, xs, acc, diag, m);
 #pragma unroll
     for (int k = 0; k < 12; ++k) { rho[k] = fs[k] - q[k]; dl[k] = {0, 0}; }
   }
+
+  // the block's forward links (2-row FP32) staged in LDS for the MR steps;
+  // the backward link of an in-block hop is the forward link of an in-block site
+  if constexpr (LK == LK_C) {
+    const float4* Ug = reinterpret_cast<const float4*>(U);
+    for (int i = threadIdx.x; i < 12 * BS; i += NT) {
+      const int mu_q = i / BS, l = i % BS;
+      ulds[i] = Ug[(size_t)mu_q * V + blk * BS + l];
+    }
+  }
+  const SapLinks<R, LK, BS> lll{ulds, U, V, blk * BS};
 
   // 2. block MR
   auto ldl = [&](int, int nb, cx<R>(&p)[12]) {
@@ -297,7 +450,7 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
     }
     __syncthreads();
     cx<R> acc[12];
-    all_hops<R, C2>(acc, U, nbr, V, s, ldl);
+    all_hops_e<R, LK>(acc, lll, e8, s, ldl);
     site_diag(q, rho, acc, diag, m);
     R nr = 0, ni = 0, dd = 0;
 #pragma unroll
@@ -335,32 +488,55 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
 // ------------------------------------------------------------ wrappers ---
 static inline int nsb_of(int V) { return (V + SPW - 1) / SPW; }
 
-void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu) {
+// Sites per workgroup of the LDS-staged stencil: a tile-shape knob chosen by
+// the autotuner (more sites = more neighbours served from LDS, fewer
+// workgroups resident per CU).
+template <typename R, int LK, int MODE, int RS>
+static void launch_rs(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu, const void* U) {
   const int V = c->geom[0].V;
-  const int nsb = nsb_of(V);
-  dim3 grid(nsb * x.ntiles), blk(256);
-  if (x.prec == P64)
-    hipLaunchKernelGGL((k_dslash<double, false, 0>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
-                       nullptr, c->d_U64, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), c->diag, nsb);
-  else
-    hipLaunchKernelGGL((k_dslash<float, true, 0>), grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), nullptr,
-                       c->d_U32, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), (float)c->diag, nsb);
+  const int nsb = (V + RS - 1) / RS;
+  hipLaunchKernelGGL((k_dslash_lds<R, LK, MODE, RS>), dim3(nsb * x.ntiles), dim3(RS * TT), 0, c->stream, x.as<R>(),
+                     y.as<R>(), b ? b->as<R>() : nullptr, U, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), (R)c->diag,
+                     nsb);
+}
+
+bool dslash_rs_valid(int prec, int rs) {
+  if (prec == P64) return rs == 16 || rs == 32 || rs == 64;
+  return rs == 32 || rs == 64 || rs == 128;
+}
+
+template <int MODE, int LK>
+static void launch_f32(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu, const void* U) {
+  switch (c->dslash_rs[P32]) {
+    case 32: launch_rs<float, LK, MODE, 32>(c, x, y, b, d_mu, U); break;
+    case 64: launch_rs<float, LK, MODE, 64>(c, x, y, b, d_mu, U); break;
+    default: launch_rs<float, LK, MODE, 128>(c, x, y, b, d_mu, U); break;
+  }
+}
+
+template <int MODE>
+static void launch_dslash(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu) {
+  if (x.prec == P64) {
+    switch (c->dslash_rs[P64]) {
+      case 16: launch_rs<double, LK_D, MODE, 16>(c, x, y, b, d_mu, c->d_U64); break;
+      case 32: launch_rs<double, LK_D, MODE, 32>(c, x, y, b, d_mu, c->d_U64); break;
+      default: launch_rs<double, LK_D, MODE, 64>(c, x, y, b, d_mu, c->d_U64); break;
+    }
+  } else if (c->fp32_links == 0) {
+    launch_f32<MODE, LK_F>(c, x, y, b, d_mu, c->d_U32f);
+  } else {
+    launch_f32<MODE, LK_C>(c, x, y, b, d_mu, c->d_U32);
+  }
   DD_HIP(hipGetLastError());
   c->st.fine_ops++;
 }
 
+void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu) {
+  launch_dslash<0>(c, x, y, nullptr, d_mu);
+}
+
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu) {
-  const int V = c->geom[0].V;
-  const int nsb = nsb_of(V);
-  dim3 grid(nsb * x.ntiles), blk(256);
-  if (x.prec == P64)
-    hipLaunchKernelGGL((k_dslash<double, false, 1>), grid, blk, 0, c->stream, x.as<double>(), r.as<double>(),
-                       b.as<double>(), c->d_U64, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), c->diag, nsb);
-  else
-    hipLaunchKernelGGL((k_dslash<float, true, 1>), grid, blk, 0, c->stream, x.as<float>(), r.as<float>(),
-                       b.as<float>(), c->d_U32, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), (float)c->diag, nsb);
-  DD_HIP(hipGetLastError());
-  c->st.fine_ops++;
+  launch_dslash<1>(c, x, r, &b, d_mu);
 }
 
 void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
@@ -373,12 +549,12 @@ void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
   DD_HIP(hipGetLastError());
 }
 
-template <typename R, bool C2, int K, int BS>
+template <typename R, int LK, int K, int BS>
 static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour) {
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
-  hipLaunchKernelGGL((k_sap_half<R, C2, K, BS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
-                     C2 ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
+  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
+                     LK == LK_C ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
                      c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
                      c->p.sap_mr_iters);
   DD_HIP(hipGetLastError());
@@ -390,12 +566,12 @@ void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const
   for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour) {
       if (x.prec == P64) {
-        if (BS == 256) launch_sap<double, false, 1, 256>(c, f, x, d_mu, colour);
-        else if (BS == 16) launch_sap<double, false, 4, 16>(c, f, x, d_mu, colour);
+        if (BS == 256) launch_sap<double, LK_D, 1, 256>(c, f, x, d_mu, colour);
+        else if (BS == 16) launch_sap<double, LK_D, 4, 16>(c, f, x, d_mu, colour);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       } else {
-        if (BS == 256) launch_sap<float, true, 2, 256>(c, f, x, d_mu, colour);
-        else if (BS == 16) launch_sap<float, true, 8, 16>(c, f, x, d_mu, colour);
+        if (BS == 256) launch_sap<float, LK_C, 2, 256>(c, f, x, d_mu, colour);
+        else if (BS == 16) launch_sap<float, LK_C, 8, 16>(c, f, x, d_mu, colour);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       }
     }

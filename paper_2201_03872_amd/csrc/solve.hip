@@ -261,6 +261,20 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
         }
         if (!done[i]) alld = false;
       }
+      if (c->p.verbose && level == 0) {
+        double mx = 0;
+        int nact = 0;
+        for (int i = 0; i < ncol; ++i)
+          if (bn[i] > 0) {
+            mx = std::max(mx, est[i] / bn[i]);
+            nact += !done[i];
+          }
+        std::fprintf(stderr, "[ddamg] outer %d: max rel. residual estimate %.3e, %d columns active, "
+                     "middle calls %lld (avg %.1f it), bottom calls %lld (avg %.1f it)\n", total, mx, nact,
+                     c->st.middle_calls, c->st.middle_calls ? (double)c->st.middle_iters / c->st.middle_calls : 0.0,
+                     c->st.bottom_calls, c->st.bottom_calls ? (double)c->st.bottom_iters / c->st.bottom_calls : 0.0);
+        std::fflush(stderr);
+      }
       if (!fixed && alld) break;
     }
     // per-column least squares and the update x += basis * y
@@ -336,8 +350,8 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
   KrylovOut ko;
   const bool bottom = (l + 2 == c->nlev);
   if (bottom) {
-    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1),
-           std::min(c->p.bottom_maxit, KMAX - 1), nullptr, prec, false, &ko);
+    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
+           nullptr, prec, false, &ko);
     c->st.bottom_calls++;
     int mx = 0;
     for (int i : ko.iters) mx = std::max(mx, i);
@@ -434,7 +448,21 @@ void setup_transition(ddamg_ctx* c, int l, const double* tv_init_host) {
   DD_HIP(hipMemcpy(d_mu, hmu.data(), hmu.size() * sizeof(double), hipMemcpyHostToDevice));
   double* d_n2 = (double*)c->pool.alloc(tv.ncol() * sizeof(double));
   for (int r = 0; r < c->p.setup_rounds; ++r) {
-    if (l == 0) {
+    if (l == 0 && c->p.setup_fine_iters > 0) {
+      // inverse iteration: k steps of SAP-preconditioned FGMRES on D x = tv
+      const int sp = c->p.precision == DDAMG_MIXED ? P32 : P64;
+      LW& ws = lw(c, 0, sp, tv.ntiles);
+      MV vin = get(c, ws.rho, 0, sp, ws.cap, tv.ntiles);
+      Precond pc = [&](const MV& v, const MV& z) {
+        if (sp != v.prec) {
+          mv_copy(c, v, vin);
+          sap_apply(c, vin, z, d_mu, z);
+        } else {
+          sap_apply(c, v, z, d_mu, z);
+        }
+      };
+      krylov(c, 0, d_mu, tv, tmp, true, 0.0, c->p.setup_fine_iters, c->p.setup_fine_iters, &pc, sp, true, nullptr);
+    } else if (l == 0) {
       sap_apply(c, tv, tmp, d_mu, tmp);
     } else {
       krylov(c, l, d_mu, tv, tmp, true, 0.0, c->p.setup_coarse_iters, c->p.setup_coarse_iters, nullptr, P64, true,
@@ -447,12 +475,39 @@ void setup_transition(ddamg_ctx* c, int l, const double* tv_init_host) {
   build_transition(c, l, tv);
   c->pool.release(d_mu);
   c->pool.release(d_n2);
-  mv_free(c, tv);
+  mv_free(c, c->tvk[l]);
+  c->tvk[l] = tv;
   mv_free(c, tmp);
+}
+
+// Bootstrap rounds: the fine test vectors are replaced by the multigrid cycle
+// applied to them (an approximate inverse iteration with the current
+// hierarchy), normalised, and every transition is rebuilt.
+void bootstrap(ddamg_ctx* c) {
+  MV& tv = c->tvk[0];
+  const int N = c->tr[0].N;
+  MV z = mv_alloc(c, 0, P64, N);
+  std::vector<double> hmu(tv.ncol(), 0.0);
+  for (int i = 0; i < N; ++i) hmu[i] = c->p.mu_setup;
+  double* d_mu = (double*)c->pool.alloc(hmu.size() * sizeof(double));
+  DD_HIP(hipMemcpy(d_mu, hmu.data(), hmu.size() * sizeof(double), hipMemcpyHostToDevice));
+  double* d_n2 = (double*)c->pool.alloc(tv.ncol() * sizeof(double));
+  for (int r = 0; r < c->p.setup_boot; ++r) {
+    mg_cycle(c, 0, d_mu, tv, z);
+    mv_norm2(c, z, d_n2);
+    mv_normalize(c, z, d_n2);
+    mv_copy(c, z, tv);
+    build_transition(c, 0, tv);
+    for (int l = 1; l + 1 < c->nlev; ++l) setup_transition(c, l, nullptr);
+  }
+  c->pool.release(d_mu);
+  c->pool.release(d_n2);
+  mv_free(c, z);
 }
 
 void build_hierarchy(ddamg_ctx* c, const double* const* tv_init) {
   for (int l = 0; l + 1 < c->nlev; ++l) setup_transition(c, l, tv_init ? tv_init[l] : nullptr);
+  if (c->nlev > 1 && c->p.setup_boot > 0) bootstrap(c);
 }
 
 // Rebuild from host test vectors (canonical layout) of transition l.
