@@ -217,6 +217,34 @@ int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
  * stored by the caller and restored with ddamg_set_tuning. */
 int ddamg_autotune(ddamg_ctx* h, int n_col, int* values);
 
+/* ---- learned smoother (gauge-covariant parallel-transport convolution net) ----
+ * Two linear layers, 1 -> 2 -> 1 spinor channels:
+ *   out_o(x) = sum_i sum_p W[p][o][i] (T_p in_i)(x),  p = 0 (identity), 1..4 = +mu, 5..8 = -mu,
+ *   T_{+mu} f(x) = U_mu(x) f(x+mu),  T_{-mu} f(x) = U_mu(x-mu)^dag f(x-mu) (antiperiodic sign included),
+ * each W[p][o][i] a complex 4x4 spin matrix (gauge covariant by construction).
+ * Weights (host, double complex): layer 1 [9][2][1][4][4], layer 2 [9][1][2][4][4];
+ * on the device they are stored in BF16 and used with FP32 accumulation.
+ * With params.smoother = DDAMG_SMOOTHER_LEARNED the network replaces the fine
+ * SAP smoother in the preconditioner; whenever it does not reduce the residual
+ * of every column (||v - D f(v)|| >= ||v||) SAP is used for that call instead
+ * (counted in ddamg_stats.learned_fallbacks). */
+int ddamg_smoother_set_weights(ddamg_ctx* h, const double* w1, const double* w2);
+int ddamg_smoother_get_weights(ddamg_ctx* h, double* w1, double* w2);
+/* y = f(x) for n_col fine vectors (device, canonical layout). */
+int ddamg_smoother_apply(ddamg_ctx* h, int n_col, const double* x, double* y);
+/* One layer (1 or 2), or its adjoint when adjoint != 0, on FP32 internal data:
+ * in: [c_in][n_col][V][4][3] complex, out: [c_out][n_col][V][4][3] (device). */
+int ddamg_ptc_layer(ddamg_ctx* h, int layer, int adjoint, int n_col, const double* in, double* out);
+/* Weight gradient of one layer: g[p][o][i][s][t] = 2 sum_{x,c,col} gout_o[s][c] conj((T_p in_i)[t][c])
+ * (= dL/dRe W + i dL/dIm W for gout = dL/d conj(out)); in, gout device, g host. */
+int ddamg_ptc_weight_grad(ddamg_ctx* h, int layer, int n_col, const double* in, const double* gout, double* g);
+/* Train the current weights with Adam on the GPU kernels: every step draws
+ * `batch` Gaussian errors e, forms r = D(mu_c) e (mu_c cycles through mus),
+ * scales both by 1/||r||, and descends the mean of ||f(r) - e||^2 / ||e||^2.
+ * loss_history (host, `steps` entries) may be NULL. */
+int ddamg_train_smoother(ddamg_ctx* h, const double* mus, int n_mu, int steps, int batch, double lr,
+                         uint64_t seed, double* loss_history);
+
 void ddamg_destroy(ddamg_ctx* h);
 const char* ddamg_strerror(int status);
 /* Message of the last error raised on the calling thread ("" if none). */

@@ -19,3 +19,4 @@ from .multigrid import (Blocking, FineLevel, CoarseOp, build_prolongator, restri
                         galerkin, sap, mr_smoother, block_mr)
 from .krylov import gmres, fgmres, block_gmres, col_norm, col_dot
 from .solver import MGParams, OracleMG
+from . import ptc

@@ -116,6 +116,13 @@ def load():
         "ddamg_set_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "ddamg_get_tuning": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "ddamg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip]),
+        "ddamg_smoother_set_weights": (ctypes.c_int, [vp, vp, vp]),
+        "ddamg_smoother_get_weights": (ctypes.c_int, [vp, vp, vp]),
+        "ddamg_smoother_apply": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),
+        "ddamg_ptc_layer": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
+        "ddamg_ptc_weight_grad": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
+        "ddamg_train_smoother": (ctypes.c_int, [vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                ctypes.c_uint64, dp]),
         "ddamg_destroy": (None, [vp]),
         "ddamg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ddamg_last_error": (ctypes.c_char_p, []),
@@ -273,6 +280,44 @@ class Context:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2}
+
+    # ---- learned smoother ----
+    def set_smoother_weights(self, w1, w2):
+        a = np.ascontiguousarray(np.asarray(w1, dtype=np.complex128).reshape(9, 2, 1, 4, 4))
+        b = np.ascontiguousarray(np.asarray(w2, dtype=np.complex128).reshape(9, 1, 2, 4, 4))
+        _check(load().ddamg_smoother_set_weights(self.h, a.ctypes.data, b.ctypes.data))
+
+    def smoother_weights(self):
+        a = np.empty((9, 2, 1, 4, 4), dtype=np.complex128)
+        b = np.empty((9, 1, 2, 4, 4), dtype=np.complex128)
+        _check(load().ddamg_smoother_get_weights(self.h, a.ctypes.data, b.ctypes.data))
+        return a, b
+
+    def smoother_apply(self, x):
+        y = self._vec(0, x.shape[0])
+        _check(load().ddamg_smoother_apply(self.h, x.shape[0], _dptr(x), _dptr(y)))
+        return y
+
+    def ptc_layer(self, layer, adjoint, x):
+        """x: [c_in][n_col][V][4][3] complex128 CUDA tensor."""
+        import torch
+        cout = {(1, 0): 2, (2, 0): 1, (1, 1): 1, (2, 1): 2}[(layer, int(bool(adjoint)))]
+        out = torch.empty((cout,) + tuple(x.shape[1:]), dtype=torch.complex128, device=self.device)
+        _check(load().ddamg_ptc_layer(self.h, layer, int(bool(adjoint)), x.shape[1], _dptr(x), _dptr(out)))
+        return out
+
+    def ptc_weight_grad(self, layer, x, gout):
+        cin, cout = (1, 2) if layer == 1 else (2, 1)
+        g = np.empty((9, cout, cin, 4, 4), dtype=np.complex128)
+        _check(load().ddamg_ptc_weight_grad(self.h, layer, x.shape[1], _dptr(x), _dptr(gout), g.ctypes.data))
+        return g
+
+    def train_smoother(self, mus, steps, batch, lr, seed=1):
+        m, mp = _mu(mus)
+        hist = np.zeros(steps)
+        _check(load().ddamg_train_smoother(self.h, mp, len(m), int(steps), int(batch), float(lr), int(seed),
+                                           hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return hist
 
     def set_tuning(self, knob, value):
         _check(load().ddamg_set_tuning(self.h, self.KNOBS.get(knob, knob), int(value)))

@@ -128,7 +128,7 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->setup_coarse_iters >= 1 && p->setup_coarse_iters <= 63, DDAMG_EINVAL, "setup_coarse_iters in [1, 63]");
   DD_CHECK(p->tol > 0 && p->r_m > 0 && p->r_b > 0, DDAMG_EINVAL, "tolerances must be positive");
   DD_CHECK(p->precision == DDAMG_PLAIN_FP64 || p->precision == DDAMG_MIXED, DDAMG_EINVAL, "precision mode");
-  DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP, DDAMG_EINVAL, "smoother: only SAP is available");
+  DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP || p->smoother == DDAMG_SMOOTHER_LEARNED, DDAMG_EINVAL, "smoother");
 }
 
 int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
@@ -177,6 +177,7 @@ void ddamg_destroy(ddamg_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   free_work(c);
+  free_ptc(c);
   c->pool.clear();
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   delete c;
@@ -529,6 +530,92 @@ int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
     }
     if (values)
       for (int k = 0; k < DDAMG_N_KNOBS; ++k) values[k] = *knob_slot(c, k);
+    return DDAMG_OK;
+  });
+}
+
+// ---------------------------------------------------------- learned smoother ---
+int ddamg_smoother_set_weights(ddamg_ctx* c, const double* w1, const double* w2) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && w1 && w2, DDAMG_EINVAL, "null pointer");
+    ptc_set_weights(c, w1, w2);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_smoother_get_weights(ddamg_ctx* c, double* w1, double* w2) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && w1 && w2, DDAMG_EINVAL, "null pointer");
+    ptc_get_weights(c, w1, w2);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_smoother_apply(ddamg_ctx* c, int n_col, const double* x, double* y) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && x && y && n_col >= 1, DDAMG_EINVAL, "bad arguments");
+    MV a = mv_alloc(c, 0, P32, n_col), b = mv_alloc(c, 0, P32, n_col);
+    MV tmp[3] = {mv_alloc(c, 0, P32, n_col), mv_alloc(c, 0, P32, n_col), mv_alloc(c, 0, P32, n_col)};
+    to_internal(c, 0, x, n_col, a);
+    ptc_smooth(c, a, b, nullptr, tmp, false);
+    from_internal(c, 0, b, n_col, y);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    MV* all[] = {&a, &b, &tmp[0], &tmp[1], &tmp[2]};
+    for (MV* m : all) mv_free(c, *m);
+    return DDAMG_OK;
+  });
+}
+
+static const int PTC_CIN[2] = {1, 2}, PTC_COUT[2] = {2, 1};
+
+int ddamg_ptc_layer(ddamg_ctx* c, int layer, int adjoint, int n_col, const double* in, double* out) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && in && out && n_col >= 1 && (layer == 1 || layer == 2), DDAMG_EINVAL, "bad arguments");
+    const int l = layer - 1;
+    const int cin = adjoint ? PTC_COUT[l] : PTC_CIN[l], cout = adjoint ? PTC_CIN[l] : PTC_COUT[l];
+    const size_t chan = (size_t)n_col * c->geom[0].V * 12 * 2;
+    MV a[2], b[2];
+    for (int i = 0; i < cin; ++i) {
+      a[i] = mv_alloc(c, 0, P32, n_col);
+      to_internal(c, 0, in + i * chan, n_col, a[i]);
+    }
+    for (int o = 0; o < cout; ++o) b[o] = mv_alloc(c, 0, P32, n_col);
+    ptc_layer(c, l, adjoint != 0, a, b);
+    for (int o = 0; o < cout; ++o) from_internal(c, 0, b[o], n_col, out + o * chan);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < cin; ++i) mv_free(c, a[i]);
+    for (int o = 0; o < cout; ++o) mv_free(c, b[o]);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_ptc_weight_grad(ddamg_ctx* c, int layer, int n_col, const double* in, const double* gout, double* g) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && in && gout && g && n_col >= 1 && (layer == 1 || layer == 2), DDAMG_EINVAL, "bad arguments");
+    const int l = layer - 1;
+    const int cin = PTC_CIN[l], cout = PTC_COUT[l];
+    const size_t chan = (size_t)n_col * c->geom[0].V * 12 * 2;
+    MV a[2], b[2];
+    for (int i = 0; i < cin; ++i) {
+      a[i] = mv_alloc(c, 0, P32, n_col);
+      to_internal(c, 0, in + i * chan, n_col, a[i]);
+    }
+    for (int o = 0; o < 2; ++o) {
+      b[o] = mv_alloc(c, 0, P32, n_col);
+      if (o < cout) to_internal(c, 0, gout + o * chan, n_col, b[o]);
+    }
+    ptc_wgrad(c, l, a, b, g);
+    for (int i = 0; i < cin; ++i) mv_free(c, a[i]);
+    for (int o = 0; o < 2; ++o) mv_free(c, b[o]);
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_train_smoother(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, uint64_t seed,
+                         double* loss_history) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mus && n_mu >= 1 && steps >= 1 && batch >= 1 && lr > 0, DDAMG_EINVAL, "bad arguments");
+    ptc_train(c, mus, n_mu, steps, batch, lr, seed, loss_history);
     return DDAMG_OK;
   });
 }

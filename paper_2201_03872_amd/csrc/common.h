@@ -149,6 +149,7 @@ struct ddamg_ctx {
   ddamg::DevPool pool;
   ddamg::Stats st;
   void* work = nullptr;         // solver workspaces (solve.hip)
+  void* ptc = nullptr;          // learned smoother state (ptc.hip)
   ddamg::MV tvk[2];             // smoothed (not orthonormalised) test vectors of each transition
   int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
   int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
@@ -197,6 +198,19 @@ void orthonormalise_P(ddamg_ctx* c, int level, double* d_P);
 void scatter_blocks(ddamg_ctx* c, int level, const MV& R, int slot);  // coarse level = level+1
 void convert_P32(ddamg_ctx* c, int level);
 void convert_blocks32(ddamg_ctx* c, int level);
+
+// ---- learned smoother (ptc.hip) ----
+void ptc_set_weights(ddamg_ctx* c, const double* w1, const double* w2);
+void ptc_get_weights(ddamg_ctx* c, double* w1, double* w2);
+bool ptc_ready(ddamg_ctx* c);
+void ptc_layer(ddamg_ctx* c, int layer, bool adjoint, const MV* in, const MV* out);
+void ptc_wgrad(ddamg_ctx* c, int layer, const MV* in, const MV* gout, double* g_host);
+bool ptc_smooth(ddamg_ctx* c, const MV& v, const MV& z, const double* d_mu, const MV* tmp, bool check);
+void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, uint64_t seed,
+               double* loss_hist);
+void free_ptc(ddamg_ctx* c);
+// fine-level smoother of the preconditioner: SAP, or the learned network with SAP fallback
+void fine_smoother(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu);
 
 // ---- host helpers ----
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);

@@ -368,7 +368,7 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
   MV s = get(c, w.s, l, prec, w.cap, nt);
   if (l == 0) {
     fine_residual(c, r, e, res, d_mu);
-    sap_apply(c, res, s, d_mu, s);
+    fine_smoother(c, res, s, d_mu);
   } else {
     MV t = get(c, w.q, l, prec, w.cap, nt);
     operator_apply(c, l, e, t, d_mu);
@@ -376,6 +376,32 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
     mr_smooth(c, l, d_mu, res, s, c->p.coarse_smooth_iters);
   }
   mv_add(c, s, e);
+}
+
+// Fine-level smoother: SAP, or the learned PTC network (FP32) with SAP as the
+// fallback whenever the network does not reduce the residual of every column.
+void fine_smoother(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu) {
+  if (c->p.smoother != DDAMG_SMOOTHER_LEARNED) {
+    sap_apply(c, f, x, d_mu, x);
+    return;
+  }
+  DD_CHECK(ptc_ready(c), DDAMG_ESTATE, "learned smoother selected but no weights set");
+  const int nt = f.ntiles;
+  LW& w = lw(c, 0, P32, nt);
+  MV in32 = f;
+  if (f.prec != P32) {
+    in32 = get(c, w.rho, 0, P32, w.cap, nt);
+    mv_copy(c, f, in32);
+  }
+  MV tmp[3] = {get(c, w.s, 0, P32, w.cap, nt), get(c, w.q, 0, P32, w.cap, nt), get(c, w.res, 0, P32, w.cap, nt)};
+  MV z32 = x.prec == P32 ? x : get(c, w.zt, 0, P32, w.cap, nt);
+  const bool ok = ptc_smooth(c, in32, z32, d_mu, tmp, true);
+  if (ok) {
+    if (x.prec != P32) mv_copy(c, z32, x);
+  } else {
+    c->st.learned_fallbacks++;
+    sap_apply(c, f, x, d_mu, x);
+  }
 }
 
 // ------------------------------------------------------------- setup ---
@@ -542,7 +568,7 @@ int solve_internal(ddamg_ctx* c, const double* d_mu, const MV& b, const MV& x, b
   Precond pc = [&](const MV& v, const MV& z) {
     const MV& in = (prec == v.prec) ? v : vin;
     if (prec != v.prec) mv_copy(c, v, vin);
-    if (c->nlev == 1) sap_apply(c, in, z, d_mu, z);
+    if (c->nlev == 1) fine_smoother(c, in, z, d_mu);
     else mg_cycle(c, 0, d_mu, in, z);
   };
   KrylovOut ko;

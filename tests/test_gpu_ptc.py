@@ -1,0 +1,172 @@
+"""GPU parity and behaviour of the learned PTC smoother, through the C ABI.
+
+The device stores weights in BF16 and accumulates in FP32; the oracle is fed
+the same BF16-rounded weights in FP64, so the bar is FP32 rounding (1e-5
+relative for the layers and the smoother, 1e-4 for the weight gradients,
+whose site sums are FP32 per lane).  Training, the use inside FGMRES and
+the SAP fallback are checked on the 4^4 and 8^4 lattices.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as S
+import oracle as O
+from oracle import ptc as OP
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.asarray(a, dtype=np.float64)
+    f = a.astype(np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (f >> 16) & 1
+    f = ((f + 0x7FFF + lsb) >> 16) << 16
+    return f.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def cbf16(w):
+    return bf16(w.real) + 1j * bf16(w.imag)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2201_03872_amd as m
+    m.load()
+    return m
+
+
+def ctx_for(dd, dims, **kw):
+    U = S.gauge_field(dims, 0.3, 81)
+    p = dd.default_params(dims=dims, kappa=0.15, n_levels=1, sap_block=(2, 2, 2, 2), **kw)
+    return dd.Context(p, U), U
+
+
+def relmax(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def test_layers_and_gradients(torch_cuda, dd):
+    torch = torch_cuda
+    dims = (4, 4, 4, 8)
+    V = S.volume(dims)
+    say("ptc layers", dims)
+    ctx, U = ctx_for(dd, dims)
+    op = O.WilsonTM(U, dims, kappa=0.15)
+    W1, W2 = cbf16(OP.random_weights(2, 1, 3, 0.3)), cbf16(OP.random_weights(1, 2, 4, 0.3))
+    ctx.set_smoother_weights(W1, W2)
+    ncol = 11
+    x = S.gaussian_spinors(ncol, V, 5)
+    xg = torch.from_numpy(x[None].copy()).cuda()
+    h = ctx.ptc_layer(1, False, xg).cpu().numpy()
+    h_ref = OP.ptc_layer(op, W1, x[None])
+    assert relmax(h, h_ref) < 1e-5
+    y = ctx.ptc_layer(2, False, torch.from_numpy(h_ref).cuda()).cpu().numpy()
+    assert relmax(y, OP.ptc_layer(op, W2, h_ref)) < 1e-5
+    # adjoint layers
+    g = S.gaussian_spinors(ncol, V, 6)[None]
+    a2 = ctx.ptc_layer(2, True, torch.from_numpy(g.copy()).cuda()).cpu().numpy()
+    assert relmax(a2, OP.ptc_layer_input_grad(op, W2, g)) < 1e-5
+    g2 = np.stack([S.gaussian_spinors(ncol, V, 7), S.gaussian_spinors(ncol, V, 8)])
+    a1 = ctx.ptc_layer(1, True, torch.from_numpy(g2).cuda()).cpu().numpy()
+    assert relmax(a1, OP.ptc_layer_input_grad(op, W1, g2)) < 1e-5
+    # weight gradients
+    G1 = ctx.ptc_weight_grad(1, xg, torch.from_numpy(g2).cuda())
+    assert relmax(G1, OP.ptc_layer_weight_grad(op, x[None], g2)) < 1e-4
+    G2 = ctx.ptc_weight_grad(2, torch.from_numpy(h_ref).cuda(), torch.from_numpy(g.copy()).cuda())
+    assert relmax(G2, OP.ptc_layer_weight_grad(op, h_ref, g)) < 1e-4
+    # the whole smoother
+    f = ctx.smoother_apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert relmax(f, OP.smoother_forward(op, W1, W2, x)[0]) < 1e-5
+    ctx.close()
+
+
+def jacobi_init(m0):
+    """f(r) = r / (4 + m0) plus a small perturbation of the second channel."""
+    W1 = np.zeros((9, 2, 1, 4, 4), dtype=np.complex128)
+    W2 = np.zeros((9, 1, 2, 4, 4), dtype=np.complex128)
+    W1[0, 0, 0] = np.eye(4)
+    W1[0, 1, 0] = 0.01 * np.eye(4)
+    W2[0, 0, 0] = np.eye(4) / (4 + m0)
+    W2[0, 0, 1] = 0.01 * np.eye(4)
+    return W1, W2
+
+
+def test_training_reduces_loss_and_helps_the_solve(torch_cuda, dd):
+    torch = torch_cuda
+    w = S.workload("tm_8x8x8x8_3level")
+    say("train + solve", w.name)
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    b = torch.from_numpy(S.rhs_for(w)).cuda()
+    mus = np.array(w.mus)
+    base = dict(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block, outer_restart=30, max_outer=2000,
+                precision=dd.MIXED)
+    ctx = dd.Context(dd.default_params(smoother=dd.SMOOTHER_LEARNED, **base), U)
+    m0 = 1 / (2 * w.kappa) - 4
+    ctx.set_smoother_weights(*jacobi_init(m0))
+    _, info0, st0 = ctx.solve(mus, b)
+    it0 = max(i["outer_iters"] for i in info0)
+    hist = ctx.train_smoother(mus, steps=150, batch=16, lr=2e-3, seed=5)
+    say("  loss first/last", hist[:5].mean(), hist[-5:].mean())
+    assert hist[-5:].mean() < 0.9 * hist[:5].mean()
+    x, info1, st1 = ctx.solve(mus, b)
+    it1 = max(i["outer_iters"] for i in info1)
+    stats = ctx.stats()
+    op = O.WilsonTM(U, w.dims, kappa=w.kappa)
+    bb = np.repeat(S.rhs_for(w), len(mus), axis=0)
+    rel = O.col_norm(bb - op.apply(x.cpu().numpy(), np.tile(mus, w.n_rhs))) / O.col_norm(bb)
+    sap = dd.Context(dd.default_params(smoother=dd.SMOOTHER_SAP, sap_cycles=1, sap_mr_iters=8, **base), U)
+    _, info_s, _ = sap.solve(mus, b)
+    it_s = max(i["outer_iters"] for i in info_s)
+    say(f"  outer iterations: untrained {it0}, trained {it1}, SAP(1,8) {it_s}; fallbacks {stats['learned_fallbacks']}")
+    assert st1 == dd.OK and np.all(rel <= 1e-10 * (1 + 1e-6))
+    assert it1 < it0
+    ctx.close()
+    sap.close()
+
+
+def test_fallback_to_sap_when_the_network_fails(torch_cuda, dd):
+    torch = torch_cuda
+    w = S.workload("tm_4x4x4x4_2rhs_3shift")
+    say("fallback", w.name)
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block,
+                          smoother=dd.SMOOTHER_LEARNED, precision=dd.MIXED)
+    ctx = dd.Context(p, U)
+    W1, W2 = jacobi_init(1 / (2 * w.kappa) - 4)
+    ctx.set_smoother_weights(W1, -20.0 * W2)          # a net that amplifies the residual
+    b = torch.from_numpy(S.rhs_for(w)).cuda()
+    x, info, st = ctx.solve(np.array(w.mus), b)
+    assert st == dd.OK
+    assert ctx.stats()["learned_fallbacks"] > 0
+    op = O.WilsonTM(U, w.dims, kappa=w.kappa)
+    bb = np.repeat(S.rhs_for(w), 3, axis=0)
+    rel = O.col_norm(bb - op.apply(x.cpu().numpy(), np.tile(np.array(w.mus), 2))) / O.col_norm(bb)
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+    ctx.close()
+
+
+def test_learned_smoother_requires_weights(dd, torch_cuda):
+    torch = torch_cuda
+    w = S.workload("tm_4x4x4x4_2rhs_3shift")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block, smoother=dd.SMOOTHER_LEARNED)
+    ctx = dd.Context(p, U)
+    with pytest.raises(dd.DDAMGError) as e:
+        ctx.solve(np.array(w.mus), torch.from_numpy(S.rhs_for(w)).cuda())
+    assert e.value.code == dd.ESTATE
+    ctx.close()
