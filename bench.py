@@ -122,6 +122,94 @@ def _cpu_baseline(w, U, outer_iters, sap_mr, np, O, S, Blocking, FineLevel):
                         f"solve needed; sampling took {time.time() - t_all:.0f}s"))
 
 
+# Learned-smoother study: 16^3x32 fields drawn like the benchmark's (eps 0.3,
+# kappa 0.150), 8 training and 4 held-out gauge seeds; 8 x 160 Adam steps of
+# 16 residual -> error pairs (20480 pairs), errors from 0..2 SAP sweeps; the
+# trained net (4 minimal-residual steps per call, SAP fallback) replaces SAP in
+# FGMRES(40) on 3 rhs x 4 shifts per held-out field.
+LEARNED_TRAIN_SEEDS = tuple(range(4101, 4109))
+LEARNED_HELDOUT_SEEDS = tuple(range(4201, 4205))
+LEARNED = dict(steps=160, batch=16, lr=2e-3, sap_sweeps=2, cycles=4, n_rhs=3)
+
+
+def learned_study(dd, S, np, torch):
+    w = S.workload(WORKLOAD)
+    mus = np.array(w.mus)
+    b = torch.from_numpy(S.rhs_for(w)[:LEARNED["n_rhs"]].copy()).cuda()
+    ncol = b.shape[0] * len(mus)
+    m0 = 1 / (2 * w.kappa) - 4
+    W1 = np.zeros((9, 2, 1, 4, 4), dtype=np.complex128)
+    W2 = np.zeros((9, 1, 2, 4, 4), dtype=np.complex128)
+    W1[0, 0, 0], W1[0, 1, 0] = np.eye(4), 0.01 * np.eye(4)          # start: f(r) = r / (4 + m0)
+    W2[0, 0, 0], W2[0, 0, 1] = np.eye(4) / (4 + m0), 0.01 * np.eye(4)
+    weights = (W1, W2)
+
+    def ctx_for(seed, **kw):
+        U = S.gauge_field(w.dims, w.eps, seed)
+        c = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, **{**SOLVER, **kw}), U)
+        c.autotune(ncol)
+        return c
+
+    t0 = time.time()
+    losses = []
+    for k, seed in enumerate(LEARNED_TRAIN_SEEDS):
+        c = ctx_for(seed)
+        c.set_smoother_weights(*weights)
+        h = c.train_smoother(mus, LEARNED["steps"], LEARNED["batch"], LEARNED["lr"], LEARNED["sap_sweeps"],
+                             seed=7 + k)
+        weights = c.smoother_weights()
+        c.close()
+        losses.append((float(h[:10].mean()), float(h[-10:].mean())))
+        log(f"  trained on gauge seed {seed}: loss {losses[-1][0]:.4f} -> {losses[-1][1]:.4f}")
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+
+    def timed_solve(c):
+        torch.cuda.synchronize()
+        t = time.time()
+        x, info, st = c.solve(mus, b)
+        torch.cuda.synchronize()
+        t = time.time() - t
+        ok = st == dd.OK and all(i["converged"] for i in info)
+        return dict(iters=max(i["outer_iters"] for i in info), seconds=t, converged=ok,
+                    worst_true_rel_res=max(i["true_rel_res"] for i in info))
+
+    rows = []
+    for seed in LEARNED_HELDOUT_SEEDS:
+        c = ctx_for(seed)
+        sap = timed_solve(c)
+        c.close()
+        c = ctx_for(seed, smoother=dd.SMOOTHER_LEARNED, smoother_cycles=LEARNED["cycles"])
+        c.set_smoother_weights(W1, W2)
+        untrained = timed_solve(c)
+        c.set_smoother_weights(*weights)
+        learned = timed_solve(c)
+        learned["fallbacks"] = c.stats()["learned_fallbacks"]
+        c.close()
+        rows.append(dict(seed=seed, sap=sap, learned_untrained=untrained, learned=learned))
+        log(f"  held-out seed {seed}: SAP {sap['iters']} it {sap['seconds']:.2f}s, untrained net "
+            f"{untrained['iters']} it, trained net {learned['iters']} it {learned['seconds']:.2f}s "
+            f"({learned['fallbacks']} fallbacks)")
+    mean = lambda key, f: float(np.mean([r[key][f] for r in rows]))
+    out = {
+        "metric": "outer FGMRES iterations and seconds per solve, learned smoother vs SAP (held-out fields)",
+        "value": mean("sap", "seconds") / mean("learned", "seconds"),
+        "unit": "SAP time / learned-smoother time",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "dtype": "f64 outer / f32 smoother / bf16 network weights",
+        "config": {"workload": "16x16x16x32 learned-smoother study", "kappa": w.kappa, "eps": w.eps,
+                   "train_seeds": list(LEARNED_TRAIN_SEEDS), "heldout_seeds": list(LEARNED_HELDOUT_SEEDS),
+                   "pairs": len(LEARNED_TRAIN_SEEDS) * LEARNED["steps"] * LEARNED["batch"],
+                   "columns": ncol, **LEARNED},
+        "train_seconds": train_s, "train_loss": losses,
+        "mean_iters": {k: mean(k, "iters") for k in ("sap", "learned_untrained", "learned")},
+        "mean_seconds": {k: mean(k, "seconds") for k in ("sap", "learned_untrained", "learned")},
+        "all_converged": all(r[k]["converged"] for r in rows for k in ("sap", "learned")),
+        "heldout": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +217,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="instead of the solve benchmark, train the learned smoother on 8 gauge fields and "
+                         "compare it with SAP on 4 held-out fields")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (how it would shard is "
@@ -142,6 +233,9 @@ def main():
 
     torch.cuda.set_device(0)
     dd.load()
+    if args.learned:
+        learned_study(dd, S, np, torch)
+        return
     w = S.workload(WORKLOAD)
     log("workload", w.name, "- generating inputs")
     U = S.gauge_field(w.dims, w.eps, w.seed_gauge)

@@ -103,6 +103,7 @@ typedef struct ddamg_params {
   int    coarsest_block;     /* 1: block GMRES per shift group on the coarsest level            */
   int    precision;          /* DDAMG_PLAIN_FP64 or DDAMG_MIXED                                 */
   int    smoother;           /* DDAMG_SMOOTHER_SAP or DDAMG_SMOOTHER_LEARNED                    */
+  int    smoother_cycles;    /* learned smoother: minimal-residual steps along f(r) per call    */
   int    col_tile;           /* columns per tile of the internal layout (4, 8 or 16; 0 = 8)     */
   uint64_t seed;             /* counter-based RNG seed of the setup vectors when none are given */
   int    verbose;            /* 0 = silent                                                      */
@@ -124,7 +125,7 @@ typedef struct ddamg_stats {
   long long n_bottom_solves;
   long long n_fine_ops;      /* fine-level operator applications of the last solve              */
   long long n_sap_calls;
-  int    learned_fallbacks;  /* learned-smoother calls replaced by SAP                          */
+  int    learned_fallbacks;  /* learned-smoother calls replaced by SAP (last solve)             */
 } ddamg_stats;
 
 /* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */
@@ -225,12 +226,14 @@ int ddamg_autotune(ddamg_ctx* h, int n_col, int* values);
  * Weights (host, double complex): layer 1 [9][2][1][4][4], layer 2 [9][1][2][4][4];
  * on the device they are stored in BF16 and used with FP32 accumulation.
  * With params.smoother = DDAMG_SMOOTHER_LEARNED the network replaces the fine
- * SAP smoother in the preconditioner; whenever it does not reduce the residual
- * of every column (||v - D f(v)|| >= ||v||) SAP is used for that call instead
- * (counted in ddamg_stats.learned_fallbacks). */
+ * SAP smoother in the preconditioner: from z = 0, r = v, params.smoother_cycles
+ * minimal-residual steps along p = f(r) (z += a p, r -= a D p,
+ * a = <Dp, r>/<Dp, Dp>).  Whenever the network's first output does not reduce
+ * the residual of every column (||v - D f(v)|| >= ||v||) SAP is used for that
+ * call instead (counted in ddamg_stats.learned_fallbacks). */
 int ddamg_smoother_set_weights(ddamg_ctx* h, const double* w1, const double* w2);
 int ddamg_smoother_get_weights(ddamg_ctx* h, double* w1, double* w2);
-/* y = f(x) for n_col fine vectors (device, canonical layout). */
+/* y = f(x), one network pass, for n_col fine vectors (device, canonical layout). */
 int ddamg_smoother_apply(ddamg_ctx* h, int n_col, const double* x, double* y);
 /* One layer (1 or 2), or its adjoint when adjoint != 0, on FP32 internal data:
  * in: [c_in][n_col][V][4][3] complex, out: [c_out][n_col][V][4][3] (device). */
@@ -238,12 +241,16 @@ int ddamg_ptc_layer(ddamg_ctx* h, int layer, int adjoint, int n_col, const doubl
 /* Weight gradient of one layer: g[p][o][i][s][t] = 2 sum_{x,c,col} gout_o[s][c] conj((T_p in_i)[t][c])
  * (= dL/dRe W + i dL/dIm W for gout = dL/d conj(out)); in, gout device, g host. */
 int ddamg_ptc_weight_grad(ddamg_ctx* h, int layer, int n_col, const double* in, const double* gout, double* g);
-/* Train the current weights with Adam on the GPU kernels: every step draws
- * `batch` Gaussian errors e, forms r = D(mu_c) e (mu_c cycles through mus),
- * scales both by 1/||r||, and descends the mean of ||f(r) - e||^2 / ||e||^2.
- * loss_history (host, `steps` entries) may be NULL. */
+/* Train the current weights with Adam on the GPU kernels from residual -> error
+ * pairs that the solver iteration produces: every step draws `batch` Gaussian
+ * errors e0 and applies k = step mod (sap_sweeps + 1) SAP error-propagation
+ * sweeps e <- e - M_SAP D e (params.sap_cycles / sap_mr_iters); then
+ * r = D(mu_c) e (mu_c cycles through mus), both scaled by 1/||r||, and Adam
+ * descends the mean of ||f(r) - e||^2 / ||e||^2.  Adam's moments start from
+ * zero on every call.  loss_history (host, `steps` entries) may be NULL.
+ * Returns DDAMG_ESTATE if no weights were set, DDAMG_EINVAL for bad sizes. */
 int ddamg_train_smoother(ddamg_ctx* h, const double* mus, int n_mu, int steps, int batch, double lr,
-                         uint64_t seed, double* loss_history);
+                         int sap_sweeps, uint64_t seed, double* loss_history);
 
 void ddamg_destroy(ddamg_ctx* h);
 const char* ddamg_strerror(int status);

@@ -60,6 +60,7 @@ class Params(ctypes.Structure):
         ("coarsest_block", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("smoother", ctypes.c_int),
+        ("smoother_cycles", ctypes.c_int),
         ("col_tile", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
@@ -122,7 +123,7 @@ def load():
         "ddamg_ptc_layer": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
         "ddamg_ptc_weight_grad": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "ddamg_train_smoother": (ctypes.c_int, [vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                                ctypes.c_uint64, dp]),
+                                                ctypes.c_int, ctypes.c_uint64, dp]),
         "ddamg_destroy": (None, [vp]),
         "ddamg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "ddamg_last_error": (ctypes.c_char_p, []),
@@ -312,10 +313,11 @@ class Context:
         _check(load().ddamg_ptc_weight_grad(self.h, layer, x.shape[1], _dptr(x), _dptr(gout), g.ctypes.data))
         return g
 
-    def train_smoother(self, mus, steps, batch, lr, seed=1):
+    def train_smoother(self, mus, steps, batch, lr, sap_sweeps=0, seed=1):
         m, mp = _mu(mus)
         hist = np.zeros(steps)
-        _check(load().ddamg_train_smoother(self.h, mp, len(m), int(steps), int(batch), float(lr), int(seed),
+        _check(load().ddamg_train_smoother(self.h, mp, len(m), int(steps), int(batch), float(lr), int(sap_sweeps),
+                                           int(seed),
                                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return hist
 

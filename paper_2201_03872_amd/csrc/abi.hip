@@ -89,6 +89,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->coarsest_block = 0;
   p->precision = DDAMG_PLAIN_FP64;
   p->smoother = DDAMG_SMOOTHER_SAP;
+  p->smoother_cycles = 1;
   p->col_tile = 8;
   p->seed = 12345;
   p->verbose = 0;
@@ -129,6 +130,7 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->tol > 0 && p->r_m > 0 && p->r_b > 0, DDAMG_EINVAL, "tolerances must be positive");
   DD_CHECK(p->precision == DDAMG_PLAIN_FP64 || p->precision == DDAMG_MIXED, DDAMG_EINVAL, "precision mode");
   DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP || p->smoother == DDAMG_SMOOTHER_LEARNED, DDAMG_EINVAL, "smoother");
+  DD_CHECK(p->smoother_cycles >= 1 && p->smoother_cycles <= 64, DDAMG_EINVAL, "smoother_cycles");
 }
 
 int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
@@ -343,6 +345,7 @@ int ddamg_solve(ddamg_ctx* c, const double* mu, int n_shift, const double* b, in
     auto t0 = std::chrono::steady_clock::now();
     c->st.middle_calls = c->st.middle_iters = c->st.bottom_calls = c->st.bottom_iters = 0;
     c->st.fine_ops = c->st.sap_calls = 0;
+    c->st.learned_fallbacks = 0;
     const int ncol = n_rhs * n_shift;
     std::vector<double> hmu(ncol);
     for (int r = 0; r < n_rhs; ++r)
@@ -554,14 +557,14 @@ int ddamg_smoother_get_weights(ddamg_ctx* c, double* w1, double* w2) {
 int ddamg_smoother_apply(ddamg_ctx* c, int n_col, const double* x, double* y) {
   return guarded([&]() -> int {
     DD_CHECK(c && x && y && n_col >= 1, DDAMG_EINVAL, "bad arguments");
+    DD_CHECK(ptc_ready(c), DDAMG_ESTATE, "smoother weights not set");
     MV a = mv_alloc(c, 0, P32, n_col), b = mv_alloc(c, 0, P32, n_col);
-    MV tmp[3] = {mv_alloc(c, 0, P32, n_col), mv_alloc(c, 0, P32, n_col), mv_alloc(c, 0, P32, n_col)};
     to_internal(c, 0, x, n_col, a);
-    ptc_smooth(c, a, b, nullptr, tmp, false);
+    ptc_apply(c, a, b);
     from_internal(c, 0, b, n_col, y);
     DD_HIP(hipStreamSynchronize(c->stream));
-    MV* all[] = {&a, &b, &tmp[0], &tmp[1], &tmp[2]};
-    for (MV* m : all) mv_free(c, *m);
+    mv_free(c, a);
+    mv_free(c, b);
     return DDAMG_OK;
   });
 }
@@ -611,11 +614,12 @@ int ddamg_ptc_weight_grad(ddamg_ctx* c, int layer, int n_col, const double* in, 
   });
 }
 
-int ddamg_train_smoother(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, uint64_t seed,
-                         double* loss_history) {
+int ddamg_train_smoother(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, int sap_sweeps,
+                         uint64_t seed, double* loss_history) {
   return guarded([&]() -> int {
-    DD_CHECK(c && mus && n_mu >= 1 && steps >= 1 && batch >= 1 && lr > 0, DDAMG_EINVAL, "bad arguments");
-    ptc_train(c, mus, n_mu, steps, batch, lr, seed, loss_history);
+    DD_CHECK(c && mus && n_mu >= 1 && steps >= 1 && batch >= 1 && lr > 0 && sap_sweeps >= 0, DDAMG_EINVAL,
+             "bad arguments");
+    ptc_train(c, mus, n_mu, steps, batch, lr, sap_sweeps, seed, loss_history);
     return DDAMG_OK;
   });
 }

@@ -205,9 +205,10 @@ void ptc_get_weights(ddamg_ctx* c, double* w1, double* w2);
 bool ptc_ready(ddamg_ctx* c);
 void ptc_layer(ddamg_ctx* c, int layer, bool adjoint, const MV* in, const MV* out);
 void ptc_wgrad(ddamg_ctx* c, int layer, const MV* in, const MV* gout, double* g_host);
-bool ptc_smooth(ddamg_ctx* c, const MV& v, const MV& z, const double* d_mu, const MV* tmp, bool check);
-void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, uint64_t seed,
-               double* loss_hist);
+void ptc_apply(ddamg_ctx* c, const MV& v, const MV& z);
+bool ptc_smooth(ddamg_ctx* c, const MV& v, const MV& z, const double* d_mu, int cycles);
+void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, int sap_sweeps,
+               uint64_t seed, double* loss_hist);
 void free_ptc(ddamg_ctx* c);
 // fine-level smoother of the preconditioner: SAP, or the learned network with SAP fallback
 void fine_smoother(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu);

@@ -228,6 +228,12 @@ struct PtcState {
   uint16_t* d_w[2] = {nullptr, nullptr};    // BF16 forward weights
   uint16_t* d_wadj[2] = {nullptr, nullptr}; // BF16 adjoint weights (input gradient)
   bool set = false;
+  // smoother workspace (FP32 fine multivectors, `cap` tiles each):
+  // hidden channels h0, h1, residual, correction, FP32 copies of input / output
+  int cap = 0;
+  MV ws[6];
+  double* d_coef = nullptr;   // per-column MR dots and coefficients, 10 doubles per column
+  int coef_cap = 0;
 };
 
 static const int CIN_OF[2] = {1, 2}, COUT_OF[2] = {2, 1};
@@ -238,8 +244,28 @@ static PtcState& state(ddamg_ctx* c) {
 }
 
 void free_ptc(ddamg_ctx* c) {
-  delete static_cast<PtcState*>(c->ptc);
+  if (!c->ptc) return;
+  PtcState* st = static_cast<PtcState*>(c->ptc);
+  for (MV& m : st->ws) mv_free(c, m);
+  if (st->d_coef) c->pool.release(st->d_coef);
+  delete st;
   c->ptc = nullptr;
+}
+
+// the smoother workspace, grown to at least nt tiles
+static MV* workspace(ddamg_ctx* c, int nt) {
+  PtcState& st = state(c);
+  if (nt > st.cap) {
+    for (MV& m : st.ws) mv_free(c, m);
+    for (MV& m : st.ws) m = mv_alloc(c, 0, P32, nt * c->T);
+    st.cap = nt;
+  }
+  if (nt * c->T > st.coef_cap) {
+    if (st.d_coef) c->pool.release(st.d_coef);
+    st.coef_cap = nt * c->T;
+    st.d_coef = (double*)c->pool.alloc((size_t)10 * st.coef_cap * sizeof(double));
+  }
+  return st.ws;
 }
 
 static size_t nweights(int layer) { return (size_t)9 * COUT_OF[layer] * CIN_OF[layer] * 16; }
@@ -351,38 +377,80 @@ void ptc_wgrad(ddamg_ctx* c, int layer, const MV* in, const MV* gout, double* g_
 }
 
 // --------------------------------------------------------- smoother use ---
-// z = f(v) (FP32).  With check, also returns whether every column's
-// residual ||v - D f(v)|| is below ||v|| (the condition for using the
-// network instead of SAP).  tmp: three FP32 fine multivectors shaped like v.
-bool ptc_smooth(ddamg_ctx* c, const MV& v, const MV& z, const double* d_mu, const MV* tmp, bool check) {
-  ptc_layer(c, 0, false, &v, tmp);
-  ptc_layer(c, 1, false, tmp, &z);
-  if (!check) return true;
-  fine_dslash(c, z, tmp[2], d_mu);
-  mv_sub(c, v, tmp[2], tmp[2]);
-  const int ncol = v.ncol();
-  // mv_norm2 uses the first 2*ncol doubles of the small buffer itself
-  double* d = small_buffer(c, 4 * ncol);
-  mv_norm2(c, v, d + 2 * ncol);
-  mv_norm2(c, tmp[2], d + 3 * ncol);
-  std::vector<double> h(2 * ncol);
-  copy_to_host(c, d + 2 * ncol, h.data(), h.size() * sizeof(double));
-  for (int i = 0; i < ncol; ++i)
-    if (h[i] > 0 && !(h[ncol + i] < h[i])) return false;
+// z = f(v) for one network pass (FP32 in, FP32 out, distinct buffers).
+void ptc_apply(ddamg_ctx* c, const MV& v, const MV& z) {
+  MV* ws = workspace(c, v.ntiles);
+  const MV h[2] = {ws[0].tiles(0, v.ntiles), ws[1].tiles(0, v.ntiles)};
+  ptc_layer(c, 0, false, &v, h);
+  ptc_layer(c, 1, false, h, &z);
+}
+
+// alpha = <q, r> / <q, q> per column (minimal-residual step), 0 where <q,q> = 0
+__global__ void k_ptc_alpha(const double* __restrict__ qr, const double* __restrict__ qq, double* __restrict__ a,
+                            int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = qq[i];
+  a[2 * i] = d > 0 ? qr[2 * i] / d : 0.0;
+  a[2 * i + 1] = d > 0 ? qr[2 * i + 1] / d : 0.0;
+}
+
+// The learned smoother: from z = 0, r = v, `cycles` minimal-residual steps
+// with the network as search direction: p = f(r), q = D p,
+// alpha = <q,r>/<q,q>, z += alpha p, r -= alpha q.  Returns false if the
+// network's own first output does not reduce the residual of every column,
+// ||v - D f(v)|| >= ||v||, i.e. ||q0||^2 >= 2 Re<q0, v>, for a column with
+// v != 0 (the condition for using SAP instead); z then holds the smoother's
+// result all the same.
+// v and z may be FP32 or FP64 (converted through the workspace).
+bool ptc_smooth(ddamg_ctx* c, const MV& v, const MV& z, const double* d_mu, int cycles) {
+  const int nt = v.ntiles, ncol = v.ncol();
+  MV* ws = workspace(c, nt);
+  PtcState& st = state(c);
+  const MV q = ws[2].tiles(0, nt), p = ws[3].tiles(0, nt), r = ws[4].tiles(0, nt);
+  const MV z32 = z.prec == P32 ? z : ws[5].tiles(0, nt);
+  double* qr0 = st.d_coef;            // [ncol] complex <q0, v>
+  double* qq0 = qr0 + 2 * ncol;       // [ncol] ||q0||^2
+  double* vv = qq0 + ncol;            // [ncol] ||v||^2
+  double* qr = vv + ncol;             // [ncol] complex
+  double* qq = qr + 2 * ncol;         // [ncol]
+  double* al = qq + ncol;             // [ncol] complex
+  mv_copy(c, v, r);
+  mv_norm2(c, r, vv);
+  mv_zero(c, z32);
+  for (int k = 0; k < cycles; ++k) {
+    ptc_apply(c, r, p);
+    fine_dslash(c, p, q, d_mu);
+    mv_dot(c, q, r, k == 0 ? qr0 : qr);
+    mv_norm2(c, q, k == 0 ? qq0 : qq);
+    hipLaunchKernelGGL(k_ptc_alpha, dim3((ncol + 255) / 256), dim3(256), 0, c->stream, k == 0 ? qr0 : qr,
+                       k == 0 ? qq0 : qq, al, ncol);
+    DD_HIP(hipGetLastError());
+    mv_axpy(c, al, p, z32, +1);
+    if (k + 1 < cycles) mv_axpy(c, al, q, r, -1);
+  }
+  if (z.prec != P32) mv_copy(c, z32, z);
+  std::vector<double> h(4 * ncol);
+  copy_to_host(c, qr0, h.data(), h.size() * sizeof(double));
+  for (int i = 0; i < ncol; ++i)   // zero columns (padding, converged) pass
+    if (h[3 * ncol + i] > 0 && !(h[2 * ncol + i] < 2.0 * h[2 * i])) return false;
   return true;
 }
 
 // ------------------------------------------------------------ training ---
 void random_fill(ddamg_ctx* c, int level, const MV& X, int ncol, uint64_t seed);
 
-// Adam on the FP64 master weights from operator-generated pairs: e random
-// Gaussian, r = D(mu_c) e, both scaled by 1/||r||; loss per column
-// ||f(r) - e||^2 / ||e||^2 (mean over the batch).
-void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, uint64_t seed,
-               double* loss_hist) {
+// Adam on the FP64 master weights from residual -> error pairs: each step
+// draws Gaussian errors e0 and lets the SAP solver iteration act on them,
+// e = (1 - M_SAP D)^k e0 with k = step mod (sap_sweeps + 1), so the pairs
+// range from rough errors to the smooth ones SAP leaves behind; r = D(mu_c) e,
+// both scaled by 1/||r||; loss per column ||f(r) - e||^2 / ||e||^2 (mean over
+// the batch).
+void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, double lr, int sap_sweeps,
+               uint64_t seed, double* loss_hist) {
   PtcState& st = state(c);
   DD_CHECK(st.set, DDAMG_ESTATE, "smoother weights not initialised");
-  DD_CHECK(steps >= 1 && batch >= 1 && n_mu >= 1, DDAMG_EINVAL, "training sizes");
+  DD_CHECK(steps >= 1 && batch >= 1 && n_mu >= 1 && sap_sweeps >= 0, DDAMG_EINVAL, "training sizes");
   MV e64 = mv_alloc(c, 0, P64, batch);
   const int ncol = e64.ncol();
   MV e = mv_alloc(c, 0, P32, batch), r = mv_alloc(c, 0, P32, batch);
@@ -405,6 +473,13 @@ void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, 
   for (int it = 0; it < steps; ++it) {
     random_fill(c, 0, e64, batch, seed + 1315423911ULL * (it + 1));
     mv_copy(c, e64, e);
+    const int k = sap_sweeps > 0 ? it % (sap_sweeps + 1) : 0;
+    for (int q = 0; q < k; ++q) {
+      // e <- e - M_SAP D e  (y, gy serve as temporaries)
+      fine_dslash(c, e, y, d_mu);
+      sap_apply(c, y, gy, d_mu, gy);
+      mv_sub(c, e, gy, e);
+    }
     fine_dslash(c, e, r, d_mu);
     mv_norm2(c, r, d_n);
     hipLaunchKernelGGL(k_scale_real, dim3((unsigned)gsz), dim3(256), 0, c->stream, r.as<float>(), d_n, np, e.T, 2,

@@ -386,19 +386,7 @@ void fine_smoother(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu) {
     return;
   }
   DD_CHECK(ptc_ready(c), DDAMG_ESTATE, "learned smoother selected but no weights set");
-  const int nt = f.ntiles;
-  LW& w = lw(c, 0, P32, nt);
-  MV in32 = f;
-  if (f.prec != P32) {
-    in32 = get(c, w.rho, 0, P32, w.cap, nt);
-    mv_copy(c, f, in32);
-  }
-  MV tmp[3] = {get(c, w.s, 0, P32, w.cap, nt), get(c, w.q, 0, P32, w.cap, nt), get(c, w.res, 0, P32, w.cap, nt)};
-  MV z32 = x.prec == P32 ? x : get(c, w.zt, 0, P32, w.cap, nt);
-  const bool ok = ptc_smooth(c, in32, z32, d_mu, tmp, true);
-  if (ok) {
-    if (x.prec != P32) mv_copy(c, z32, x);
-  } else {
+  if (!ptc_smooth(c, f, x, d_mu, c->p.smoother_cycles)) {
     c->st.learned_fallbacks++;
     sap_apply(c, f, x, d_mu, x);
   }

@@ -4,7 +4,8 @@ The device stores weights in BF16 and accumulates in FP32; the oracle is fed
 the same BF16-rounded weights in FP64, so the bar is FP32 rounding (1e-5
 relative for the layers and the smoother, 1e-4 for the weight gradients,
 whose site sums are FP32 per lane).  Training, the use inside FGMRES and
-the SAP fallback are checked on the 4^4 and 8^4 lattices.
+the SAP fallback are checked on the 4^4 and 8^4 lattices (training on two
+gauge fields, evaluation on a third).
 """
 import sys
 
@@ -106,35 +107,46 @@ def jacobi_init(m0):
     return W1, W2
 
 
-def test_training_reduces_loss_and_helps_the_solve(torch_cuda, dd):
+def test_training_reduces_loss_and_helps_on_a_held_out_field(torch_cuda, dd):
+    """Train on two 8^4 gauge fields, solve on a third one (gauge covariance
+    makes the weights field-independent): the trained net must cut the outer
+    iterations of the untrained one; SAP is reported beside it."""
     torch = torch_cuda
     w = S.workload("tm_8x8x8x8_3level")
     say("train + solve", w.name)
-    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
     b = torch.from_numpy(S.rhs_for(w)).cuda()
     mus = np.array(w.mus)
     base = dict(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block, outer_restart=30, max_outer=2000,
-                precision=dd.MIXED)
-    ctx = dd.Context(dd.default_params(smoother=dd.SMOOTHER_LEARNED, **base), U)
+                precision=dd.MIXED, sap_cycles=1, sap_mr_iters=8)
     m0 = 1 / (2 * w.kappa) - 4
+    weights = jacobi_init(m0)
+    for k, seed in enumerate((3101, 3102)):
+        ctx = dd.Context(dd.default_params(**base), S.gauge_field(w.dims, w.eps, seed))
+        ctx.set_smoother_weights(*weights)
+        hist = ctx.train_smoother(mus, steps=200, batch=16, lr=2e-3, sap_sweeps=2, seed=5 + k)
+        say(f"  seed {seed}: loss first/last {hist[:5].mean():.4f} {hist[-5:].mean():.4f}")
+        if k == 0:   # the second field continues from trained weights
+            assert hist[-6:].mean() < 0.9 * hist[:6].mean()
+        weights = ctx.smoother_weights()
+        ctx.close()
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    ctx = dd.Context(dd.default_params(smoother=dd.SMOOTHER_LEARNED, smoother_cycles=4, **base), U)
     ctx.set_smoother_weights(*jacobi_init(m0))
-    _, info0, st0 = ctx.solve(mus, b)
+    _, info0, _ = ctx.solve(mus, b)
     it0 = max(i["outer_iters"] for i in info0)
-    hist = ctx.train_smoother(mus, steps=150, batch=16, lr=2e-3, seed=5)
-    say("  loss first/last", hist[:5].mean(), hist[-5:].mean())
-    assert hist[-5:].mean() < 0.9 * hist[:5].mean()
+    ctx.set_smoother_weights(*weights)
     x, info1, st1 = ctx.solve(mus, b)
     it1 = max(i["outer_iters"] for i in info1)
-    stats = ctx.stats()
+    fb = ctx.stats()["learned_fallbacks"]
     op = O.WilsonTM(U, w.dims, kappa=w.kappa)
     bb = np.repeat(S.rhs_for(w), len(mus), axis=0)
     rel = O.col_norm(bb - op.apply(x.cpu().numpy(), np.tile(mus, w.n_rhs))) / O.col_norm(bb)
-    sap = dd.Context(dd.default_params(smoother=dd.SMOOTHER_SAP, sap_cycles=1, sap_mr_iters=8, **base), U)
+    sap = dd.Context(dd.default_params(smoother=dd.SMOOTHER_SAP, **base), U)
     _, info_s, _ = sap.solve(mus, b)
     it_s = max(i["outer_iters"] for i in info_s)
-    say(f"  outer iterations: untrained {it0}, trained {it1}, SAP(1,8) {it_s}; fallbacks {stats['learned_fallbacks']}")
+    say(f"  held-out field: outer iterations untrained {it0}, trained {it1} ({fb} fallbacks), SAP(1,8) {it_s}")
     assert st1 == dd.OK and np.all(rel <= 1e-10 * (1 + 1e-6))
-    assert it1 < it0
+    assert it1 < 0.8 * it0
     ctx.close()
     sap.close()
 
