@@ -105,6 +105,8 @@ typedef struct ddamg_params {
   int    smoother;           /* DDAMG_SMOOTHER_SAP or DDAMG_SMOOTHER_LEARNED                    */
   int    smoother_cycles;    /* learned smoother: minimal-residual steps along f(r) per call    */
   int    col_tile;           /* columns per tile of the internal layout (4, 8 or 16; 0 = 8)     */
+  int    max_active_cols;    /* outer solve: columns in flight at once (0 = as memory allows);  */
+                             /* the others wait and join as converged columns leave             */
   uint64_t seed;             /* counter-based RNG seed of the setup vectors when none are given */
   int    verbose;            /* 0 = silent                                                      */
 } ddamg_params;
@@ -126,6 +128,7 @@ typedef struct ddamg_stats {
   long long n_fine_ops;      /* fine-level operator applications of the last solve              */
   long long n_sap_calls;
   int    learned_fallbacks;  /* learned-smoother calls replaced by SAP (last solve)             */
+  int    col_removals;       /* compactions of the active column set (last solve)               */
 } ddamg_stats;
 
 /* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */
@@ -184,6 +187,17 @@ int ddamg_level_info(ddamg_ctx* h, int level, int* volume, int* dof, int dims[4]
  * entries or NULL.  Returns DDAMG_NOT_CONVERGED if any column misses tol. */
 int ddamg_solve(ddamg_ctx* h, const double* mu, int n_shift, const double* b, int n_rhs,
                 double* x, int use_x0, ddamg_col_info* info);
+
+/* Many independent systems on the same gauge field in one simultaneous solve
+ * (uneven batches): system s has n_rhs[s] right-hand sides and n_shift[s]
+ * twisted masses.  mu: host, the systems' shifts one after the other
+ * (sum n_shift entries); b: device, their right-hand sides one after the other
+ * (sum n_rhs fields [V][4][3]); x: device, the columns of system 0
+ * (rhs-major, shift fastest), then of system 1, ... (sum n_rhs*n_shift fields);
+ * info: host, one entry per column, or NULL.  All columns share the hierarchy
+ * and leave the solve as they converge.  Returns as ddamg_solve. */
+int ddamg_solve_batch(ddamg_ctx* h, int n_sys, const int* n_rhs, const int* n_shift, const double* mu,
+                      const double* b, double* x, int use_x0, ddamg_col_info* info);
 
 /* Statistics of the last setup / solve. */
 int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);

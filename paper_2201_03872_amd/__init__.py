@@ -62,6 +62,7 @@ class Params(ctypes.Structure):
         ("smoother", ctypes.c_int),
         ("smoother_cycles", ctypes.c_int),
         ("col_tile", ctypes.c_int),
+        ("max_active_cols", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
     ]
@@ -77,6 +78,7 @@ class Stats(ctypes.Structure):
         ("avg_middle_iters", ctypes.c_double), ("avg_bottom_iters", ctypes.c_double),
         ("n_middle_solves", ctypes.c_longlong), ("n_bottom_solves", ctypes.c_longlong),
         ("n_fine_ops", ctypes.c_longlong), ("n_sap_calls", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_int),
+        ("col_removals", ctypes.c_int),
     ]
 
 
@@ -112,6 +114,8 @@ def load():
         "ddamg_get_coarse_op": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "ddamg_level_info": (ctypes.c_int, [vp, ctypes.c_int, ip, ip, ip]),
         "ddamg_solve": (ctypes.c_int, [vp, dp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, P(ColInfo)]),
+        "ddamg_solve_batch": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), dp, vp, vp,
+                                             ctypes.c_int, P(ColInfo)]),
         "ddamg_get_stats": (ctypes.c_int, [vp, P(Stats)]),
         "ddamg_time_op": (ctypes.c_int, [vp] + [ctypes.c_int] * 5 + [dp]),
         "ddamg_set_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
@@ -274,6 +278,31 @@ class Context:
                     allow=(OK, NOT_CONVERGED))
         return x, [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res)
                    for i in info], st
+
+    def solve_batch(self, systems, x0=None):
+        """systems: list of (mus, b) with b a [n_rhs][V][4][3] complex128 CUDA
+        tensor; all systems are solved in one simultaneous batch.  Returns
+        (list of x [n_rhs*n_shift][V][4][3] per system, list of info lists, status)."""
+        import torch
+        n_rhs = [int(b.shape[0]) for _, b in systems]
+        n_shift = [len(np.atleast_1d(m)) for m, _ in systems]
+        mu = np.ascontiguousarray(np.concatenate([np.atleast_1d(np.asarray(m, dtype=np.float64)) for m, _ in systems]))
+        b = torch.cat([bb for _, bb in systems]).contiguous()
+        ncol = sum(r * k for r, k in zip(n_rhs, n_shift))
+        x = x0.clone() if x0 is not None else torch.zeros((ncol,) + tuple(b.shape[1:]), dtype=torch.complex128,
+                                                          device=self.device)
+        info = (ColInfo * ncol)()
+        ir, ik = (ctypes.c_int * len(systems))(*n_rhs), (ctypes.c_int * len(systems))(*n_shift)
+        st = _check(load().ddamg_solve_batch(self.h, len(systems), ir, ik,
+                                             mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _dptr(b), _dptr(x),
+                                             int(x0 is not None), info), allow=(OK, NOT_CONVERGED))
+        xs, infos, o = [], [], 0
+        for r, k in zip(n_rhs, n_shift):
+            xs.append(x[o:o + r * k])
+            infos.append([dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res)
+                          for i in info[o:o + r * k]])
+            o += r * k
+        return xs, infos, st
 
     def stats(self) -> dict:
         s = Stats()

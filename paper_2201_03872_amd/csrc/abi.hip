@@ -14,7 +14,6 @@ void build_sap_lists(ddamg_ctx* c);
 void upload_gauge(ddamg_ctx* c, const double* gauge, int on_device);
 void build_hierarchy(ddamg_ctx* c, const double* const* tv_init);
 void rebuild_from_test_vectors(ddamg_ctx* c, int l, const double* tv_host);
-int solve_internal(ddamg_ctx* c, const double* d_mu, const MV& b, const MV& x, bool x_zero, std::vector<int>& iters);
 void free_work(ddamg_ctx* c);
 void random_fill(ddamg_ctx* c, int level, const MV& X, int ncol, uint64_t seed);
 void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2);
@@ -90,6 +89,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->precision = DDAMG_PLAIN_FP64;
   p->smoother = DDAMG_SMOOTHER_SAP;
   p->smoother_cycles = 1;
+  p->max_active_cols = 0;
   p->col_tile = 8;
   p->seed = 12345;
   p->verbose = 0;
@@ -131,6 +131,7 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->precision == DDAMG_PLAIN_FP64 || p->precision == DDAMG_MIXED, DDAMG_EINVAL, "precision mode");
   DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP || p->smoother == DDAMG_SMOOTHER_LEARNED, DDAMG_EINVAL, "smoother");
   DD_CHECK(p->smoother_cycles >= 1 && p->smoother_cycles <= 64, DDAMG_EINVAL, "smoother_cycles");
+  DD_CHECK(p->max_active_cols >= 0, DDAMG_EINVAL, "max_active_cols");
 }
 
 int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
@@ -323,71 +324,104 @@ int ddamg_set_test_vectors(ddamg_ctx* c, int level, const double* tv) {
   });
 }
 
-// Expand b ([n_rhs] canonical) to columns col = r*n_shift + k in the internal layout.
-static void load_rhs(ddamg_ctx* c, const double* b, int n_rhs, int n_shift, const MV& B) {
-  const LevelGeom& g = c->geom[0];
-  const size_t colbytes = (size_t)g.V * 12 * 2 * sizeof(double);
-  const int ncol = n_rhs * n_shift;
-  double* tmp = (double*)c->pool.alloc(colbytes * ncol);
-  for (int r = 0; r < n_rhs; ++r)
-    for (int k = 0; k < n_shift; ++k)
-      DD_HIP(hipMemcpyAsync((char*)tmp + colbytes * (r * n_shift + k), (const char*)b + colbytes * r, colbytes,
-                            hipMemcpyDeviceToDevice, c->stream));
-  to_internal(c, 0, tmp, ncol, B);
+// Columns the outer solve keeps in flight: params.max_active_cols, or (0)
+// as many as the free device memory holds, at the bytes per column of the
+// FGMRES(m) basis, the preconditioned basis, the ping-pong right-hand sides /
+// solutions and the smoother's temporaries.
+static int active_columns(ddamg_ctx* c, int ncol) {
+  if (c->p.max_active_cols > 0) return std::min(ncol, c->p.max_active_cols);
+  const double col64 = (double)c->geom[0].V * 12 * 16;
+  const int m = std::min(c->p.outer_restart, 63);
+  const double zfac = c->p.precision == DDAMG_MIXED ? 0.5 : 1.0;
+  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8));
+  size_t fre = 0, tot = 0;
+  DD_HIP(hipMemGetInfo(&fre, &tot));
+  const int fit = (int)std::max(8.0, 0.85 * (double)fre / per_col);
+  return std::min(ncol, fit);
+}
+
+// Solve the columns (shift hmu[i], right-hand side b[rhs_of[i]]) together.
+static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std::vector<int>& rhs_of,
+                         const double* b, double* x, int use_x0, ddamg_col_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  c->st.middle_calls = c->st.middle_iters = c->st.bottom_calls = c->st.bottom_iters = 0;
+  c->st.fine_ops = c->st.sap_calls = 0;
+  c->st.learned_fallbacks = 0;
+  c->st.col_removals = 0;
+  const int ncol = (int)hmu.size();
+  for (double m : hmu) DD_CHECK(std::isfinite(m), DDAMG_EINVAL, "twisted mass is NaN/Inf");
+  // NaN guard on the right-hand sides (canonical, one field per distinct rhs)
+  int nb = 0;
+  for (int r : rhs_of) nb = std::max(nb, r + 1);
+  {
+    MV Bc = mv_alloc(c, 0, P64, nb);
+    to_internal(c, 0, b, nb, Bc);
+    double* d_n2 = (double*)c->pool.alloc(Bc.ncol() * sizeof(double));
+    mv_norm2(c, Bc, d_n2);
+    std::vector<double> bn(Bc.ncol());
+    copy_to_host(c, d_n2, bn.data(), bn.size() * sizeof(double));
+    c->pool.release(d_n2);
+    mv_free(c, Bc);
+    for (int i = 0; i < nb; ++i) DD_CHECK(std::isfinite(bn[i]), DDAMG_EINVAL, "right-hand side contains NaN/Inf");
+  }
+  OuterJob job;
+  job.ncol = ncol;
+  job.mu = hmu;
+  job.rhs_of = rhs_of;
+  job.b = b;
+  job.x = x;
+  job.use_x0 = use_x0 != 0;
+  job.max_active = active_columns(c, ncol);
+  outer_solve(c, job);
   DD_HIP(hipStreamSynchronize(c->stream));
-  c->pool.release(tmp);
+  c->st.outer_iters = job.total;
+  int status = DDAMG_OK;
+  for (int i = 0; i < ncol; ++i) {
+    if (!job.converged[i]) status = DDAMG_NOT_CONVERGED;
+    if (info) {
+      info[i].outer_iters = job.iters[i];
+      info[i].converged = job.converged[i];
+      info[i].true_rel_res = job.relres[i];
+    }
+  }
+  c->st.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
 }
 
 int ddamg_solve(ddamg_ctx* c, const double* mu, int n_shift, const double* b, int n_rhs, double* x, int use_x0,
                 ddamg_col_info* info) {
   return guarded([&]() -> int {
     DD_CHECK(c && mu && b && x && n_shift >= 1 && n_rhs >= 1, DDAMG_EINVAL, "null pointer or empty batch");
-    auto t0 = std::chrono::steady_clock::now();
-    c->st.middle_calls = c->st.middle_iters = c->st.bottom_calls = c->st.bottom_iters = 0;
-    c->st.fine_ops = c->st.sap_calls = 0;
-    c->st.learned_fallbacks = 0;
     const int ncol = n_rhs * n_shift;
     std::vector<double> hmu(ncol);
+    std::vector<int> rhs_of(ncol);
     for (int r = 0; r < n_rhs; ++r)
-      for (int k = 0; k < n_shift; ++k) hmu[r * n_shift + k] = mu[k];
-    MV B = mv_alloc(c, 0, P64, ncol), X = mv_alloc(c, 0, P64, ncol);
-    double* d_mu = upload_mu(c, hmu.data(), ncol, B.ncol());
-    load_rhs(c, b, n_rhs, n_shift, B);
-    // NaN guard on the right-hand sides
-    double* d_n2 = (double*)c->pool.alloc(B.ncol() * sizeof(double));
-    mv_norm2(c, B, d_n2);
-    std::vector<double> bn(B.ncol());
-    copy_to_host(c, d_n2, bn.data(), bn.size() * sizeof(double));
-    for (int i = 0; i < ncol; ++i) DD_CHECK(std::isfinite(bn[i]), DDAMG_EINVAL, "right-hand side contains NaN/Inf");
-    if (use_x0) to_internal(c, 0, x, ncol, X);
-    std::vector<int> iters;
-    solve_internal(c, d_mu, B, X, !use_x0, iters);
-    // final FP64 true residual
-    MV R = mv_alloc(c, 0, P64, ncol);
-    fine_residual(c, B, X, R, d_mu);
-    mv_norm2(c, R, d_n2);
-    std::vector<double> rn(B.ncol());
-    copy_to_host(c, d_n2, rn.data(), rn.size() * sizeof(double));
-    from_internal(c, 0, X, ncol, x);
-    DD_HIP(hipStreamSynchronize(c->stream));
-    int status = DDAMG_OK;
-    for (int i = 0; i < ncol; ++i) {
-      const double rel = bn[i] > 0 ? std::sqrt(rn[i] / bn[i]) : 0.0;
-      const int conv = rel <= c->p.tol;
-      if (!conv) status = DDAMG_NOT_CONVERGED;
-      if (info) {
-        info[i].outer_iters = i < (int)iters.size() ? iters[i] : 0;
-        info[i].converged = conv;
-        info[i].true_rel_res = rel;
+      for (int k = 0; k < n_shift; ++k) {
+        hmu[r * n_shift + k] = mu[k];
+        rhs_of[r * n_shift + k] = r;
       }
+    return solve_columns(c, hmu, rhs_of, b, x, use_x0, info);
+  });
+}
+
+int ddamg_solve_batch(ddamg_ctx* c, int n_sys, const int* n_rhs, const int* n_shift, const double* mu,
+                      const double* b, double* x, int use_x0, ddamg_col_info* info) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && n_rhs && n_shift && mu && b && x && n_sys >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    std::vector<double> hmu;
+    std::vector<int> rhs_of;
+    int r0 = 0, k0 = 0;
+    for (int s = 0; s < n_sys; ++s) {
+      DD_CHECK(n_rhs[s] >= 1 && n_shift[s] >= 1, DDAMG_EINVAL, "every system needs a rhs and a shift");
+      for (int r = 0; r < n_rhs[s]; ++r)
+        for (int k = 0; k < n_shift[s]; ++k) {
+          hmu.push_back(mu[k0 + k]);
+          rhs_of.push_back(r0 + r);
+        }
+      r0 += n_rhs[s];
+      k0 += n_shift[s];
     }
-    mv_free(c, B);
-    mv_free(c, X);
-    mv_free(c, R);
-    c->pool.release(d_mu);
-    c->pool.release(d_n2);
-    c->st.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return status;
+    return solve_columns(c, hmu, rhs_of, b, x, use_x0, info);
   });
 }
 
@@ -405,6 +439,7 @@ int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
     s->n_fine_ops = c->st.fine_ops;
     s->n_sap_calls = c->st.sap_calls;
     s->learned_fallbacks = c->st.learned_fallbacks;
+    s->col_removals = c->st.col_removals;
     return DDAMG_OK;
   });
 }

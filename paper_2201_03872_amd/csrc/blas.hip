@@ -153,6 +153,48 @@ void from_internal(ddamg_ctx* c, int level, const MV& in, int n_col, double* can
   DD_HIP(hipGetLastError());
 }
 
+// Column-mapped conversions for the outer solve's scheduler: internal column
+// j of `mv` <-> canonical field map[j] of `canon` ([*][V][dof] complex);
+// columns with map[j] < 0 are left untouched.
+template <typename R>
+__global__ void k_canon_cols(R* __restrict__ in, double* __restrict__ canon, const int* __restrict__ int2can,
+                             const int* __restrict__ map, int n_col, int V, int dof, int T, int dir) {
+  constexpr int RW = Chunk<R>::RW, CPC = RW / 2;
+  const int nchunk = 2 * dof / RW;
+  const size_t total = (size_t)n_col * V * dof;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % dof);
+    const size_t cs = i / dof;
+    const int s = (int)(cs % V);
+    const int col = (int)(cs / V);
+    const int f = map[col];
+    if (f < 0) continue;
+    const int tile = col / T, t = col % T;
+    R* q = in + (size_t)tile * nchunk * V * T * RW + (((size_t)(k / CPC) * V + s) * T + t) * RW + (k % CPC) * 2;
+    double* d = canon + (((size_t)f * V + int2can[s]) * dof + k) * 2;
+    if (dir == 0) {
+      q[0] = (R)d[0];
+      q[1] = (R)d[1];
+    } else {
+      d[0] = (double)q[0];
+      d[1] = (double)q[1];
+    }
+  }
+}
+
+void canon_cols(ddamg_ctx* c, int level, const MV& mv, const int* d_map, double* canon, int dir) {
+  const LevelGeom& g = c->geom[level];
+  DD_CHECK(mv.nsites == g.V && mv.dof == g.dof, DDAMG_EINVAL, "canon_cols: shape");
+  const size_t n = (size_t)mv.ncol() * g.V * g.dof;
+  if (mv.prec == P64)
+    hipLaunchKernelGGL(k_canon_cols<double>, grid_for(n), dim3(256), 0, c->stream, mv.as<double>(), canon,
+                       g.d_int2can, d_map, mv.ncol(), g.V, g.dof, mv.T, dir);
+  else
+    hipLaunchKernelGGL(k_canon_cols<float>, grid_for(n), dim3(256), 0, c->stream, mv.as<float>(), canon,
+                       g.d_int2can, d_map, mv.ncol(), g.V, g.dof, mv.T, dir);
+  DD_HIP(hipGetLastError());
+}
+
 // -------------------------------------------------- elementwise ops ---
 // Every lane handles one real pair (complex) of one column; column index of
 // real i in a tile: t = (i / RW) % T.
@@ -160,6 +202,38 @@ template <typename RS, typename RD>
 __global__ void k_copy(const RS* __restrict__ a, RD* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     b[i] = (RD)a[i];
+}
+
+// Column gather / scatter between a full multivector and a compacted one of
+// the same level and precision.  map[j] (j < compact.ncol()) is the full
+// column of compact slot j, or -1 for an empty slot.  dir 0: compact <- full
+// (empty slots zeroed); dir 1: full <- compact (empty slots skipped, other
+// full columns untouched).  One thread per 16-byte chunk of a compact slot.
+__global__ void k_gather_cols(uint4* __restrict__ full, uint4* __restrict__ comp, const int* __restrict__ map,
+                              size_t units_per_tile, size_t n_units, int T, int dir) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_units; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t tile = i / units_per_tile, rem = i % units_per_tile;
+    const int t = (int)(rem % T);
+    const size_t base = rem - t;                                  // (chunk, site) unit of slot 0
+    const int col = map[tile * T + t];
+    if (col < 0) {
+      if (dir == 0) comp[i] = make_uint4(0, 0, 0, 0);
+      continue;
+    }
+    const size_t f = (size_t)(col / T) * units_per_tile + base + col % T;
+    if (dir == 0) comp[i] = full[f];
+    else full[f] = comp[i];
+  }
+}
+
+void mv_gather_cols(ddamg_ctx* c, const MV& full, const MV& comp, const int* d_map, int dir) {
+  DD_CHECK(full.prec == comp.prec && full.nsites == comp.nsites && full.nchunk == comp.nchunk && full.T == comp.T,
+           DDAMG_EINVAL, "column gather: shapes");
+  const size_t upt = (size_t)comp.nchunk * comp.nsites * comp.T;
+  const size_t n = upt * comp.ntiles;
+  hipLaunchKernelGGL(k_gather_cols, grid_for(n), dim3(256), 0, c->stream, (uint4*)full.p, (uint4*)comp.p, d_map, upt,
+                     n, comp.T, dir);
+  DD_HIP(hipGetLastError());
 }
 
 // Plain device copy kernel (reads and writes a.bytes()); calibrates the

@@ -122,6 +122,7 @@ struct Stats {
   long long middle_calls = 0, middle_iters = 0, bottom_calls = 0, bottom_iters = 0;
   long long fine_ops = 0, sap_calls = 0;
   int learned_fallbacks = 0;
+  int col_removals = 0;
 };
 
 }  // namespace ddamg
@@ -169,6 +170,7 @@ void mv_scale(ddamg_ctx* c, const double* d_alpha, const MV& x);  // x *= alpha_
 void mv_sub(ddamg_ctx* c, const MV& a, const MV& b, const MV& out);   // out = a - b
 void mv_add(ddamg_ctx* c, const MV& x, const MV& y);                  // y += x
 void mv_copy_kernel(ddamg_ctx* c, const MV& s, const MV& d);          // plain copy kernel
+void mv_gather_cols(ddamg_ctx* c, const MV& full, const MV& comp, const int* d_map, int dir);
 // per-column complex dots <V_j, w> for j < k, written to d_out[j*ncol + c] (complex)
 void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out);
 // w -= sum_j coef[j*ncol+c] V_j   (coef complex, device)
@@ -179,6 +181,8 @@ void mv_dot(ddamg_ctx* c, const MV& a, const MV& b, double* d_out);  // per colu
 // canonical <-> internal conversion (fine or coarse level)
 void to_internal(ddamg_ctx* c, int level, const double* canon, int n_col, const MV& out);
 void from_internal(ddamg_ctx* c, int level, const MV& in, int n_col, double* canon);
+// dir 0: mv column j <- canon field map[j]; dir 1: canon field map[j] <- mv column j (map[j] < 0: skipped)
+void canon_cols(ddamg_ctx* c, int level, const MV& mv, const int* d_map, double* canon, int dir);
 
 // ---- fine-level kernels (fine.hip) ----
 void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu);
@@ -212,6 +216,25 @@ void ptc_train(ddamg_ctx* c, const double* mus, int n_mu, int steps, int batch, 
 void free_ptc(ddamg_ctx* c);
 // fine-level smoother of the preconditioner: SAP, or the learned network with SAP fallback
 void fine_smoother(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu);
+
+// A batch of fine-level systems for the outer solve: column i has shift mu[i],
+// right-hand side field rhs_of[i] of b and solution field i of x (canonical
+// layout, device).  At most max_active columns are in flight at once.
+struct OuterJob {
+  int ncol = 0;
+  std::vector<double> mu;
+  std::vector<int> rhs_of;
+  const double* b = nullptr;
+  double* x = nullptr;
+  bool use_x0 = false;
+  int max_active = 0;
+  // results per column
+  std::vector<int> iters;
+  std::vector<double> relres;   // true FP64 relative residual when the column left
+  std::vector<char> converged;
+  int total = 0;                // outer iterations (cycles x steps) of the whole batch
+};
+void outer_solve(ddamg_ctx* c, OuterJob& job);
 
 // ---- host helpers ----
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);

@@ -26,7 +26,7 @@ void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, in
 void random_fill(ddamg_ctx* c, int level, const MV& X, int ncol, uint64_t seed);
 
 using cd = std::complex<double>;
-using Precond = std::function<void(const MV& v, const MV& z)>;
+using Precond = std::function<void(const MV& v, const MV& z, const double* d_mu)>;
 constexpr int KMAX = 64;
 
 // ------------------------------------------------------------ kernels ---
@@ -74,8 +74,11 @@ struct LW {
   int prec = 0;
   std::vector<MV> V, Z;
   MV zt, rc, ec, res, s, q, rho;
+  MV cb, cx, cb2, cx2;           // outer solve: active right-hand sides / solutions (ping-pong)
   double* d_h = nullptr;         // [KMAX][ncol] complex dots + [ncol] norm
   double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
+  int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
+  double* d_muc = nullptr;       // [ncol] shifts of the active columns
 };
 
 struct Work {
@@ -97,12 +100,16 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles) {
   if (ntiles > w.cap) {
     for (auto& m : w.V) mv_free(c, m);
     for (auto& m : w.Z) mv_free(c, m);
-    MV* all[] = {&w.zt, &w.rc, &w.ec, &w.res, &w.s, &w.q, &w.rho};
+    MV* all[] = {&w.zt, &w.rc, &w.ec, &w.res, &w.s, &w.q, &w.rho, &w.cb, &w.cx, &w.cb2, &w.cx2};
     for (MV* m : all) mv_free(c, *m);
     w.V.clear();
     w.Z.clear();
     if (w.d_h) c->pool.release(w.d_h);
     if (w.d_aux) c->pool.release(w.d_aux);
+    if (w.d_map) c->pool.release(w.d_map);
+    if (w.d_muc) c->pool.release(w.d_muc);
+    w.d_map = nullptr;
+    w.d_muc = nullptr;
     w.cap = ntiles;
     w.prec = prec;
     const int ncol = ntiles * c->T;
@@ -131,17 +138,183 @@ struct KrylovOut {
 
 static double host_norm_guard(double v) { return v > 0 ? std::sqrt(v) : 0.0; }
 
+// Host-side state of one restarted (F)GMRES cycle over ncol lockstep columns:
+// Hessenberg matrices, Givens rotations and right-hand sides per column.
+struct Cycle {
+  int m = 0;
+  std::vector<cd> H, g, sn;
+  std::vector<double> cs, hbuf, coef;
+  std::vector<int> kc;          // Arnoldi steps used per column (-1: all of the cycle)
+  Cycle(int ncol, int m_) : m(m_), H((size_t)ncol * (m_ + 1) * m_), g((size_t)ncol * (m_ + 1)), sn((size_t)ncol * m_),
+                            cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol) {}
+};
+
+// One (F)GMRES cycle on the first nt tiles of the level's workspace: V[0]
+// holds the residual r with per-column norms beta (host; d_n2 holds their
+// squares).  Up to min(m, budget) Arnoldi steps with classical Gram-Schmidt
+// (one fused multi-dot and multi-axpy per step, section 4), per-column Givens
+// least squares on the host, then x += Z y (or V y).  Columns flagged done take
+// no step; a column whose estimate meets tol_abs stops at that step.  Returns
+// the number of steps; cy.kc[i] the steps that entered column i's update.
+static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, const double* d_mu, const Precond* pc,
+                       int zprec, int budget, bool fixed, const std::vector<double>& beta, std::vector<char>& done,
+                       const std::vector<double>& tol_abs, std::vector<double>& est, const std::vector<double>& bn,
+                       Cycle& cy, double* d_n2, int& total) {
+  const int prec = x.prec, ncol = nt * c->T, cap = w.cap, m = cy.m;
+  MV r = basis(c, w.V, 0, level, prec, cap, nt);
+  mv_normalize(c, r, d_n2);
+  for (int i = 0; i < ncol; ++i) {
+    cy.kc[i] = done[i] ? 0 : -1;
+    for (int j = 0; j <= m; ++j) cy.g[(size_t)i * (m + 1) + j] = 0;
+    cy.g[(size_t)i * (m + 1)] = beta[i];
+  }
+  int jj = 0;
+  for (int j = 0; j < m && j < budget; ++j) {
+    MV vj = basis(c, w.V, j, level, prec, cap, nt);
+    MV z = vj;
+    if (pc) {
+      z = basis(c, w.Z, j, level, zprec, cap, nt);
+      (*pc)(vj, z, d_mu);
+    }
+    MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
+    if (z.prec != prec) {
+      MV zt = get(c, w.zt, level, prec, cap, nt);
+      mv_copy(c, z, zt);
+      operator_apply(c, level, zt, vn, d_mu);
+    } else {
+      operator_apply(c, level, z, vn, d_mu);
+    }
+    std::vector<MV> Vs(j + 1);
+    for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
+    mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
+    mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
+    mv_norm2(c, vn, d_n2);
+    // one copy of the dots and the norm
+    const size_t nh = (size_t)(j + 1) * ncol * 2;
+    copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
+    copy_to_host(c, d_n2, cy.hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
+    mv_normalize(c, vn, d_n2);
+    ++total;
+    jj = j + 1;
+    bool alld = true;
+    for (int i = 0; i < ncol; ++i) {
+      cd* Hc = &cy.H[(size_t)i * (m + 1) * m];
+      for (int q = 0; q <= j; ++q)
+        Hc[(size_t)q * m + j] = cd(cy.hbuf[((size_t)q * ncol + i) * 2], cy.hbuf[((size_t)q * ncol + i) * 2 + 1]);
+      const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+      Hc[(size_t)(j + 1) * m + j] = hn;
+      if (done[i] && cy.kc[i] >= 0) continue;
+      // apply the previous rotations to column j
+      for (int q = 0; q < j; ++q) {
+        const cd a = Hc[(size_t)q * m + j], bb = Hc[(size_t)(q + 1) * m + j];
+        const double cq = cy.cs[(size_t)i * m + q];
+        const cd sq = cy.sn[(size_t)i * m + q];
+        Hc[(size_t)q * m + j] = cq * a + sq * bb;
+        Hc[(size_t)(q + 1) * m + j] = -std::conj(sq) * a + cq * bb;
+      }
+      const cd a = Hc[(size_t)j * m + j], bb = Hc[(size_t)(j + 1) * m + j];
+      double cc;
+      cd ss, rr;
+      if (std::abs(bb) == 0) { cc = 1; ss = 0; rr = a; }
+      else if (std::abs(a) == 0) { cc = 0; ss = std::conj(bb) / std::abs(bb); rr = std::abs(bb); }
+      else {
+        const double na = std::abs(a), nr = std::hypot(na, std::abs(bb));
+        cc = na / nr;
+        ss = (a / na) * std::conj(bb) / nr;
+        rr = (a / na) * nr;
+      }
+      cy.cs[(size_t)i * m + j] = cc;
+      cy.sn[(size_t)i * m + j] = ss;
+      Hc[(size_t)j * m + j] = rr;
+      Hc[(size_t)(j + 1) * m + j] = 0;
+      cd* gc = &cy.g[(size_t)i * (m + 1)];
+      const cd gj = gc[j];
+      gc[j] = cc * gj;
+      gc[j + 1] = -std::conj(ss) * gj;
+      est[i] = std::abs(gc[j + 1]);
+      if (!fixed && (est[i] <= tol_abs[i] || hn == 0)) {
+        done[i] = 1;
+        cy.kc[i] = j + 1;
+      }
+      if (!done[i]) alld = false;
+    }
+    if (c->p.verbose && level == 0) {
+      double mx = 0;
+      int nact = 0;
+      for (int i = 0; i < ncol; ++i)
+        if (bn[i] > 0) {
+          mx = std::max(mx, est[i] / bn[i]);
+          nact += !done[i];
+        }
+      std::fprintf(stderr, "[ddamg] outer %d: max rel. residual estimate %.3e, %d columns active, "
+                   "middle calls %lld (avg %.1f it), bottom calls %lld (avg %.1f it)\n", total, mx, nact,
+                   c->st.middle_calls, c->st.middle_calls ? (double)c->st.middle_iters / c->st.middle_calls : 0.0,
+                   c->st.bottom_calls, c->st.bottom_calls ? (double)c->st.bottom_iters / c->st.bottom_calls : 0.0);
+      std::fflush(stderr);
+    }
+    if (!fixed && alld) break;
+  }
+  // per-column least squares and the update x += basis * y
+  cy.coef.assign((size_t)jj * ncol * 2, 0.0);
+  for (int i = 0; i < ncol; ++i) {
+    const int k = cy.kc[i] >= 0 ? cy.kc[i] : jj;
+    cy.kc[i] = k;
+    if (k == 0) continue;
+    const cd* Hc = &cy.H[(size_t)i * (m + 1) * m];
+    const cd* gc = &cy.g[(size_t)i * (m + 1)];
+    std::vector<cd> y(k);
+    for (int q = k - 1; q >= 0; --q) {
+      cd acc = gc[q];
+      for (int p = q + 1; p < k; ++p) acc -= Hc[(size_t)q * m + p] * y[p];
+      const cd d = Hc[(size_t)q * m + q];
+      y[q] = std::abs(d) > 0 ? acc / d : cd(0);
+    }
+    for (int q = 0; q < k; ++q) {
+      cy.coef[((size_t)q * ncol + i) * 2] = y[q].real();
+      cy.coef[((size_t)q * ncol + i) * 2 + 1] = y[q].imag();
+    }
+  }
+  if (jj > 0) {
+    DD_HIP(hipMemcpyAsync(w.d_aux, cy.coef.data(), cy.coef.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+    std::vector<MV> B(jj);
+    for (int q = 0; q < jj; ++q)
+      B[q] = pc ? basis(c, w.Z, q, level, zprec, cap, nt) : basis(c, w.V, q, level, prec, cap, nt);
+    mv_multiaxpy(c, B.data(), jj, w.d_aux, x, +1);
+    DD_HIP(hipStreamSynchronize(c->stream));   // coef is a host vector reused next cycle
+  }
+  return jj;
+}
+
+// r = b - A x into V[0] of the workspace; beta (host) = column norms, d_n2 their squares
+static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, const MV& x, const double* d_mu,
+                           bool x_is_zero, double* d_n2, std::vector<double>& beta) {
+  const int prec = b.prec, ncol = nt * c->T;
+  MV r = basis(c, w.V, 0, level, prec, w.cap, nt);
+  if (x_is_zero) {
+    mv_copy(c, b, r);
+  } else if (level == 0) {
+    fine_residual(c, b, x, r, d_mu);
+  } else {
+    MV t = get(c, w.res, level, prec, w.cap, nt);
+    operator_apply(c, level, x, t, d_mu);
+    mv_sub(c, b, t, r);
+  }
+  mv_norm2(c, r, d_n2);
+  beta.resize(ncol);
+  copy_to_host(c, d_n2, beta.data(), ncol * sizeof(double));
+  for (int i = 0; i < ncol; ++i) beta[i] = host_norm_guard(beta[i]);
+}
+
 // (F)GMRES(m) on level `level` for all columns of b (precision of b/x);
 // preconditioner output precision zprec.  x holds the initial guess unless
 // x_zero.  fixed: run exactly maxit iterations without a convergence test.
 void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero, double tol, int m,
             int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out) {
-  const int nt = b.ntiles, ncol = b.ncol(), prec = b.prec;
+  const int nt = b.ntiles, ncol = b.ncol();
   DD_CHECK(m >= 1 && m < KMAX, DDAMG_EINVAL, "Krylov restart length must be in [1, 63]");
-  LW& w = lw(c, level, prec, nt);
-  const int cap = w.cap;
-  std::vector<double> hbuf((size_t)KMAX * ncol * 2 + ncol);
-  std::vector<double> bn(ncol), tol_abs(ncol), est(ncol);
+  LW& w = lw(c, level, b.prec, nt);
+  std::vector<double> bn(ncol), tol_abs(ncol), est(ncol), beta;
   double* d_n2 = w.d_h + (size_t)KMAX * ncol * 2;
   mv_norm2(c, b, d_n2);
   copy_to_host(c, d_n2, bn.data(), ncol * sizeof(double));
@@ -153,158 +326,24 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
     est[i] = bn[i];
   }
   std::vector<int> iters(ncol, 0);
-  std::vector<cd> H((size_t)ncol * (m + 1) * m), g((size_t)ncol * (m + 1)), sn((size_t)ncol * m);
-  std::vector<double> cs((size_t)ncol * m);
-  std::vector<int> kc(ncol);
-  std::vector<double> coef;
+  Cycle cy(ncol, m);
   int total = 0;
   bool first = true;
   if (x_zero) mv_zero(c, x);
   while (true) {
-    MV r = basis(c, w.V, 0, level, prec, cap, nt);
-    if (x_zero && first) {
-      mv_copy(c, b, r);
-    } else {
-      MV t = get(c, w.res, level, prec, cap, nt);
-      if (level == 0 && prec == b.prec) fine_residual(c, b, x, r, d_mu);
-      else {
-        operator_apply(c, level, x, t, d_mu);
-        mv_sub(c, b, t, r);
-      }
-    }
+    residual_norms(c, level, w, nt, b, x, d_mu, x_zero && first, d_n2, beta);
     first = false;
-    std::vector<double> beta(ncol);
-    mv_norm2(c, r, d_n2);
-    copy_to_host(c, d_n2, beta.data(), ncol * sizeof(double));
     bool all = true;
     for (int i = 0; i < ncol; ++i) {
-      beta[i] = host_norm_guard(beta[i]);
       est[i] = beta[i];
       if (!fixed && beta[i] <= tol_abs[i]) done[i] = 1;
       if (bn[i] == 0) done[i] = 1;
       if (!done[i]) all = false;
     }
     if ((all && !fixed) || total >= maxit) break;
-    mv_normalize(c, r, d_n2);
-    for (int i = 0; i < ncol; ++i) {
-      kc[i] = done[i] ? 0 : -1;
-      for (int j = 0; j <= m; ++j) g[(size_t)i * (m + 1) + j] = 0;
-      g[(size_t)i * (m + 1)] = beta[i];
-    }
-    int jj = 0;
-    for (int j = 0; j < m && total < maxit; ++j) {
-      MV vj = basis(c, w.V, j, level, prec, cap, nt);
-      MV z = vj;
-      if (pc) {
-        z = basis(c, w.Z, j, level, zprec, cap, nt);
-        (*pc)(vj, z);
-      }
-      MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
-      if (z.prec != prec) {
-        MV zt = get(c, w.zt, level, prec, cap, nt);
-        mv_copy(c, z, zt);
-        operator_apply(c, level, zt, vn, d_mu);
-      } else {
-        operator_apply(c, level, z, vn, d_mu);
-      }
-      std::vector<MV> Vs(j + 1);
-      for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
-      mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
-      mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
-      mv_norm2(c, vn, d_n2);
-      // one copy of the dots and the norm
-      const size_t nh = (size_t)(j + 1) * ncol * 2;
-      copy_to_host(c, w.d_h, hbuf.data(), nh * sizeof(double));
-      copy_to_host(c, d_n2, hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
-      mv_normalize(c, vn, d_n2);
-      ++total;
-      jj = j + 1;
-      bool alld = true;
-      for (int i = 0; i < ncol; ++i) {
-        cd* Hc = &H[(size_t)i * (m + 1) * m];
-        for (int q = 0; q <= j; ++q)
-          Hc[(size_t)q * m + j] = cd(hbuf[((size_t)q * ncol + i) * 2], hbuf[((size_t)q * ncol + i) * 2 + 1]);
-        const double hn = host_norm_guard(hbuf[(size_t)KMAX * ncol * 2 + i]);
-        Hc[(size_t)(j + 1) * m + j] = hn;
-        if (done[i] && kc[i] >= 0) continue;
-        // apply the previous rotations to column j
-        for (int q = 0; q < j; ++q) {
-          const cd a = Hc[(size_t)q * m + j], bb = Hc[(size_t)(q + 1) * m + j];
-          const double cq = cs[(size_t)i * m + q];
-          const cd sq = sn[(size_t)i * m + q];
-          Hc[(size_t)q * m + j] = cq * a + sq * bb;
-          Hc[(size_t)(q + 1) * m + j] = -std::conj(sq) * a + cq * bb;
-        }
-        const cd a = Hc[(size_t)j * m + j], bb = Hc[(size_t)(j + 1) * m + j];
-        double cc;
-        cd ss, rr;
-        if (std::abs(bb) == 0) { cc = 1; ss = 0; rr = a; }
-        else if (std::abs(a) == 0) { cc = 0; ss = std::conj(bb) / std::abs(bb); rr = std::abs(bb); }
-        else {
-          const double na = std::abs(a), nr = std::hypot(na, std::abs(bb));
-          cc = na / nr;
-          ss = (a / na) * std::conj(bb) / nr;
-          rr = (a / na) * nr;
-        }
-        cs[(size_t)i * m + j] = cc;
-        sn[(size_t)i * m + j] = ss;
-        Hc[(size_t)j * m + j] = rr;
-        Hc[(size_t)(j + 1) * m + j] = 0;
-        cd* gc = &g[(size_t)i * (m + 1)];
-        const cd gj = gc[j];
-        gc[j] = cc * gj;
-        gc[j + 1] = -std::conj(ss) * gj;
-        est[i] = std::abs(gc[j + 1]);
-        if (!fixed && (est[i] <= tol_abs[i] || hn == 0)) {
-          done[i] = 1;
-          kc[i] = j + 1;
-        }
-        if (!done[i]) alld = false;
-      }
-      if (c->p.verbose && level == 0) {
-        double mx = 0;
-        int nact = 0;
-        for (int i = 0; i < ncol; ++i)
-          if (bn[i] > 0) {
-            mx = std::max(mx, est[i] / bn[i]);
-            nact += !done[i];
-          }
-        std::fprintf(stderr, "[ddamg] outer %d: max rel. residual estimate %.3e, %d columns active, "
-                     "middle calls %lld (avg %.1f it), bottom calls %lld (avg %.1f it)\n", total, mx, nact,
-                     c->st.middle_calls, c->st.middle_calls ? (double)c->st.middle_iters / c->st.middle_calls : 0.0,
-                     c->st.bottom_calls, c->st.bottom_calls ? (double)c->st.bottom_iters / c->st.bottom_calls : 0.0);
-        std::fflush(stderr);
-      }
-      if (!fixed && alld) break;
-    }
-    // per-column least squares and the update x += basis * y
-    coef.assign((size_t)jj * ncol * 2, 0.0);
-    for (int i = 0; i < ncol; ++i) {
-      const int k = kc[i] >= 0 ? kc[i] : jj;
-      if (k == 0) continue;
-      const cd* Hc = &H[(size_t)i * (m + 1) * m];
-      const cd* gc = &g[(size_t)i * (m + 1)];
-      std::vector<cd> y(k);
-      for (int q = k - 1; q >= 0; --q) {
-        cd acc = gc[q];
-        for (int p = q + 1; p < k; ++p) acc -= Hc[(size_t)q * m + p] * y[p];
-        const cd d = Hc[(size_t)q * m + q];
-        y[q] = std::abs(d) > 0 ? acc / d : cd(0);
-      }
-      for (int q = 0; q < k; ++q) {
-        coef[((size_t)q * ncol + i) * 2] = y[q].real();
-        coef[((size_t)q * ncol + i) * 2 + 1] = y[q].imag();
-      }
-      iters[i] += k;
-      if (kc[i] < 0) kc[i] = jj;
-    }
-    if (jj > 0) {
-      DD_HIP(hipMemcpyAsync(w.d_aux, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-      std::vector<MV> B(jj);
-      for (int q = 0; q < jj; ++q) B[q] = pc ? basis(c, w.Z, q, level, zprec, cap, nt) : basis(c, w.V, q, level, prec, cap, nt);
-      mv_multiaxpy(c, B.data(), jj, w.d_aux, x, +1);
-      DD_HIP(hipStreamSynchronize(c->stream));   // coef is a host vector reused next cycle
-    }
+    gmres_cycle(c, level, w, nt, x, d_mu, pc, zprec, maxit - total, fixed, beta, done, tol_abs, est, bn, cy, d_n2,
+                total);
+    for (int i = 0; i < ncol; ++i) iters[i] += cy.kc[i];
     bool all2 = true;
     for (int i = 0; i < ncol; ++i)
       if (!done[i]) all2 = false;
@@ -316,6 +355,179 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
     for (int i = 0; i < ncol; ++i) out->relres[i] = bn[i] > 0 ? est[i] / bn[i] : 0.0;
     out->total = total;
   }
+}
+
+// ------------------------------------------------------- outer solve ---
+void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e);
+
+// The top-level FP64 flexible GMRES over a batch of columns (column i: shift
+// mu[i], right-hand side field rhs_of[i] of b, solution field i of x, both in
+// the canonical layout on the device).  A scheduler keeps at most `max_active`
+// columns in the internal layout at once.  At every restart the true FP64
+// residual of each active column is recomputed; columns that meet tol (or
+// have used max_outer iterations) write their solution back and leave, and
+// waiting columns take their place.  When the membership changes, the active
+// columns are gathered into dense tiles (ping-pong buffers), so converged
+// columns cost nothing afterwards (section 3: shrinking the vector bundle).
+void outer_solve(ddamg_ctx* c, OuterJob& job) {
+  const int T = c->T, ncol = job.ncol;
+  const int m = std::min(c->p.outer_restart, KMAX - 1);
+  const int wmax = std::max(1, std::min(ncol, job.max_active));
+  const int ntw = (wmax + T - 1) / T;
+  const int prec = c->p.precision == DDAMG_MIXED ? P32 : P64;
+  LW& w = lw(c, 0, P64, ntw);
+  LW& w0 = lw(c, 0, prec, ntw);   // preconditioner-precision temporaries on level 0
+  const int cap = w.cap;
+  if (!w.d_map) {
+    w.d_map = (int*)c->pool.alloc((size_t)cap * T * 3 * sizeof(int));
+    w.d_muc = (double*)c->pool.alloc((size_t)cap * T * sizeof(double));
+  }
+  MV Bs[2] = {get(c, w.cb, 0, P64, cap, ntw), get(c, w.cb2, 0, P64, cap, ntw)};
+  MV Xs[2] = {get(c, w.cx, 0, P64, cap, ntw), get(c, w.cx2, 0, P64, cap, ntw)};
+  MV vin = get(c, w0.rho, 0, prec, w0.cap, ntw);
+  Precond pc = [&](const MV& v, const MV& z, const double* dm) {
+    const MV in = (prec == v.prec) ? v : vin.tiles(0, v.ntiles);
+    if (prec != v.prec) mv_copy(c, v, in);
+    if (c->nlev == 1) fine_smoother(c, in, z, dm);
+    else mg_cycle(c, 0, dm, in, z);
+  };
+  job.iters.assign(ncol, 0);
+  job.relres.assign(ncol, 0.0);
+  job.converged.assign(ncol, 0);
+  std::vector<double> bnorm(ncol, -1.0);
+  std::vector<int> act;            // slot -> column (-1: empty)
+  int next = 0, cur = 0, nt = 0, total = 0;
+  double* d_n2 = w.d_h + (size_t)KMAX * cap * T * 2;
+  Cycle cy(cap * T, m);
+  std::vector<double> beta, bn, tol_abs, est;
+  std::vector<char> done;
+  std::vector<char> leave;
+  bool rebuild = true;
+  while (true) {
+    if (rebuild) {
+      // new membership: kept columns first, then waiting ones, in dense tiles
+      std::vector<int> nact, keep_map, b_map, x_map;
+      for (int i = 0; i < (int)act.size(); ++i)
+        if (act[i] >= 0 && !(i < (int)leave.size() && leave[i])) {
+          nact.push_back(act[i]);
+          keep_map.push_back(i);
+        }
+      const int nkeep = (int)nact.size();
+      while ((int)nact.size() < wmax && next < ncol) {
+        nact.push_back(next++);
+        keep_map.push_back(-1);
+      }
+      if (nact.empty()) break;
+      const int ntn = ((int)nact.size() + T - 1) / T;
+      nact.resize(ntn * T, -1);
+      keep_map.resize(ntn * T, -1);
+      b_map.assign(ntn * T, -1);
+      x_map.assign(ntn * T, -1);
+      std::vector<double> nmu(ntn * T, 0.0);
+      for (int i = 0; i < ntn * T; ++i) {
+        if (nact[i] < 0) continue;
+        nmu[i] = job.mu[nact[i]];
+        if (i >= nkeep) {
+          b_map[i] = job.rhs_of[nact[i]];
+          if (job.use_x0) x_map[i] = nact[i];
+        }
+      }
+      int* d_keep = w.d_map;
+      int* d_bmap = w.d_map + cap * T;
+      int* d_xmap = w.d_map + 2 * cap * T;
+      DD_HIP(hipMemcpyAsync(d_keep, keep_map.data(), ntn * T * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      DD_HIP(hipMemcpyAsync(d_bmap, b_map.data(), ntn * T * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      DD_HIP(hipMemcpyAsync(d_xmap, x_map.data(), ntn * T * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      DD_HIP(hipMemcpyAsync(w.d_muc, nmu.data(), ntn * T * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      const int alt = act.empty() ? cur : 1 - cur;
+      const MV nb = Bs[alt].tiles(0, ntn), nx = Xs[alt].tiles(0, ntn);
+      if (act.empty()) {
+        mv_zero(c, nb);
+        mv_zero(c, nx);
+      } else {
+        // kept columns move from the current buffers (empty slots become zero)
+        const MV ob = Bs[cur].tiles(0, nt), ox = Xs[cur].tiles(0, nt);
+        mv_gather_cols(c, ob, nb, d_keep, 0);
+        mv_gather_cols(c, ox, nx, d_keep, 0);
+      }
+      canon_cols(c, 0, nb, d_bmap, const_cast<double*>(job.b), 0);
+      if (job.use_x0) canon_cols(c, 0, nx, d_xmap, job.x, 0);
+      DD_HIP(hipStreamSynchronize(c->stream));   // the host maps above are reused
+      if (!act.empty()) c->st.col_removals++;
+      act = nact;
+      cur = alt;
+      nt = ntn;
+      const int nc = nt * T;
+      // right-hand-side norms of the new columns
+      std::vector<double> bn2(nc);
+      mv_norm2(c, nb, d_n2);
+      copy_to_host(c, d_n2, bn2.data(), nc * sizeof(double));
+      bn.assign(nc, 0.0);
+      tol_abs.assign(nc, 0.0);
+      for (int i = 0; i < nc; ++i) {
+        if (act[i] < 0) continue;
+        if (bnorm[act[i]] < 0) bnorm[act[i]] = host_norm_guard(bn2[i]);
+        bn[i] = bnorm[act[i]];
+        tol_abs[i] = c->p.tol * bn[i];
+      }
+      est.assign(nc, 0.0);
+      done.assign(nc, 0);
+      leave.assign(nc, 0);
+      rebuild = false;
+      if (c->p.verbose) {
+        std::fprintf(stderr, "[ddamg] outer %d: %d columns active in %d tiles, %d waiting\n", total,
+                     (int)(act.size() - std::count(act.begin(), act.end(), -1)), nt, ncol - next);
+        std::fflush(stderr);
+      }
+    }
+    const MV b = Bs[cur].tiles(0, nt), x = Xs[cur].tiles(0, nt);
+    const int nc = nt * T;
+    residual_norms(c, 0, w, nt, b, x, w.d_muc, false, d_n2, beta);
+    bool any_leave = false;
+    for (int i = 0; i < nc; ++i) {
+      est[i] = beta[i];
+      if (act[i] < 0) {
+        done[i] = 1;
+        continue;
+      }
+      const int col = act[i];
+      const bool conv = bn[i] == 0 || beta[i] <= tol_abs[i];
+      job.relres[col] = bn[i] > 0 ? beta[i] / bn[i] : 0.0;
+      job.converged[col] = conv;
+      done[i] = 0;
+      if (conv || job.iters[col] >= c->p.max_outer) {
+        leave[i] = 1;
+        any_leave = true;
+      }
+    }
+    if (any_leave) {
+      // solutions of the leaving columns go back to the caller's x
+      std::vector<int> out_map(nc, -1);
+      for (int i = 0; i < nc; ++i)
+        if (leave[i]) out_map[i] = act[i];
+      int* d_out = w.d_map + cap * T;
+      DD_HIP(hipMemcpyAsync(d_out, out_map.data(), nc * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      canon_cols(c, 0, x, d_out, job.x, 1);
+      DD_HIP(hipStreamSynchronize(c->stream));
+    }
+    int n_stay = 0;
+    for (int i = 0; i < nc; ++i) n_stay += act[i] >= 0 && !leave[i];
+    if (any_leave && (next < ncol || n_stay == 0 || (n_stay + T - 1) / T < nt)) {
+      rebuild = true;   // compact (and refill) before the next cycle
+      continue;
+    }
+    if (n_stay == 0) break;
+    for (int i = 0; i < nc; ++i)
+      if (leave[i]) {   // left, but no tile to gain: carried as a finished slot
+        done[i] = 1;
+        act[i] = -1;
+        leave[i] = 0;
+      }
+    gmres_cycle(c, 0, w, nt, x, w.d_muc, &pc, prec, m, false, beta, done, tol_abs, est, bn, cy, d_n2, total);
+    for (int i = 0; i < nc; ++i)
+      if (act[i] >= 0) job.iters[act[i]] += cy.kc[i];
+  }
+  job.total = total;
 }
 
 // --------------------------------------------------------------- MG ---
@@ -357,7 +569,7 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
     for (int i : ko.iters) mx = std::max(mx, i);
     c->st.bottom_iters += ko.total;
   } else {
-    Precond pc = [&](const MV& v, const MV& z) { mg_cycle(c, l + 1, d_mu, v, z); };
+    Precond pc = [&](const MV& v, const MV& z, const double* dm) { mg_cycle(c, l + 1, dm, v, z); };
     krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_m, std::min(c->p.middle_restart, KMAX - 1), c->p.middle_maxit, &pc,
            prec, false, &ko);
     c->st.middle_calls++;
@@ -467,12 +679,12 @@ void setup_transition(ddamg_ctx* c, int l, const double* tv_init_host) {
       const int sp = c->p.precision == DDAMG_MIXED ? P32 : P64;
       LW& ws = lw(c, 0, sp, tv.ntiles);
       MV vin = get(c, ws.rho, 0, sp, ws.cap, tv.ntiles);
-      Precond pc = [&](const MV& v, const MV& z) {
+      Precond pc = [&](const MV& v, const MV& z, const double* dm) {
         if (sp != v.prec) {
           mv_copy(c, v, vin);
-          sap_apply(c, vin, z, d_mu, z);
+          sap_apply(c, vin, z, dm, z);
         } else {
-          sap_apply(c, v, z, d_mu, z);
+          sap_apply(c, v, z, dm, z);
         }
       };
       krylov(c, 0, d_mu, tv, tmp, true, 0.0, c->p.setup_fine_iters, c->p.setup_fine_iters, &pc, sp, true, nullptr);
@@ -548,23 +760,5 @@ void rebuild_from_test_vectors(ddamg_ctx* c, int l, const double* tv_host) {
 // ------------------------------------------------------------- solve ---
 // Outer FP64 FGMRES over all columns, preconditioned by the MG cycle in the
 // precision of the chosen mode.
-int solve_internal(ddamg_ctx* c, const double* d_mu, const MV& b, const MV& x, bool x_zero, std::vector<int>& iters) {
-  const int prec = c->p.precision == DDAMG_MIXED ? P32 : P64;
-  const int nt = b.ntiles;
-  LW& w0 = lw(c, 0, prec, nt);   // preconditioner-precision temporaries on level 0
-  MV vin = get(c, w0.rho, 0, prec, w0.cap, nt);
-  Precond pc = [&](const MV& v, const MV& z) {
-    const MV& in = (prec == v.prec) ? v : vin;
-    if (prec != v.prec) mv_copy(c, v, vin);
-    if (c->nlev == 1) fine_smoother(c, in, z, d_mu);
-    else mg_cycle(c, 0, d_mu, in, z);
-  };
-  KrylovOut ko;
-  krylov(c, 0, d_mu, b, x, x_zero, c->p.tol, std::min(c->p.outer_restart, KMAX - 1), c->p.max_outer, &pc, prec, false,
-         &ko);
-  iters = ko.iters;
-  c->st.outer_iters = ko.total;
-  return 0;
-}
 
 }  // namespace ddamg
