@@ -96,6 +96,10 @@ typedef struct ddamg_params {
   double r_b;                /* bottom relative tolerance (1e-1)                                */
   int    outer_restart;      /* FGMRES restart length at the top level                          */
   int    max_outer;          /* cap on outer iterations                                         */
+  int    inner_iters;        /* > 0: each outer step preconditions with an FP32 FGMRES of up to */
+                             /* this many steps (restart 63) around the MG cycle / smoother;     */
+                             /* 0: the MG cycle / smoother alone                                 */
+  double inner_tol;          /* relative residual at which that inner FGMRES stops early        */
   int    middle_restart;     /* FGMRES restart on the middle level                              */
   int    middle_maxit;       /* cap on middle-level iterations per call                         */
   int    bottom_maxit;       /* cap on bottom iterations per call                               */
@@ -129,6 +133,7 @@ typedef struct ddamg_stats {
   long long n_sap_calls;
   int    learned_fallbacks;  /* learned-smoother calls replaced by SAP (last solve)             */
   int    col_removals;       /* compactions of the active column set (last solve)               */
+  long long n_inner_iters;   /* FP32 inner FGMRES steps over all outer steps (last solve)       */
 } ddamg_stats;
 
 /* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */

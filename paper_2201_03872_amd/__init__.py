@@ -53,6 +53,8 @@ class Params(ctypes.Structure):
         ("r_b", ctypes.c_double),
         ("outer_restart", ctypes.c_int),
         ("max_outer", ctypes.c_int),
+        ("inner_iters", ctypes.c_int),
+        ("inner_tol", ctypes.c_double),
         ("middle_restart", ctypes.c_int),
         ("middle_maxit", ctypes.c_int),
         ("bottom_maxit", ctypes.c_int),
@@ -78,7 +80,7 @@ class Stats(ctypes.Structure):
         ("avg_middle_iters", ctypes.c_double), ("avg_bottom_iters", ctypes.c_double),
         ("n_middle_solves", ctypes.c_longlong), ("n_bottom_solves", ctypes.c_longlong),
         ("n_fine_ops", ctypes.c_longlong), ("n_sap_calls", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_int),
-        ("col_removals", ctypes.c_int),
+        ("col_removals", ctypes.c_int), ("n_inner_iters", ctypes.c_longlong),
     ]
 
 

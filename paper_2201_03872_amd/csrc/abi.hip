@@ -90,6 +90,8 @@ void ddamg_default_params(ddamg_params* p) {
   p->smoother = DDAMG_SMOOTHER_SAP;
   p->smoother_cycles = 1;
   p->max_active_cols = 0;
+  p->inner_iters = 0;
+  p->inner_tol = 1e-2;
   p->col_tile = 8;
   p->seed = 12345;
   p->verbose = 0;
@@ -132,6 +134,8 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->smoother == DDAMG_SMOOTHER_SAP || p->smoother == DDAMG_SMOOTHER_LEARNED, DDAMG_EINVAL, "smoother");
   DD_CHECK(p->smoother_cycles >= 1 && p->smoother_cycles <= 64, DDAMG_EINVAL, "smoother_cycles");
   DD_CHECK(p->max_active_cols >= 0, DDAMG_EINVAL, "max_active_cols");
+  DD_CHECK(p->inner_iters >= 0 && p->inner_iters <= 10000 && p->inner_tol >= 0 && p->inner_tol < 1, DDAMG_EINVAL,
+           "inner_iters / inner_tol");
 }
 
 int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
@@ -333,7 +337,8 @@ static int active_columns(ddamg_ctx* c, int ncol) {
   const double col64 = (double)c->geom[0].V * 12 * 16;
   const int m = std::min(c->p.outer_restart, 63);
   const double zfac = c->p.precision == DDAMG_MIXED ? 0.5 : 1.0;
-  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8));
+  const int mi = std::min(c->p.inner_iters, 63);
+  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8) + (mi > 0 ? 0.5 * (2 * mi + 2) : 0.0));
   size_t fre = 0, tot = 0;
   DD_HIP(hipMemGetInfo(&fre, &tot));
   const int fit = (int)std::max(8.0, 0.85 * (double)fre / per_col);
@@ -348,6 +353,7 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
   c->st.fine_ops = c->st.sap_calls = 0;
   c->st.learned_fallbacks = 0;
   c->st.col_removals = 0;
+  c->st.inner_iters = 0;
   const int ncol = (int)hmu.size();
   for (double m : hmu) DD_CHECK(std::isfinite(m), DDAMG_EINVAL, "twisted mass is NaN/Inf");
   // NaN guard on the right-hand sides (canonical, one field per distinct rhs)
@@ -440,6 +446,7 @@ int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
     s->n_sap_calls = c->st.sap_calls;
     s->learned_fallbacks = c->st.learned_fallbacks;
     s->col_removals = c->st.col_removals;
+    s->n_inner_iters = c->st.inner_iters;
     return DDAMG_OK;
   });
 }

@@ -123,6 +123,7 @@ struct Stats {
   long long fine_ops = 0, sap_calls = 0;
   int learned_fallbacks = 0;
   int col_removals = 0;
+  long long inner_iters = 0;
 };
 
 }  // namespace ddamg

@@ -16,6 +16,7 @@
 #include <complex>
 #include <functional>
 #include <map>
+#include <tuple>
 
 #include "common.h"
 #include "device.h"
@@ -82,7 +83,7 @@ struct LW {
 };
 
 struct Work {
-  std::map<std::pair<int, int>, LW> lw;
+  std::map<std::tuple<int, int, int>, LW> lw;   // (level, precision, role)
 };
 
 static Work& work(ddamg_ctx* c) {
@@ -95,8 +96,10 @@ void free_work(ddamg_ctx* c) {
   c->work = nullptr;
 }
 
-static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles) {
-  LW& w = work(c).lw[{level, prec}];
+// Workspace of one Krylov solver: role 0 for the solver of a level, role 1
+// for the inner FGMRES of the outer solve (same level, its own basis).
+static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
+  LW& w = work(c).lw[{level, prec, role}];
   if (ntiles > w.cap) {
     for (auto& m : w.V) mv_free(c, m);
     for (auto& m : w.Z) mv_free(c, m);
@@ -310,10 +313,10 @@ static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, 
 // preconditioner output precision zprec.  x holds the initial guess unless
 // x_zero.  fixed: run exactly maxit iterations without a convergence test.
 void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero, double tol, int m,
-            int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out) {
+            int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out, int role = 0) {
   const int nt = b.ntiles, ncol = b.ncol();
   DD_CHECK(m >= 1 && m < KMAX, DDAMG_EINVAL, "Krylov restart length must be in [1, 63]");
-  LW& w = lw(c, level, b.prec, nt);
+  LW& w = lw(c, level, b.prec, nt, role);
   std::vector<double> bn(ncol), tol_abs(ncol), est(ncol), beta;
   double* d_n2 = w.d_h + (size_t)KMAX * ncol * 2;
   mv_norm2(c, b, d_n2);
@@ -385,11 +388,25 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
   MV Bs[2] = {get(c, w.cb, 0, P64, cap, ntw), get(c, w.cb2, 0, P64, cap, ntw)};
   MV Xs[2] = {get(c, w.cx, 0, P64, cap, ntw), get(c, w.cx2, 0, P64, cap, ntw)};
   MV vin = get(c, w0.rho, 0, prec, w0.cap, ntw);
+  Precond smooth = [&](const MV& v, const MV& z, const double* dm) {
+    if (c->nlev == 1) fine_smoother(c, v, z, dm);
+    else mg_cycle(c, 0, dm, v, z);
+  };
+  // With inner_iters > 0 every outer step is preconditioned by an inner
+  // FGMRES in the preconditioner's precision (FP32 Gram-Schmidt and stencil)
+  // around the MG cycle / smoother, solved to inner_tol; the FP64 outer
+  // FGMRES wins the accuracy back.
+  const int mi = std::min(c->p.inner_iters, KMAX - 1);
   Precond pc = [&](const MV& v, const MV& z, const double* dm) {
     const MV in = (prec == v.prec) ? v : vin.tiles(0, v.ntiles);
     if (prec != v.prec) mv_copy(c, v, in);
-    if (c->nlev == 1) fine_smoother(c, in, z, dm);
-    else mg_cycle(c, 0, dm, in, z);
+    if (mi > 0) {
+      KrylovOut ko;
+      krylov(c, 0, dm, in, z, true, c->p.inner_tol, mi, c->p.inner_iters, &smooth, prec, false, &ko, 1);
+      c->st.inner_iters += ko.total;
+    } else {
+      smooth(in, z, dm);
+    }
   };
   job.iters.assign(ncol, 0);
   job.relres.assign(ncol, 0.0);
