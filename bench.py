@@ -289,6 +289,24 @@ def main():
     bytes64 = V * (576 + ncol * 48 * 8)
     ctx.close()
 
+    # the coarse stencil on the hierarchy of this workload (4^4 then 2^4
+    # aggregates, 24 / 32 test vectors): BF16 MFMA against the FP32 vector
+    # kernel and FP64, HIP events on the context stream
+    cctx = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, setup_rounds=1), U)
+    coarse = {}
+    for level in (1, 2):
+        Vc, dof, cdims = cctx.level_info(level)
+        flops = Vc * 9 * dof * dof * 8 * ncol
+        row = {"sites": Vc, "dof": dof, "flop_per_launch": flops}
+        for name, prec, knob in (("bf16_mfma", dd.FP32, 1), ("fp32_vector", dd.FP32, 0), ("fp64", dd.FP64, 0)):
+            cctx.set_tuning("coarse_mfma", knob)
+            sec = cctx.time_op(2, level, prec, ncol, 50)
+            row[name] = {"us": sec * 1e6, "TFLOPs": flops / sec / 1e12}
+        row["bf16_mfma"]["frac_of_bf16_peak"] = row["bf16_mfma"]["TFLOPs"] / 2500.0
+        coarse[f"level{level}"] = row
+    cctx.close()
+    log("coarse stencil", coarse)
+
     plain = None
     if not args.no_plain:
         pctx, plain = run_form(dd.PLAIN_FP64, 1, 0, SOLVER)
@@ -339,6 +357,7 @@ def main():
                      "frac": sap_tf / 157.3, "traffic": measured_traffic(),
                      "us_per_launch": t_sap * 1e6},
         "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
+        "coarse_stencil_48col": coarse,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -226,7 +226,9 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
 #define DDAMG_KNOB_DSLASH_SITES_FP64 0
 #define DDAMG_KNOB_DSLASH_SITES_FP32 1
 #define DDAMG_KNOB_FP32_LINKS        2   /* 0: full 3x3 FP32 links; 1: 2-row compressed */
-#define DDAMG_N_KNOBS 3
+#define DDAMG_KNOB_COARSE_MFMA       3   /* FP32 coarse stencil: 1 (default) BF16 MFMA with FP32
+                                            accumulation where d % 16 == 0; 0 FP32 vector kernel */
+#define DDAMG_N_KNOBS 4
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

@@ -510,6 +510,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_DSLASH_SITES_FP64: return &c->dslash_rs[P64];
     case DDAMG_KNOB_DSLASH_SITES_FP32: return &c->dslash_rs[P32];
     case DDAMG_KNOB_FP32_LINKS: return &c->fp32_links;
+    case DDAMG_KNOB_COARSE_MFMA: return &c->coarse_mfma;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -519,6 +520,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_DSLASH_SITES_FP64: return dslash_rs_valid(P64, value);
     case DDAMG_KNOB_DSLASH_SITES_FP32: return dslash_rs_valid(P32, value);
     case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
+    case DDAMG_KNOB_COARSE_MFMA: return value == 0 || value == 1;
     default: return false;
   }
 }

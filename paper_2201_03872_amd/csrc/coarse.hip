@@ -66,9 +66,148 @@ __global__ void k_coarse(const R* __restrict__ x, R* __restrict__ y, const R* __
   store_one(y + (size_t)tile * tile_reals, V, TC, s, t, i, acc);
 }
 
+// ------------------------------------------------- MFMA coarse stencil ---
+// The coarse stencil is a dense contraction per coarse site: Y (d x n) =
+// sum_p A_p (d x d) X_{n_p} (d x n) over the 9 blocks, all complex.  In real
+// form, with A' = [Re A | Im A] (d x 2d),
+//   Re Y = A' [Re X; -Im X],   Im Y = A' [Im X; Re X],
+// so one real product of depth 18d per site serves both halves.  It runs on
+// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  A workgroup
+// owns one coarse site and up to four 16-column groups (two tiles each), so
+// each block operand is loaded once for up to 64 columns; wave w computes the
+// rows [16w, 16w+16) of both halves.  Lane layout of the instruction (A 16x32,
+// B 32x16, D 16x16): lane l holds A[l%16][8(l/16)+e], B[8(l/16)+e][l%16]
+// (e = 0..7) and D[4(l/16)+r][l%16] (r = 0..3).  The blocks are stored once in
+// that A layout, [site][p][row tile][k step][lane][8], so every operand is one
+// coalesced 16-byte load per lane.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// blocks (column-major complex [site][9][col][row], FP64) -> BF16 A layout
+__global__ void k_blocks_bf16(const double* __restrict__ blk, bf16x8* __restrict__ out, int V, int d) {
+  const int MT = d / 16, KS = d / 16;
+  const size_t n = (size_t)V * 9 * MT * KS * 64;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(q % 64);
+    const int ks = (int)((q / 64) % KS);
+    const int mt = (int)((q / (64 * KS)) % MT);
+    const size_t sp = q / ((size_t)64 * KS * MT);       // site * 9 + p
+    const int i = 16 * mt + lane % 16;
+    const int k0 = 32 * ks + 8 * (lane / 16);
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + e;
+      const int jj = k < d ? k : k - d;
+      const double* a = blk + ((sp * d + jj) * d + i) * 2;
+      v[e] = (__bf16)(float)(k < d ? a[0] : a[1]);
+    }
+    out[q] = v;
+  }
+}
+
+// GPW = 16-column groups per workgroup: 4 reads each block once for 64
+// columns (large coarse lattices); 1 gives four times the workgroups, which
+// wins on small coarse lattices where the stencil is latency bound.
+template <int MFMA_GPW>
+__global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x, float* __restrict__ y,
+                                                     const bf16x8* __restrict__ A, const int* __restrict__ nbr,
+                                                     const double* __restrict__ mu, double muf, int V, int d,
+                                                     size_t tile_reals, int ntiles) {
+  const int ngrp = (ntiles + 1) / 2;
+  const int nwgc = (ngrp + MFMA_GPW - 1) / MFMA_GPW;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = wg % V, g0 = (wg / V) * MFMA_GPW;
+  const int ng = min(MFMA_GPW, ngrp - g0);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int KS = d / 16, MT = d / 16;
+  const int j = lane % 16, kb = lane / 16;
+  f32x4 accr[MFMA_GPW], acci[MFMA_GPW];
+#pragma unroll
+  for (int g = 0; g < MFMA_GPW; ++g) {
+    accr[g] = f32x4{0, 0, 0, 0};
+    acci[g] = f32x4{0, 0, 0, 0};
+  }
+  const bf16x8* Aw = A + ((size_t)s * 9 * MT + w) * KS * 64 + lane;
+  for (int p = 0; p < 9; ++p) {
+    const int nb = p == 0 ? s : nbr[(size_t)(p - 1) * V + s];
+    const bf16x8* Ap = Aw + (size_t)p * MT * KS * 64;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = 32 * ks + 8 * kb;
+      const bool re_part = k0 < d;
+      const int c0 = re_part ? k0 : k0 - d;
+      const bf16x8 a = Ap[(size_t)ks * 64];
+#pragma unroll
+      for (int g = 0; g < MFMA_GPW; ++g) {
+        if (g >= ng) break;
+        const int col = 16 * (g0 + g) + j;
+        const int tile = col / TC, t = col % TC;
+        bf16x8 b1, b2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (tile < ntiles)
+            v = *reinterpret_cast<const float4*>(x + (size_t)tile * tile_reals +
+                                                 (((size_t)(c0 / 2 + q) * V + nb) * TC + t) * 4);
+          // v = (re, im) of complex c0+2q and c0+2q+1
+          if (re_part) {
+            b1[2 * q] = (__bf16)v.x; b1[2 * q + 1] = (__bf16)v.z;
+            b2[2 * q] = (__bf16)v.y; b2[2 * q + 1] = (__bf16)v.w;
+          } else {
+            b1[2 * q] = (__bf16)(-v.y); b1[2 * q + 1] = (__bf16)(-v.w);
+            b2[2 * q] = (__bf16)v.x; b2[2 * q + 1] = (__bf16)v.z;
+          }
+        }
+        accr[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, accr[g], 0, 0, 0);
+        acci[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b2, acci[g], 0, 0, 0);
+      }
+    }
+  }
+  // twist i dmu mu gamma5_c on the site's own x (FP32), then store
+#pragma unroll
+  for (int g = 0; g < MFMA_GPW; ++g) {
+    if (g >= ng) break;
+    const int col = 16 * (g0 + g) + j;
+    const int tile = col / TC, t = col % TC;
+    if (tile >= ntiles) continue;
+    const float m = (float)(muf * mu[tile * TC + t]);
+    const float* xt = x + (size_t)tile * tile_reals;
+    float* yt = y + (size_t)tile * tile_reals;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + 4 * kb + r;
+      const size_t o = (((size_t)(i / 2) * V + s) * TC + t) * 4 + (i % 2) * 2;
+      const float gm = i < d / 2 ? m : -m;
+      yt[o] = accr[g][r] - gm * xt[o + 1];
+      yt[o + 1] = acci[g][r] + gm * xt[o];
+    }
+  }
+  (void)nwgc;
+}
+
+static bool use_mfma(ddamg_ctx* c, int level, const MV& x) {
+  const int d = c->geom[level].dof;
+  return x.prec == P32 && c->coarse_mfma && d % 16 == 0 && d <= 64 && c->coarse[level].d_blk16 != nullptr;
+}
+
 void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
   const LevelGeom& g = c->geom[level];
   const int d = g.dof;
+  if (use_mfma(c, level, x)) {
+    const int ngrp = (x.ntiles + 1) / 2;
+    if ((size_t)g.V * ngrp >= 8192) {
+      const int nwgc = (ngrp + 3) / 4;
+      hipLaunchKernelGGL(k_coarse_mfma<4>, dim3(g.V * nwgc), dim3(64 * (d / 16)), 0, c->stream, x.as<float>(),
+                         y.as<float>(), (const bf16x8*)c->coarse[level].d_blk16, g.d_nbr, d_mu,
+                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles);
+    } else {
+      hipLaunchKernelGGL(k_coarse_mfma<1>, dim3(g.V * ngrp), dim3(64 * (d / 16)), 0, c->stream, x.as<float>(),
+                         y.as<float>(), (const bf16x8*)c->coarse[level].d_blk16, g.d_nbr, d_mu,
+                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles);
+    }
+    DD_HIP(hipGetLastError());
+    return;
+  }
   dim3 grid(g.V * x.ntiles), blk(d * TC);
   if (x.prec == P64)
     hipLaunchKernelGGL((k_coarse<double, 0>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
@@ -342,6 +481,14 @@ void convert_blocks32(ddamg_ctx* c, int level) {
   const size_t n = (size_t)g.V * 9 * g.dof * g.dof * 2;
   hipLaunchKernelGGL(k_d2f, grid1(n), dim3(256), 0, c->stream, c->coarse[level].d_blk64, c->coarse[level].d_blk32, n);
   DD_HIP(hipGetLastError());
+  // BF16 copy in the MFMA operand layout (same number of reals, 2 bytes each)
+  if (g.dof % 16 == 0 && g.dof <= 256) {
+    if (!c->coarse[level].d_blk16) c->coarse[level].d_blk16 = c->pool.alloc(n * 2);
+    const size_t nv = (size_t)g.V * 9 * (g.dof / 16) * (g.dof / 16) * 64;
+    hipLaunchKernelGGL(k_blocks_bf16, grid1(nv), dim3(256), 0, c->stream, c->coarse[level].d_blk64,
+                       (bf16x8*)c->coarse[level].d_blk16, g.V, g.dof);
+    DD_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace ddamg

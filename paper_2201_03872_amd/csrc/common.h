@@ -105,6 +105,7 @@ struct Transfer {
 struct Coarse {
   double* d_blk64 = nullptr;  // [V][9][d col][d row] complex (column-major blocks)
   float* d_blk32 = nullptr;
+  void* d_blk16 = nullptr;    // BF16 blocks in the MFMA operand layout (d % 16 == 0)
   double mu_factor = 1.0;
 };
 
@@ -155,6 +156,7 @@ struct ddamg_ctx {
   ddamg::MV tvk[2];             // smoothed (not orthonormalised) test vectors of each transition
   int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
   int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
+  int coarse_mfma = 1;          // FP32 coarse stencil on BF16 MFMA (d % 16 == 0)
 };
 
 namespace ddamg {

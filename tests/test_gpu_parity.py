@@ -216,8 +216,45 @@ def test_transfer_and_coarse_operator_parity(torch_cuda, dd):
     yc_ref = coarse.apply(xc, mus)
     yc = ctx.apply_op(1, dd.FP64, mus, torch.from_numpy(xc).cuda()).cpu().numpy()
     assert np.max(relerr_cols(yc, yc_ref)) < 1e-13
+    ctx.set_tuning("coarse_mfma", 0)      # FP32 vector kernel
     yc32 = ctx.apply_op(1, dd.FP32, mus, torch.from_numpy(xc).cuda()).cpu().numpy()
     assert np.max(relerr_cols(yc32, yc_ref)) < 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("N,N2", [(8, 8), (24, 32)])
+def test_coarse_mfma_parity(torch_cuda, dd, N, N2):
+    """The FP32 coarse stencil on BF16 MFMA (FP32 accumulation) against the
+    oracle's FP64 Galerkin operator, on both coarse levels (d = 2N = 16, 48;
+    d = 2N2 = 16, 64), for ragged column counts (odd tile counts leave a
+    half-empty 16-column group).  BF16 keeps 8 mantissa bits, so the bar is
+    1e-2 relative per column; the FP32 vector kernel meets 1e-5."""
+    torch = torch_cuda
+    dims, agg = (8, 4, 4, 8), (2, 2, 2, 2)
+    say("coarse MFMA", dims, N, N2)
+    ctx, U, V = _two_level_case(dd, dims, agg, N, n_levels=3, agg2=(2, 2, 2, 2), N2=N2)
+    tv = S.gaussian_spinors(N, V, 75).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv)
+    blk = Blocking(dims, agg)
+    c2 = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), build_prolongator(tv, blk), blk)
+    tv2 = S.gaussian_coarse(N2, blk.nblocks, 2 * N, 76)
+    ctx.set_test_vectors(1, tv2)
+    blk2 = Blocking(blk.cdims, (2, 2, 2, 2))
+    c3 = galerkin(c2, build_prolongator(tv2, blk2), blk2)
+    assert ctx.get_tuning("coarse_mfma") == 1
+    for ncol in (5, 24, 9):
+        mus = np.linspace(0.002, 0.2, ncol)
+        for level, cop, nb, d in ((1, c2, blk.nblocks, 2 * N), (2, c3, blk2.nblocks, 2 * N2)):
+            x = S.gaussian_coarse(ncol, nb, d, 77 + ncol + level)
+            ref = cop.apply(x, mus)
+            xg = torch.from_numpy(x).cuda()
+            ctx.set_tuning("coarse_mfma", 1)
+            ym = ctx.apply_op(level, dd.FP32, mus, xg).cpu().numpy()
+            ctx.set_tuning("coarse_mfma", 0)
+            yv = ctx.apply_op(level, dd.FP32, mus, xg).cpu().numpy()
+            em, ev = np.max(relerr_cols(ym, ref)), np.max(relerr_cols(yv, ref))
+            say(f"  level {level} d {d} ncol {ncol}: MFMA {em:.2e}, FP32 vector {ev:.2e}")
+            assert em < 1e-2 and ev < 1e-5
     ctx.close()
 
 
