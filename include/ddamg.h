@@ -204,6 +204,16 @@ int ddamg_solve(ddamg_ctx* h, const double* mu, int n_shift, const double* b, in
 int ddamg_solve_batch(ddamg_ctx* h, int n_sys, const int* n_rhs, const int* n_shift, const double* mu,
                       const double* b, double* x, int use_x0, ddamg_col_info* info);
 
+/* Solve D_level(mu_c) x_c = b_c on a coarse level (level >= 1) with
+ * restarted GMRES (block = 0, per column) or block GMRES (block != 0: columns
+ * with equal mu form one block, section 4; block Gram-Schmidt and Cholesky QR
+ * on the GPU), restart min(maxit, 63), to relative residual tol or maxit
+ * (block) steps.  b, x: device, canonical layout of that level; mu: host
+ * [n_col]; iters: host [n_col] or NULL.  The coarsest-level solve of the
+ * multigrid cycle uses the block form when params.coarsest_block != 0. */
+int ddamg_coarse_solve(ddamg_ctx* h, int level, int precision, int block, const double* mu, int n_col,
+                       const double* b, double* x, double tol, int maxit, int* iters);
+
 /* Statistics of the last setup / solve. */
 int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);
 

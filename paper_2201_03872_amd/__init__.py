@@ -118,6 +118,8 @@ def load():
         "ddamg_solve": (ctypes.c_int, [vp, dp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, P(ColInfo)]),
         "ddamg_solve_batch": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), dp, vp, vp,
                                              ctypes.c_int, P(ColInfo)]),
+        "ddamg_coarse_solve": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp,
+                                              ctypes.c_double, ctypes.c_int, ip]),
         "ddamg_get_stats": (ctypes.c_int, [vp, P(Stats)]),
         "ddamg_time_op": (ctypes.c_int, [vp] + [ctypes.c_int] * 5 + [dp]),
         "ddamg_set_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
@@ -305,6 +307,17 @@ class Context:
                           for i in info[o:o + r * k]])
             o += r * k
         return xs, infos, st
+
+    def coarse_solve(self, level, precision, block, mu, b, tol, maxit):
+        """(Block) GMRES on coarse level `level`: b [n_col][Vc][dof] complex128
+        CUDA tensor, mu [n_col].  Returns (x, iterations per column)."""
+        import torch
+        m, mp = _mu(mu)
+        x = torch.zeros_like(b)
+        it = (ctypes.c_int * b.shape[0])()
+        _check(load().ddamg_coarse_solve(self.h, level, precision, int(bool(block)), mp, b.shape[0], _dptr(b),
+                                         _dptr(x), float(tol), int(maxit), it))
+        return x, list(it)
 
     def stats(self) -> dict:
         s = Stats()

@@ -18,7 +18,7 @@ LIBDIR = os.path.join(HERE, "lib")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "libddamg.so")
 
-SOURCES = ["fine.hip", "coarse.hip", "blas.hip", "ctx.hip", "solve.hip", "ptc.hip", "abi.hip"]
+SOURCES = ["fine.hip", "coarse.hip", "blas.hip", "ctx.hip", "solve.hip", "block.hip", "ptc.hip", "abi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -185,6 +185,7 @@ void ddamg_destroy(ddamg_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   free_work(c);
   free_ptc(c);
+  free_block_work(c);
   c->pool.clear();
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   delete c;
@@ -428,6 +429,40 @@ int ddamg_solve_batch(ddamg_ctx* c, int n_sys, const int* n_rhs, const int* n_sh
       k0 += n_shift[s];
     }
     return solve_columns(c, hmu, rhs_of, b, x, use_x0, info);
+  });
+}
+
+int ddamg_coarse_solve(ddamg_ctx* c, int level, int precision, int block, const double* mu, int n_col,
+                       const double* b, double* x, double tol, int maxit, int* iters) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mu && b && x && n_col >= 1 && maxit >= 1 && tol > 0, DDAMG_EINVAL, "bad arguments");
+    DD_CHECK(level >= 1 && level < c->nlev, DDAMG_ESTATE, "no such coarse level");
+    DD_CHECK(precision == DDAMG_FP64 || precision == DDAMG_FP32, DDAMG_EINVAL, "precision");
+    const int prec = precision == DDAMG_FP64 ? P64 : P32;
+    MV b64 = mv_alloc(c, level, P64, n_col);
+    to_internal(c, level, b, n_col, b64);
+    MV B = prec == P64 ? b64 : mv_like(c, b64, P32);
+    if (prec != P64) mv_copy(c, b64, B);
+    MV X = mv_alloc(c, level, prec, n_col);
+    double* d_mu = upload_mu(c, mu, n_col, B.ncol());
+    const int m = std::min(maxit, 63);
+    std::vector<int> it;
+    if (block) block_gmres(c, level, d_mu, B, X, true, tol, m, maxit, &it, nullptr, nullptr);
+    else level_gmres(c, level, d_mu, B, X, tol, m, maxit, &it, nullptr, nullptr);
+    MV x64 = prec == P64 ? X : mv_like(c, X, P64);
+    if (prec != P64) mv_copy(c, X, x64);
+    from_internal(c, level, x64, n_col, x);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    if (iters)
+      for (int i = 0; i < n_col; ++i) iters[i] = it[i];
+    if (prec != P64) {
+      mv_free(c, B);
+      mv_free(c, x64);
+    }
+    mv_free(c, b64);
+    mv_free(c, X);
+    c->pool.release(d_mu);
+    return DDAMG_OK;
   });
 }
 

@@ -153,6 +153,7 @@ struct ddamg_ctx {
   ddamg::Stats st;
   void* work = nullptr;         // solver workspaces (solve.hip)
   void* ptc = nullptr;          // learned smoother state (ptc.hip)
+  void* bwork = nullptr;        // block GMRES workspaces (block.hip)
   ddamg::MV tvk[2];             // smoothed (not orthonormalised) test vectors of each transition
   int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
   int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
@@ -238,6 +239,12 @@ struct OuterJob {
   int total = 0;                // outer iterations (cycles x steps) of the whole batch
 };
 void outer_solve(ddamg_ctx* c, OuterJob& job);
+// restarted block GMRES(m) on a level, columns grouped by equal shift
+void block_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero, double tol,
+                 int m, int maxit, std::vector<int>* iters, std::vector<double>* relres, int* total);
+void free_block_work(ddamg_ctx* c);
+void level_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, double tol, int m, int maxit,
+                 std::vector<int>* iters, std::vector<double>* relres, int* total);
 
 // ---- host helpers ----
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);

@@ -360,6 +360,16 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
   }
 }
 
+// Plain restarted GMRES(m) on one level (no preconditioner), per column.
+void level_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, double tol, int m, int maxit,
+                 std::vector<int>* iters, std::vector<double>* relres, int* total) {
+  KrylovOut ko;
+  krylov(c, level, d_mu, b, x, true, tol, m, maxit, nullptr, b.prec, false, &ko);
+  if (iters) *iters = ko.iters;
+  if (relres) *relres = ko.relres;
+  if (total) *total = ko.total;
+}
+
 // ------------------------------------------------------- outer solve ---
 void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e);
 
@@ -578,12 +588,16 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
   restrict_mv(c, l, r, rc);
   KrylovOut ko;
   const bool bottom = (l + 2 == c->nlev);
-  if (bottom) {
+  if (bottom && c->p.coarsest_block) {
+    int total = 0;
+    block_gmres(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
+                nullptr, nullptr, &total);
+    c->st.bottom_calls++;
+    c->st.bottom_iters += total;
+  } else if (bottom) {
     krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
            nullptr, prec, false, &ko);
     c->st.bottom_calls++;
-    int mx = 0;
-    for (int i : ko.iters) mx = std::max(mx, i);
     c->st.bottom_iters += ko.total;
   } else {
     Precond pc = [&](const MV& v, const MV& z, const double* dm) { mg_cycle(c, l + 1, dm, v, z); };

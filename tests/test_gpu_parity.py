@@ -332,11 +332,13 @@ def test_solve_two_level(torch_cuda, dd, precision):
     assert all(i["converged"] for i in info)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_solve_three_level(torch_cuda, dd, precision):
+@pytest.mark.parametrize("precision,block", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_solve_three_level(torch_cuda, dd, precision, block):
+    """Three-level MG-preconditioned solve; block = 1 solves the coarsest
+    level with block GMRES over the columns of each shift."""
     w = S.workload("tm_8x8x8x8_3level")
-    say("solve", w.name, "precision", precision)
-    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision)
+    say("solve", w.name, "precision", precision, "block", block)
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision, coarsest_block=block)
     assert st == dd.OK
     assert np.all(rel <= 1e-10 * (1 + 1e-6))
 
@@ -356,4 +358,72 @@ def test_error_paths(torch_cuda, dd):
     with pytest.raises(dd.DDAMGError) as e:
         ctx.solve([0.01], torch.from_numpy(b).cuda())
     assert e.value.code == dd.EINVAL
+    ctx.close()
+
+
+def _coarse_case(dd, torch):
+    dims, agg, N = (8, 4, 4, 8), (2, 2, 2, 2), 8
+    ctx, U, V = _two_level_case(dd, dims, agg, N)
+    tv = S.gaussian_spinors(N, V, 81).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv)
+    blk = Blocking(dims, agg)
+    coarse = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), build_prolongator(tv, blk), blk)
+    return ctx, coarse, blk.nblocks, 2 * N
+
+
+def test_block_gmres_iterates_match_oracle(torch_cuda, dd):
+    """Block GMRES on the GPU (block Gram-Schmidt, Cholesky QR, Givens least
+    squares) builds the same block Krylov space and least-squares solution as
+    the oracle's block GMRES (numpy QR and lstsq): after k block steps the
+    iterates agree to rounding, group by group (equal shifts)."""
+    torch = torch_cuda
+    say("block GMRES iterates")
+    ctx, coarse, nb, d = _coarse_case(dd, torch)
+    groups = {0.01: 3, 0.07: 2, 0.2: 1}
+    mus = np.concatenate([[m] * s for m, s in groups.items()])
+    b = S.gaussian_coarse(len(mus), nb, d, 82)
+    for k in (1, 3, 6):
+        x, it = ctx.coarse_solve(1, dd.FP64, True, mus, torch.from_numpy(b).cuda(), 1e-14, k)
+        x = x.cpu().numpy()
+        o = 0
+        for m, s in groups.items():
+            sl = slice(o, o + s)
+            xr, info = O.block_gmres(lambda X: coarse.apply(X, np.full(s, m)), b[sl], 1e-14, k)
+            err = np.max(relerr_cols(x[sl], xr))
+            say(f"  k={k} mu={m} s={s}: max rel. difference {err:.2e}")
+            assert err < 1e-9
+            o += s
+        assert all(i == k for i in it)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,mfma", [("FP64", 0), ("FP32", 0), ("FP32", 1)])
+def test_block_gmres_converges(torch_cuda, dd, precision, mfma):
+    """Block and per-column GMRES on the GPU reach the tolerance by the FP64
+    oracle residual; the block form never needs more steps (its Krylov space
+    contains every column's), and identical right-hand sides in one block
+    (a rank-deficient block: Cholesky QR drops the dependent direction) give
+    identical solutions.  With the BF16 MFMA coarse stencil the attainable
+    residual is that of an 8-bit mantissa operator (2e-3 here), so its bar is
+    1e-2."""
+    torch = torch_cuda
+    ctx, coarse, nb, d = _coarse_case(dd, torch)
+    ctx.set_tuning("coarse_mfma", mfma)
+    tol = {("FP64", 0): 1e-8, ("FP32", 0): 1e-4, ("FP32", 1): 1e-2}[(precision, mfma)]
+    mus = np.array([0.0005] * 6 + [0.05] * 6)
+    b = S.gaussian_coarse(len(mus), nb, d, 83)
+    b[3] = b[0]                                   # identical right-hand sides: a rank-deficient block
+    bg = torch.from_numpy(b).cuda()
+    prec = getattr(dd, precision)
+    xb, itb = ctx.coarse_solve(1, prec, True, mus, bg, tol, 400)
+    xg, itg = ctx.coarse_solve(1, prec, False, mus, bg, tol, 400)
+    for name, x, it in (("block", xb.cpu().numpy(), itb), ("gmres", xg.cpu().numpy(), itg)):
+        rel = O.col_norm(b - coarse.apply(x, mus)) / O.col_norm(b)
+        say(f"  {name} {precision} mfma={mfma}: iterations {max(it)}, worst true rel. residual {rel.max():.2e}")
+    for x in (xb.cpu().numpy(), xg.cpu().numpy()):
+        rel = O.col_norm(b - coarse.apply(x, mus)) / O.col_norm(b)
+        assert np.all(rel <= 1.5 * tol), rel
+    xb = xb.cpu().numpy()
+    assert np.max(np.abs(xb[3] - xb[0])) <= 1e-6 * np.max(np.abs(xb[0]))
+    assert max(itb) <= max(itg)
     ctx.close()
