@@ -238,7 +238,11 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
 #define DDAMG_KNOB_FP32_LINKS        2   /* 0: full 3x3 FP32 links; 1: 2-row compressed */
 #define DDAMG_KNOB_COARSE_MFMA       3   /* FP32 coarse stencil: 1 (default) BF16 MFMA with FP32
                                             accumulation where d % 16 == 0; 0 FP32 vector kernel */
-#define DDAMG_N_KNOBS 4
+#define DDAMG_KNOB_SAP_VARIANT       4   /* FP32 SAP on 4^4 blocks: 0 (default) 2 columns per workgroup,
+                                            the block's 2-row links staged in LDS; 1 2 columns, links
+                                            read through L1/L2; 2 one column, links through L1/L2
+                                            (less LDS per workgroup, more workgroups per CU) */
+#define DDAMG_N_KNOBS 5
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

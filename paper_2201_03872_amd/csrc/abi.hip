@@ -546,6 +546,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_DSLASH_SITES_FP32: return &c->dslash_rs[P32];
     case DDAMG_KNOB_FP32_LINKS: return &c->fp32_links;
     case DDAMG_KNOB_COARSE_MFMA: return &c->coarse_mfma;
+    case DDAMG_KNOB_SAP_VARIANT: return &c->sap_variant;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -556,6 +557,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_DSLASH_SITES_FP32: return dslash_rs_valid(P32, value);
     case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
     case DDAMG_KNOB_COARSE_MFMA: return value == 0 || value == 1;
+    case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 2;
     default: return false;
   }
 }
@@ -609,6 +611,19 @@ int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
         }
       c->fp32_links = bl;
       c->dslash_rs[P32] = bs;
+    }
+    // FP32 SAP on 4^4 blocks: columns per workgroup x links in LDS or through the caches
+    if (c->geom[0].gsize == 256) {
+      double best = 1e30;
+      int bv = c->sap_variant;
+      for (int v : {0, 1, 2}) {
+        c->sap_variant = v;
+        double sec = 0;
+        const int st = ddamg_time_op(c, 1, 0, DDAMG_FP32, n_col, 2, &sec);
+        if (st != DDAMG_OK) return st;
+        if (sec < best) { best = sec; bv = v; }
+      }
+      c->sap_variant = bv;
     }
     if (values)
       for (int k = 0; k < DDAMG_N_KNOBS; ++k) values[k] = *knob_slot(c, k);

@@ -158,6 +158,8 @@ struct ddamg_ctx {
   int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
   int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
   int coarse_mfma = 1;          // FP32 coarse stencil on BF16 MFMA (d % 16 == 0)
+  int sap_variant = 0;          // FP32 SAP on 4^4 blocks: 0 = 2 columns/WG, links in LDS; 1 = 2 columns, links
+                                // through L1/L2; 2 = 1 column/WG, links through L1/L2
 };
 
 namespace ddamg {

@@ -333,9 +333,10 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
 }
 
 // ---------------------------------------------------------------- SAP ---
-// Links of the in-block MR steps: FP32 2-row links staged in LDS (sign from
-// the neighbour table), or FP64 full links from global memory.
-template <typename R, int LK, int BS>
+// Links of the in-block MR steps: FP32 2-row links staged in LDS (ULDS; sign
+// from the neighbour table), or read through the caches from global memory
+// (FP32 2-row or FP64 full links).
+template <typename R, int LK, int BS, bool ULDS>
 struct SapLinks {
   static constexpr bool table_sign = (LK == LK_C);
   const float4* ulds;
@@ -343,7 +344,7 @@ struct SapLinks {
   int V;
   int base;
   __device__ __forceinline__ void operator()(int mu, int site, cx<R> (&u)[9]) const {
-    if constexpr (LK == LK_C) {
+    if constexpr (LK == LK_C && ULDS) {
       const int l = site - base;
       unpack_2row(ulds[(mu * 3) * BS + l], ulds[(mu * 3 + 1) * BS + l], ulds[(mu * 3 + 2) * BS + l], u);
     } else {
@@ -361,7 +362,7 @@ struct SapLinks {
 //   3. x += delta on the block.
 // Blocks of one colour never neighbour each other, so the in-place update of
 // x is race free.
-template <typename R, int LK, int K, int BS>
+template <typename R, int LK, int K, int BS, bool ULDS>
 __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   constexpr int WL = NT >= 64 ? 64 : NT;    // lanes per wave actually used
   __shared__ C lds[NCH * BS * K];
   __shared__ R red[NW][K][3];
-  __shared__ float4 ulds[LK == LK_C ? 12 * BS : 1];
+  __shared__ float4 ulds[(LK == LK_C && ULDS) ? 12 * BS : 1];
 
   // the NSUB workgroups of one block read the same 128-byte rows: keep them
   // on one XCD (shared L2) by numbering workgroups XCD-contiguously
@@ -412,14 +413,14 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
 
   // the block's forward links (2-row FP32) staged in LDS for the MR steps;
   // the backward link of an in-block hop is the forward link of an in-block site
-  if constexpr (LK == LK_C) {
+  if constexpr (LK == LK_C && ULDS) {
     const float4* Ug = reinterpret_cast<const float4*>(U);
     for (int i = threadIdx.x; i < 12 * BS; i += NT) {
       const int mu_q = i / BS, l = i % BS;
       ulds[i] = Ug[(size_t)mu_q * V + blk * BS + l];
     }
   }
-  const SapLinks<R, LK, BS> lll{ulds, U, V, blk * BS};
+  const SapLinks<R, LK, BS, ULDS> lll{ulds, U, V, blk * BS};
 
   // 2. block MR
   auto ldl = [&](int, int nb, cx<R>(&p)[12]) {
@@ -549,11 +550,11 @@ void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
   DD_HIP(hipGetLastError());
 }
 
-template <typename R, int LK, int K, int BS>
+template <typename R, int LK, int K, int BS, bool ULDS = true>
 static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour) {
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
-  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
+  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
                      LK == LK_C ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
                      c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
                      c->p.sap_mr_iters);
@@ -570,7 +571,9 @@ void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const
         else if (BS == 16) launch_sap<double, LK_D, 4, 16>(c, f, x, d_mu, colour);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       } else {
-        if (BS == 256) launch_sap<float, LK_C, 2, 256>(c, f, x, d_mu, colour);
+        if (BS == 256 && c->sap_variant == 0) launch_sap<float, LK_C, 2, 256, true>(c, f, x, d_mu, colour);
+        else if (BS == 256 && c->sap_variant == 1) launch_sap<float, LK_C, 2, 256, false>(c, f, x, d_mu, colour);
+        else if (BS == 256) launch_sap<float, LK_C, 1, 256, false>(c, f, x, d_mu, colour);
         else if (BS == 16) launch_sap<float, LK_C, 8, 16>(c, f, x, d_mu, colour);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       }

@@ -164,10 +164,12 @@ def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
     fg = torch.from_numpy(f).cuda()
     x64 = ctx.apply_sap(dd.FP64, mus, fg).cpu().numpy()
     assert np.max(relerr_cols(x64, ref)) < 1e-12
-    x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
-    e = np.max(relerr_cols(x32, ref))
-    say("  fp32 SAP relative error", e)
-    assert e < 1e-4
+    for variant in (0, 1, 2):     # columns per workgroup x link staging (4^4 blocks only)
+        ctx.set_tuning("sap_variant", variant)
+        x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
+        e = np.max(relerr_cols(x32, ref))
+        say("  fp32 SAP relative error", variant, e)
+        assert e < 1e-4
     ctx.close()
 
 
