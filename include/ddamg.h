@@ -109,6 +109,8 @@ typedef struct ddamg_params {
   int    smoother;           /* DDAMG_SMOOTHER_SAP or DDAMG_SMOOTHER_LEARNED                    */
   int    smoother_cycles;    /* learned smoother: minimal-residual steps along f(r) per call    */
   int    col_tile;           /* columns per tile of the internal layout (4, 8 or 16; 0 = 8)     */
+  int    use_graphs;         /* 1: unpreconditioned (coarsest-level) GMRES runs its Arnoldi     */
+                             /* steps as captured HIP graphs with device-side least squares    */
   int    max_active_cols;    /* outer solve: columns in flight at once (0 = as memory allows);  */
                              /* the others wait and join as converged columns leave             */
   uint64_t seed;             /* counter-based RNG seed of the setup vectors when none are given */

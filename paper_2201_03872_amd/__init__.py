@@ -64,6 +64,7 @@ class Params(ctypes.Structure):
         ("smoother", ctypes.c_int),
         ("smoother_cycles", ctypes.c_int),
         ("col_tile", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
         ("max_active_cols", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),

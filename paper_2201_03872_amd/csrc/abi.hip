@@ -91,6 +91,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->smoother_cycles = 1;
   p->max_active_cols = 0;
   p->inner_iters = 0;
+  p->use_graphs = 1;
   p->inner_tol = 1e-2;
   p->col_tile = 8;
   p->seed = 12345;
@@ -186,6 +187,7 @@ void ddamg_destroy(ddamg_ctx* c) {
   free_work(c);
   free_ptc(c);
   free_block_work(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   c->pool.clear();
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   delete c;

@@ -491,7 +491,24 @@ __global__ void k_multidot2(const double* __restrict__ part, double* __restrict_
   out[2 * i + 1] = b;
 }
 
+// workgroups along the vector length of the first reduction stage
+static int multidot_nbm(const MV& w, int k) {
+  const size_t M = (size_t)w.nchunk * w.nsites;
+  const int ngroups = (k + KB - 1) / KB;
+  int nbM = (int)std::min<size_t>((M + 31) / 32, 4096 / ((size_t)w.ntiles * ngroups) + 1);
+  return nbM < 1 ? 1 : nbM;
+}
+
+// doubles of the partial sums mv_multidot needs for k vectors shaped like w
+size_t multidot_partials(const MV& w, int k) { return (size_t)multidot_nbm(w, k) * k * w.ncol() * 2; }
+
 void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out) {
+  mv_multidot_buf(c, Vs, k, w, d_out, nullptr);
+}
+
+// part: partial-sum buffer of at least multidot_partials(w, k) doubles, or
+// nullptr for the context's scratch buffer
+void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out, double* part) {
   DD_CHECK(k >= 1 && k <= MAXK, DDAMG_EINVAL, "mv_multidot: k");
   DD_CHECK(w.T == TTB, DDAMG_EINVAL, "mv_multidot: tile width");
   PtrPack pk;
@@ -501,10 +518,9 @@ void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out) 
   }
   const size_t M = (size_t)w.nchunk * w.nsites;
   const int ngroups = (k + KB - 1) / KB;
-  int nbM = (int)std::min<size_t>((M + 31) / 32, 4096 / ((size_t)w.ntiles * ngroups) + 1);
-  if (nbM < 1) nbM = 1;
+  const int nbM = multidot_nbm(w, k);
   const int ncol = w.ncol();
-  double* part = scratch(c, (size_t)nbM * k * ncol * 2 * sizeof(double));
+  if (!part) part = scratch(c, multidot_partials(w, k) * sizeof(double));
   dim3 grid(nbM, w.ntiles, ngroups);
   if (w.prec == P64)
     hipLaunchKernelGGL(k_multidot1<double>, grid, dim3(256), 0, c->stream, pk, k, w.as<double>(), part, M, w.ntiles,
@@ -525,9 +541,12 @@ __global__ void k_re_only(const double* in, double* out, int n) {
   if (i < n) out[i] = in[2 * i];
 }
 
-void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out) {
-  double* cbuf = small_buffer(c, 2 * a.ncol());
-  mv_multidot(c, &a, 1, a, cbuf);
+void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out) { mv_norm2_buf(c, a, d_out, nullptr, nullptr); }
+
+// cbuf: 2 * ncol doubles, part: multidot_partials(a, 1) doubles (nullptr: context buffers)
+void mv_norm2_buf(ddamg_ctx* c, const MV& a, double* d_out, double* cbuf, double* part) {
+  if (!cbuf) cbuf = small_buffer(c, 2 * a.ncol());
+  mv_multidot_buf(c, &a, 1, a, cbuf, part);
   hipLaunchKernelGGL(k_re_only, dim3((a.ncol() + 255) / 256), dim3(256), 0, c->stream, cbuf, d_out, a.ncol());
   DD_HIP(hipGetLastError());
 }

@@ -132,6 +132,7 @@ struct Stats {
 struct ddamg_ctx {
   ddamg_params p;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;   // private stream for graph capture (default priority)
   int T = 8;
   int nlev = 1;
   double m0 = 0, diag = 0;
@@ -182,6 +183,10 @@ void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out);
 // w -= sum_j coef[j*ncol+c] V_j   (coef complex, device)
 void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign);
 void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out);          // per column, real
+// variants on caller-owned buffers (no context scratch: safe to capture in a graph)
+size_t multidot_partials(const MV& w, int k);
+void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out, double* part);
+void mv_norm2_buf(ddamg_ctx* c, const MV& a, double* d_out, double* cbuf, double* part);
 void mv_dot(ddamg_ctx* c, const MV& a, const MV& b, double* d_out);  // per column complex
 // masked scaling: columns with mask==0 are zeroed
 // canonical <-> internal conversion (fine or coarse level)

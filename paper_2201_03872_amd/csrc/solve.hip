@@ -12,6 +12,7 @@
 // solution uses exactly the iterations up to the one at which it met its own
 // tolerance.  The small Hessenberg least-squares problems are solved on the
 // host after one device->host copy per iteration.
+#include <algorithm>
 #include <chrono>
 #include <complex>
 #include <functional>
@@ -80,7 +81,38 @@ struct LW {
   double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
   int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
   double* d_muc = nullptr;       // [ncol] shifts of the active columns
+  struct GraphState* gs = nullptr;   // captured GMRES steps (unpreconditioned solves)
 };
+
+// Captured Arnoldi steps of an unpreconditioned GMRES(m) on one workspace:
+// one executable graph per step j, valid for one tile count, restart length
+// and set of tile-shape knobs; every buffer a graph touches is owned here or
+// by the workspace, so the recorded pointers stay valid until the workspace
+// is reallocated (which destroys the graphs).
+struct GraphState {
+  int nt = -1, m = 0, ncol = 0;
+  int knobs[6] = {0, 0, 0, 0, 0, 0};
+  double *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr, *d_tol = nullptr, *d_est = nullptr;
+  double *d_n2 = nullptr, *d_cbuf = nullptr, *d_part = nullptr, *d_mu = nullptr, *d_coef = nullptr;
+  int *d_kc = nullptr, *d_done = nullptr;
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> exec;
+};
+
+static void destroy_graphs(ddamg_ctx* c, GraphState* g) {
+  if (!g) return;
+  for (auto e : g->exec)
+    if (e) hipGraphExecDestroy(e);
+  for (auto q : g->graph)
+    if (q) hipGraphDestroy(q);
+  double* dbl[] = {g->d_H, g->d_cs, g->d_sn, g->d_g, g->d_tol, g->d_est, g->d_n2, g->d_cbuf, g->d_part, g->d_mu,
+                   g->d_coef};
+  for (double* p : dbl)
+    if (p) c->pool.release(p);
+  if (g->d_kc) c->pool.release(g->d_kc);
+  if (g->d_done) c->pool.release(g->d_done);
+  delete g;
+}
 
 struct Work {
   std::map<std::tuple<int, int, int>, LW> lw;   // (level, precision, role)
@@ -92,6 +124,8 @@ static Work& work(ddamg_ctx* c) {
 }
 
 void free_work(ddamg_ctx* c) {
+  if (!c->work) return;
+  for (auto& kv : static_cast<Work*>(c->work)->lw) destroy_graphs(c, kv.second.gs);
   delete static_cast<Work*>(c->work);
   c->work = nullptr;
 }
@@ -113,6 +147,8 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     if (w.d_muc) c->pool.release(w.d_muc);
     w.d_map = nullptr;
     w.d_muc = nullptr;
+    destroy_graphs(c, w.gs);
+    w.gs = nullptr;
     w.cap = ntiles;
     w.prec = prec;
     const int ncol = ntiles * c->T;
@@ -309,6 +345,287 @@ static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, 
   for (int i = 0; i < ncol; ++i) beta[i] = host_norm_guard(beta[i]);
 }
 
+// ------------------------------------------------- captured GMRES steps ---
+// Device-side Givens least squares of the per-column Hessenberg matrices, so
+// that an unpreconditioned Arnoldi step needs no host round trip.
+// H: [ncol][m+1][m] complex, cs: [ncol][m], sn: [ncol][m] complex,
+// g: [ncol][m+1] complex; dots: [j+1][ncol] complex (the Gram-Schmidt
+// coefficients of step j), n2: [ncol] squared norms after orthogonalisation.
+__global__ void k_g_init(const double* __restrict__ n2, const double* __restrict__ tol, double* __restrict__ g,
+                         int* __restrict__ kc, int* __restrict__ done, double* __restrict__ est, int m, int ncol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  const double beta = n2[i] > 0 ? sqrt(n2[i]) : 0.0;
+  double* gi = g + (size_t)i * (m + 1) * 2;
+  for (int q = 0; q <= m; ++q) gi[2 * q] = gi[2 * q + 1] = 0.0;
+  gi[0] = beta;
+  const int d = beta <= tol[i] ? 1 : 0;   // also zero columns (tol = beta = 0)
+  done[i] = d;
+  kc[i] = d ? 0 : -1;
+  est[i] = beta;
+}
+
+__global__ void k_g_step(int j, int m, int ncol, const double* __restrict__ dots, const double* __restrict__ n2,
+                         double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                         double* __restrict__ g, int* __restrict__ kc, int* __restrict__ done,
+                         const double* __restrict__ tol, double* __restrict__ est) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  double* Hc = H + (size_t)i * (m + 1) * m * 2;
+  for (int q = 0; q <= j; ++q) {
+    Hc[((size_t)q * m + j) * 2] = dots[((size_t)q * ncol + i) * 2];
+    Hc[((size_t)q * m + j) * 2 + 1] = dots[((size_t)q * ncol + i) * 2 + 1];
+  }
+  const double hn = n2[i] > 0 ? sqrt(n2[i]) : 0.0;
+  Hc[((size_t)(j + 1) * m + j) * 2] = hn;
+  Hc[((size_t)(j + 1) * m + j) * 2 + 1] = 0.0;
+  if (done[i] && kc[i] >= 0) return;
+  double* ci = cs + (size_t)i * m;
+  double* si = sn + (size_t)i * m * 2;
+  for (int q = 0; q < j; ++q) {   // previous rotations
+    double* a = Hc + ((size_t)q * m + j) * 2;
+    double* b = Hc + ((size_t)(q + 1) * m + j) * 2;
+    const double ar = a[0], ai = a[1], br = b[0], bi = b[1];
+    const double c = ci[q], sr = si[2 * q], sim = si[2 * q + 1];
+    // a' = c a + s b ; b' = -conj(s) a + c b
+    a[0] = c * ar + (sr * br - sim * bi);
+    a[1] = c * ai + (sr * bi + sim * br);
+    b[0] = -(sr * ar + sim * ai) + c * br;
+    b[1] = -(sr * ai - sim * ar) + c * bi;
+  }
+  double* a = Hc + ((size_t)j * m + j) * 2;
+  double* b = Hc + ((size_t)(j + 1) * m + j) * 2;
+  const double na = hypot(a[0], a[1]), nb = hypot(b[0], b[1]);
+  double c, sr, sim, rr, ri;
+  if (nb == 0) { c = 1; sr = 0; sim = 0; rr = a[0]; ri = a[1]; }
+  else if (na == 0) { c = 0; sr = b[0] / nb; sim = -b[1] / nb; rr = nb; ri = 0; }
+  else {
+    const double nr = hypot(na, nb);
+    c = na / nr;
+    // s = (a/|a|) conj(b) / nr
+    const double ur = a[0] / na, ui = a[1] / na;
+    sr = (ur * b[0] + ui * b[1]) / nr;
+    sim = (ui * b[0] - ur * b[1]) / nr;
+    rr = ur * nr;
+    ri = ui * nr;
+  }
+  ci[j] = c;
+  si[2 * j] = sr;
+  si[2 * j + 1] = sim;
+  a[0] = rr; a[1] = ri;
+  b[0] = 0; b[1] = 0;
+  double* gi = g + (size_t)i * (m + 1) * 2;
+  const double gr = gi[2 * j], gim = gi[2 * j + 1];
+  gi[2 * j] = c * gr;
+  gi[2 * j + 1] = c * gim;
+  gi[2 * (j + 1)] = -(sr * gr + sim * gim);       // -conj(s) g_j
+  gi[2 * (j + 1) + 1] = -(sr * gim - sim * gr);
+  est[i] = hypot(gi[2 * (j + 1)], gi[2 * (j + 1) + 1]);
+  if (est[i] <= tol[i] || hn == 0) {
+    done[i] = 1;
+    kc[i] = j + 1;
+  }
+}
+
+// y from the rotated triangle (k = kc or jj steps), written as update
+// coefficients coef[q][i] (complex) for q < jj; kc[i] <- k
+__global__ void k_g_solve(int jj, int m, int ncol, const double* __restrict__ H, const double* __restrict__ g,
+                          int* __restrict__ kc, double* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  const int k = kc[i] >= 0 ? kc[i] : jj;
+  kc[i] = k;
+  const double* Hc = H + (size_t)i * (m + 1) * m * 2;
+  const double* gi = g + (size_t)i * (m + 1) * 2;
+  for (int q = jj - 1; q >= k; --q) coef[((size_t)q * ncol + i) * 2] = coef[((size_t)q * ncol + i) * 2 + 1] = 0.0;
+  for (int q = k - 1; q >= 0; --q) {
+    double vr = gi[2 * q], vi = gi[2 * q + 1];
+    for (int p = q + 1; p < k; ++p) {
+      const double hr = Hc[((size_t)q * m + p) * 2], hi = Hc[((size_t)q * m + p) * 2 + 1];
+      const double yr = coef[((size_t)p * ncol + i) * 2], yi = coef[((size_t)p * ncol + i) * 2 + 1];
+      vr -= hr * yr - hi * yi;
+      vi -= hr * yi + hi * yr;
+    }
+    const double dr = Hc[((size_t)q * m + q) * 2], di = Hc[((size_t)q * m + q) * 2 + 1];
+    const double dn = dr * dr + di * di;
+    double yr = 0, yi = 0;
+    if (dn > 0) {   // (vr + i vi) / (dr + i di)
+      yr = (vr * dr + vi * di) / dn;
+      yi = (vi * dr - vr * di) / dn;
+    }
+    coef[((size_t)q * ncol + i) * 2] = yr;
+    coef[((size_t)q * ncol + i) * 2 + 1] = yi;
+  }
+}
+
+static hipStream_t capture_stream(ddamg_ctx* c) {
+  if (!c->cap_stream) DD_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  return c->cap_stream;
+}
+
+static void knob_state(ddamg_ctx* c, int (&k)[6]) {
+  k[0] = c->dslash_rs[0];
+  k[1] = c->dslash_rs[1];
+  k[2] = c->fp32_links;
+  k[3] = c->coarse_mfma;
+  k[4] = c->sap_variant;
+  k[5] = 0;
+}
+
+static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {
+  int k[6];
+  knob_state(c, k);
+  GraphState* g = w.gs;
+  const bool same = g && g->nt == nt && g->m == m && std::equal(k, k + 6, g->knobs);
+  if (same) return *g;
+  destroy_graphs(c, g);
+  g = new GraphState();
+  w.gs = g;
+  g->nt = nt;
+  g->m = m;
+  g->ncol = nt * c->T;
+  std::copy(k, k + 6, g->knobs);
+  const size_t n = g->ncol;
+  auto dal = [&](size_t cnt) { return (double*)c->pool.alloc(std::max<size_t>(cnt, 1) * sizeof(double)); };
+  g->d_H = dal(n * (m + 1) * m * 2);
+  g->d_cs = dal(n * m);
+  g->d_sn = dal(n * m * 2);
+  g->d_g = dal(n * (m + 1) * 2);
+  g->d_tol = dal(n);
+  g->d_est = dal(n);
+  g->d_n2 = dal(n);
+  g->d_cbuf = dal(2 * n);
+  g->d_mu = dal(n);
+  g->d_coef = dal((size_t)KMAX * n * 2);
+  size_t part = 0;
+  const MV v0 = basis(c, w.V, 0, level, w.prec, w.cap, nt);
+  for (int q = 1; q <= m + 1; ++q) part = std::max(part, multidot_partials(v0, q));
+  g->d_part = dal(part);
+  g->d_kc = (int*)c->pool.alloc(n * sizeof(int));
+  g->d_done = (int*)c->pool.alloc(n * sizeof(int));
+  g->graph.assign(m, nullptr);
+  g->exec.assign(m, nullptr);
+  return *g;
+}
+
+// One Arnoldi step j (operator, CGS, norm, normalisation, Givens) on the
+// current stream; used for capture only, so it must not synchronise.
+static void arnoldi_step_device(ddamg_ctx* c, int level, LW& w, GraphState& g, int j) {
+  const int nt = g.nt, prec = w.prec, cap = w.cap;
+  MV vj = basis(c, w.V, j, level, prec, cap, nt);
+  MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
+  operator_apply(c, level, vj, vn, g.d_mu);
+  std::vector<MV> Vs(j + 1);
+  for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
+  mv_multidot_buf(c, Vs.data(), j + 1, vn, w.d_h, g.d_part);
+  mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
+  mv_norm2_buf(c, vn, g.d_n2, g.d_cbuf, g.d_part);
+  mv_normalize(c, vn, g.d_n2);
+  hipLaunchKernelGGL(k_g_step, dim3((g.ncol + 63) / 64), dim3(64), 0, c->stream, j, g.m, g.ncol, w.d_h, g.d_n2,
+                     g.d_H, g.d_cs, g.d_sn, g.d_g, g.d_kc, g.d_done, g.d_tol, g.d_est);
+  DD_HIP(hipGetLastError());
+}
+
+static hipGraphExec_t step_graph(ddamg_ctx* c, int level, LW& w, GraphState& g, int j) {
+  if (g.exec[j]) return g.exec[j];
+  // every basis vector the step touches exists before capture
+  for (int i = 0; i <= j + 1; ++i) basis(c, w.V, i, level, w.prec, w.cap, g.nt);
+  const hipStream_t saved = c->stream;
+  // order the capture after all work already queued on the caller's stream
+  DD_HIP(hipStreamSynchronize(saved));
+  c->stream = capture_stream(c);
+  DD_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    arnoldi_step_device(c, level, w, g, j);
+  } catch (...) {
+    hipStreamEndCapture(c->stream, &graph);
+    if (graph) hipGraphDestroy(graph);
+    c->stream = saved;
+    throw;
+  }
+  const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->stream = saved;
+  DD_HIP(e);
+  g.graph[j] = graph;
+  DD_HIP(hipGraphInstantiate(&g.exec[j], graph, nullptr, nullptr, 0));
+  return g.exec[j];
+}
+
+// Unpreconditioned restarted GMRES(m) whose Arnoldi steps are captured HIP
+// graphs with the least squares on the device: the host only launches one
+// graph per step and reads the convergence flags every few steps.
+static void krylov_graph(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero,
+                         double tol, int m, int maxit, KrylovOut* out) {
+  constexpr int CHECK_EVERY = 4;
+  const int nt = b.ntiles, ncol = b.ncol(), prec = b.prec;
+  LW& w = lw(c, level, prec, nt);
+  GraphState& g = graph_state(c, w, level, nt, m);
+  DD_HIP(hipMemcpyAsync(g.d_mu, d_mu, ncol * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  std::vector<double> bn(ncol), tol_abs(ncol);
+  mv_norm2(c, b, g.d_n2);
+  copy_to_host(c, g.d_n2, bn.data(), ncol * sizeof(double));
+  for (int i = 0; i < ncol; ++i) {
+    bn[i] = host_norm_guard(bn[i]);
+    tol_abs[i] = tol * bn[i];
+  }
+  DD_HIP(hipMemcpyAsync(g.d_tol, tol_abs.data(), ncol * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  std::vector<int> iters(ncol, 0), kc(ncol), done(ncol);
+  std::vector<double> est(ncol);
+  int total = 0;
+  bool first = true;
+  if (x_zero) mv_zero(c, x);
+  while (true) {
+    MV r = basis(c, w.V, 0, level, prec, w.cap, nt);
+    if (x_zero && first) {
+      mv_copy(c, b, r);
+    } else {
+      MV t = get(c, w.res, level, prec, w.cap, nt);
+      operator_apply(c, level, x, t, d_mu);
+      mv_sub(c, b, t, r);
+    }
+    first = false;
+    mv_norm2(c, r, g.d_n2);
+    mv_normalize(c, r, g.d_n2);
+    hipLaunchKernelGGL(k_g_init, dim3((ncol + 63) / 64), dim3(64), 0, c->stream, g.d_n2, g.d_tol, g.d_g, g.d_kc,
+                       g.d_done, g.d_est, m, ncol);
+    DD_HIP(hipGetLastError());
+    copy_to_host(c, g.d_done, done.data(), ncol * sizeof(int));
+    if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; }) || total >= maxit) {
+      copy_to_host(c, g.d_est, est.data(), ncol * sizeof(double));
+      break;
+    }
+    int jj = 0;
+    for (int j = 0; j < m && total < maxit; ++j) {
+      hipGraphExec_t e = step_graph(c, level, w, g, j);
+      DD_HIP(hipGraphLaunch(e, c->stream));
+      ++total;
+      jj = j + 1;
+      if (jj % CHECK_EVERY == 0 || jj == m) {
+        copy_to_host(c, g.d_done, done.data(), ncol * sizeof(int));
+        if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
+      }
+    }
+    hipLaunchKernelGGL(k_g_solve, dim3((ncol + 63) / 64), dim3(64), 0, c->stream, jj, m, ncol, g.d_H, g.d_g,
+                       g.d_kc, g.d_coef);
+    DD_HIP(hipGetLastError());
+    std::vector<MV> B(jj);
+    for (int q = 0; q < jj; ++q) B[q] = basis(c, w.V, q, level, prec, w.cap, nt);
+    mv_multiaxpy(c, B.data(), jj, g.d_coef, x, +1);
+    copy_to_host(c, g.d_kc, kc.data(), ncol * sizeof(int));
+    copy_to_host(c, g.d_est, est.data(), ncol * sizeof(double));
+    copy_to_host(c, g.d_done, done.data(), ncol * sizeof(int));
+    for (int i = 0; i < ncol; ++i) iters[i] += kc[i];
+    if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; }) || total >= maxit) break;
+  }
+  if (out) {
+    out->iters = iters;
+    out->relres.resize(ncol);
+    for (int i = 0; i < ncol; ++i) out->relres[i] = bn[i] > 0 ? est[i] / bn[i] : 0.0;
+    out->total = total;
+  }
+}
+
 // (F)GMRES(m) on level `level` for all columns of b (precision of b/x);
 // preconditioner output precision zprec.  x holds the initial guess unless
 // x_zero.  fixed: run exactly maxit iterations without a convergence test.
@@ -316,6 +633,10 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
             int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out, int role = 0) {
   const int nt = b.ntiles, ncol = b.ncol();
   DD_CHECK(m >= 1 && m < KMAX, DDAMG_EINVAL, "Krylov restart length must be in [1, 63]");
+  if (!pc && !fixed && role == 0 && c->p.use_graphs) {
+    krylov_graph(c, level, d_mu, b, x, x_zero, tol, m, maxit, out);
+    return;
+  }
   LW& w = lw(c, level, b.prec, nt, role);
   std::vector<double> bn(ncol), tol_abs(ncol), est(ncol), beta;
   double* d_n2 = w.d_h + (size_t)KMAX * ncol * 2;

@@ -429,3 +429,42 @@ def test_block_gmres_converges(torch_cuda, dd, precision, mfma):
     assert np.max(np.abs(xb[3] - xb[0])) <= 1e-6 * np.max(np.abs(xb[0]))
     assert max(itb) <= max(itg)
     ctx.close()
+
+
+def test_captured_gmres_steps_match_host_path(torch_cuda, dd):
+    """GMRES on a coarse level with its Arnoldi steps captured as HIP graphs
+    (least squares on the device) gives the iterates of the host-driven
+    GMRES, replay after replay, with other work on the stream in between and
+    after the tile count changes (graphs re-captured)."""
+    torch = torch_cuda
+    say("captured GMRES steps")
+    dims, agg, N = (8, 4, 4, 8), (2, 2, 2, 2), 8
+    U = S.gauge_field(dims, 0.3, 61)
+    V = S.volume(dims)
+    tv = S.gaussian_spinors(N, V, 91)
+    ctxs = []
+    for graphs in (1, 0):
+        p = dd.default_params(dims=dims, kappa=0.15, n_levels=2, sap_block=agg, agg=[agg, (2, 2, 2, 2)], n_tv=[N, 8],
+                              setup_rounds=1, use_graphs=graphs)
+        ctxs.append(dd.Context(p, U, tv_init=[tv]))
+        ctxs[-1].set_test_vectors(0, tv.reshape(N, V, 12))   # P from exactly these vectors
+    blk = Blocking(dims, agg)
+    coarse = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), build_prolongator(tv.reshape(N, V, 12), blk), blk)
+    xf = torch.from_numpy(S.gaussian_spinors(3, V, 92)).cuda()
+    for rep, ncol in enumerate((12, 12, 5, 12, 17)):
+        mus = np.linspace(0.003, 0.3, ncol)
+        b = S.gaussian_coarse(ncol, blk.nblocks, 2 * N, 93 + rep)
+        bg = torch.from_numpy(b).cuda()
+        for prec, tol in ((dd.FP64, 1e-9), (dd.FP32, 1e-4)):
+            xg, itg = ctxs[0].coarse_solve(1, prec, False, mus, bg, tol, 40)
+            ctxs[0].apply_op(0, dd.FP64, np.full(3, 0.01), xf)          # eager work between replays
+            xh, ith = ctxs[1].coarse_solve(1, prec, False, mus, bg, tol, 40)
+            d = np.max(relerr_cols(xg.cpu().numpy(), xh.cpu().numpy()))
+            rel = O.col_norm(b - coarse.apply(xg.cpu().numpy(), mus)) / O.col_norm(b)
+            say(f"  rep {rep} ncol {ncol} prec {prec}: graph vs host {d:.2e}, iterations {max(itg)}/{max(ith)}, "
+                f"worst residual {rel.max():.2e}")
+            assert d < (1e-10 if prec == dd.FP64 else 1e-4)
+            assert itg == ith
+            assert np.all(rel <= (1.5 * tol if prec == dd.FP64 else 1e-2))
+    for ctx in ctxs:
+        ctx.close()
