@@ -34,9 +34,9 @@ WORKLOAD = "tm_16x16x16x32_12rhs_4shift"
 # aggregation hierarchy does not reduce the outer iteration count there.
 SOLVER = dict(n_levels=1, sap_cycles=1, sap_mr_iters=12, outer_restart=40, max_outer=3000)
 # The tuned form: FP64 FGMRES(12) whose every step is an FP32 inner FGMRES of
-# up to 40 steps (to 1e-2) around FP32 SAP; the outer FP64 iteration wins the
-# accuracy back.
-TUNED = dict(SOLVER, outer_restart=12, inner_iters=40, inner_tol=1e-2)
+# up to 40 steps (to 1e-2, Arnoldi basis stored in FP16) around FP32 SAP; the
+# outer FP64 iteration wins the accuracy back.
+TUNED = dict(SOLVER, outer_restart=12, inner_iters=40, inner_tol=1e-2, inner_fp16=1)
 
 
 def log(*a):
@@ -44,20 +44,25 @@ def log(*a):
 
 
 TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_half_fp32_16x16x16x32_48col.md")
+# the FP32 SAP half-sweep kernel of each autotuner variant (4^4 blocks)
+SAP_KERNELS = {0: "k_sap_half<float, 2, 2, 256, true>", 1: "k_sap_half<float, 2, 2, 256, false>",
+               2: "k_sap_half<float, 2, 1, 256, false>"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per launch of the SAP half sweep from the committed counter
-    summary, valid only while the kernel source is unchanged (else None)."""
+    summary, valid only for the same kernel variant while its source is
+    unchanged (else None)."""
     import hashlib
     try:
         note = open(TRAFFIC_NOTE).read()
     except OSError:
         return None
     digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    fields = dict(line.split(":", 1) for line in note.splitlines() if line.startswith(("kernel_source_sha256", "traffic_bytes_per_launch")))
-    if fields.get("kernel_source_sha256", "").strip() != digest:
+    keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "kernel:")
+    fields = dict(line.split(":", 1) for line in note.splitlines() if line.startswith(keys))
+    if fields.get("kernel_source_sha256", "").strip() != digest or fields.get("kernel", "").strip() != kernel:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -331,12 +336,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 outer / f32 preconditioner",
+        "dtype": "f64 outer / f32 inner (f16 basis storage) / f32 preconditioner",
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": "16x16x16x32", "kappa": w.kappa, "n_rhs": w.n_rhs,
                    "shifts": list(w.mus), "columns": ncol, "tol": 1e-10,
-                   "solver": "FP64 FGMRES(12) over FP32 FGMRES(40, to 1e-2) over FP32 red-black SAP "
-                             "(4^4 blocks, 1 cycle, 12 MR steps)",
+                   "solver": "FP64 FGMRES(12) over FP32 FGMRES(40, to 1e-2, FP16 basis) over FP32 red-black "
+                             "SAP (4^4 blocks, 1 cycle, 12 MR steps)",
                    "plain_solver": "FP64 FGMRES(40) over FP64 red-black SAP (same blocks and steps)"},
         "all_converged": tuned["allconv"],
         "worst_true_rel_res": tuned["worst"],
@@ -352,9 +357,9 @@ def main():
                    "fp64_us": t64 * 1e6, "fp64_GBs": bytes64 / t64 / 1e9,
                    "fp64_GFLOPs": 1320 * V * ncol / t64 / 1e9,
                    "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": "k_sap_half<float> (FP32 red-black SAP half sweep, 48 columns)",
+        "roofline": {"kernel": SAP_KERNELS[tuned["tuned"]["sap_variant"]] + " (FP32 red-black SAP half sweep, 48 columns)",
                      "bound": "alu", "achieved": sap_tf, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": sap_tf / 157.3, "traffic": measured_traffic(),
+                     "frac": sap_tf / 157.3, "traffic": measured_traffic(SAP_KERNELS[tuned["tuned"]["sap_variant"]]),
                      "us_per_launch": t_sap * 1e6},
         "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
         "coarse_stencil_48col": coarse,

@@ -100,6 +100,7 @@ typedef struct ddamg_params {
                              /* this many steps (restart 63) around the MG cycle / smoother;     */
                              /* 0: the MG cycle / smoother alone                                 */
   double inner_tol;          /* relative residual at which that inner FGMRES stops early        */
+  int    inner_fp16;         /* 1: that inner FGMRES keeps its Arnoldi basis in FP16 (scaled)   */
   int    middle_restart;     /* FGMRES restart on the middle level                              */
   int    middle_maxit;       /* cap on middle-level iterations per call                         */
   int    bottom_maxit;       /* cap on bottom iterations per call                               */

@@ -55,6 +55,7 @@ class Params(ctypes.Structure):
         ("max_outer", ctypes.c_int),
         ("inner_iters", ctypes.c_int),
         ("inner_tol", ctypes.c_double),
+        ("inner_fp16", ctypes.c_int),
         ("middle_restart", ctypes.c_int),
         ("middle_maxit", ctypes.c_int),
         ("bottom_maxit", ctypes.c_int),

@@ -93,6 +93,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->inner_iters = 0;
   p->use_graphs = 1;
   p->inner_tol = 1e-2;
+  p->inner_fp16 = 0;
   p->col_tile = 8;
   p->seed = 12345;
   p->verbose = 0;

@@ -45,6 +45,9 @@ MV mv_alloc(ddamg_ctx* c, int level, int prec, int ncol_min) {
   a.dof = c->geom[level].dof;
   a.nsites = c->geom[level].V;
   a.nchunk = 2 * a.dof / reals_per_chunk(prec);
+  // FP16 bases hold unit vectors: scale their entries (about 1/sqrt(n)) to
+  // about 1/16, far from the FP16 subnormal and overflow ranges
+  if (prec == P16) a.hscale = std::sqrt((double)a.nsites * a.dof) / 16.0;
   a.p = c->pool.alloc(a.bytes());
   a.owned = true;
   mv_zero(c, a);
@@ -55,6 +58,7 @@ MV mv_like(ddamg_ctx* c, const MV& a, int prec) {
   MV b = a;
   b.prec = prec;
   b.nchunk = 2 * a.dof / reals_per_chunk(prec);
+  b.hscale = prec == P16 ? std::sqrt((double)a.nsites * a.dof) / 16.0 : 1.0;
   b.p = c->pool.alloc(b.bytes());
   b.owned = true;
   mv_zero(c, b);
@@ -204,6 +208,13 @@ __global__ void k_copy(const RS* __restrict__ a, RD* __restrict__ b, size_t n) {
     b[i] = (RD)a[i];
 }
 
+// FP32 <-> FP16 (same layout): b = a * scale
+template <typename RS, typename RD>
+__global__ void k_copy_scaled(const RS* __restrict__ a, RD* __restrict__ b, size_t n, float scale) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (RD)((float)a[i] * scale);
+}
+
 // Column gather / scatter between a full multivector and a compacted one of
 // the same level and precision.  map[j] (j < compact.ncol()) is the full
 // column of compact slot j, or -1 for an empty slot.  dir 0: compact <- full
@@ -249,6 +260,18 @@ void mv_copy(ddamg_ctx* c, const MV& s, const MV& d) {
   DD_CHECK(s.nsites == d.nsites && s.dof == d.dof && s.ntiles == d.ntiles, DDAMG_EINVAL, "mv_copy: shape");
   if (s.prec == d.prec) {
     DD_HIP(hipMemcpyAsync(d.p, s.p, s.bytes(), hipMemcpyDeviceToDevice, c->stream));
+    return;
+  }
+  if (s.prec == P16 || d.prec == P16) {
+    DD_CHECK((s.prec == P32 || d.prec == P32) && s.reals() == d.reals(), DDAMG_EINVAL, "mv_copy: FP16 needs FP32");
+    const size_t n = s.reals();
+    if (d.prec == P16)
+      hipLaunchKernelGGL((k_copy_scaled<float, _Float16>), grid_for(n), dim3(256), 0, c->stream, s.as<float>(),
+                         d.as<_Float16>(), n, (float)d.hscale);
+    else
+      hipLaunchKernelGGL((k_copy_scaled<_Float16, float>), grid_for(n), dim3(256), 0, c->stream, s.as<_Float16>(),
+                         d.as<float>(), n, (float)(1.0 / s.hscale));
+    DD_HIP(hipGetLastError());
     return;
   }
   // chunk widths differ between precisions: convert through the complex index
@@ -418,9 +441,9 @@ struct PtrPack {
 // handles one group of KB basis vectors (blockIdx.z): the KB accumulators
 // are statically indexed registers; w is re-read once per group.
 constexpr int KB = 8;
-template <typename R>
+template <typename R, typename RV = R>
 __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* __restrict__ w, double* __restrict__ part,
-                                                   size_t M, int ntiles, int ncol) {
+                                                   size_t M, int ntiles, int ncol, double vscale) {
   constexpr int RW = Chunk<R>::RW;
   constexpr int T = TTB;
   const int t = threadIdx.x % T, row = threadIdx.x / T;
@@ -432,9 +455,9 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
   double accr[KB], acci[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) { accr[j] = 0; acci[j] = 0; }
-  const R* vp[KB];
+  const RV* vp[KB];
 #pragma unroll
-  for (int j = 0; j < KB; ++j) vp[j] = reinterpret_cast<const R*>(Vs.p[j0 + (j < kk ? j : 0)]);
+  for (int j = 0; j < KB; ++j) vp[j] = reinterpret_cast<const RV*>(Vs.p[j0 + (j < kk ? j : 0)]);
   for (size_t m = (size_t)blockIdx.x * 32 + row; m < M; m += (size_t)nbM * 32) {
     const size_t off = (size_t)tile * tile_reals + (m * T + t) * RW;
     R wv[RW];
@@ -443,7 +466,7 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       if (j < kk) {
-        const R* v = vp[j] + off;
+        const RV* v = vp[j] + off;
 #pragma unroll
         for (int r = 0; r < RW; r += 2) {
           const double vr = v[r], vi = v[r + 1], xr = wv[r], xi = wv[r + 1];
@@ -474,8 +497,8 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
     for (int w4 = 0; w4 < 4; ++w4) { a += red[w4][tt][j][0]; b += red[w4][tt][j][1]; }
     const int col = tile * T + tt;
     double* pp = part + (((size_t)blockIdx.x * k + j0 + j) * ncol + col) * 2;
-    pp[0] = a;
-    pp[1] = b;
+    pp[0] = a * vscale;
+    pp[1] = b * vscale;
   }
 }
 
@@ -512,10 +535,13 @@ void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_o
   DD_CHECK(k >= 1 && k <= MAXK, DDAMG_EINVAL, "mv_multidot: k");
   DD_CHECK(w.T == TTB, DDAMG_EINVAL, "mv_multidot: tile width");
   PtrPack pk;
+  const bool half = Vs[0].prec == P16 && w.prec == P32;
   for (int j = 0; j < k; ++j) {
-    DD_CHECK(Vs[j].prec == w.prec && Vs[j].reals() == w.reals(), DDAMG_EINVAL, "mv_multidot: shape");
+    DD_CHECK((Vs[j].prec == w.prec || half) && Vs[j].prec == Vs[0].prec && Vs[j].reals() == w.reals(), DDAMG_EINVAL,
+             "mv_multidot: shape");
     pk.p[j] = Vs[j].p;
   }
+  const double vscale = half ? 1.0 / Vs[0].hscale : 1.0;
   const size_t M = (size_t)w.nchunk * w.nsites;
   const int ngroups = (k + KB - 1) / KB;
   const int nbM = multidot_nbm(w, k);
@@ -524,10 +550,13 @@ void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_o
   dim3 grid(nbM, w.ntiles, ngroups);
   if (w.prec == P64)
     hipLaunchKernelGGL(k_multidot1<double>, grid, dim3(256), 0, c->stream, pk, k, w.as<double>(), part, M, w.ntiles,
-                       ncol);
+                       ncol, 1.0);
+  else if (half)
+    hipLaunchKernelGGL((k_multidot1<float, _Float16>), grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M,
+                       w.ntiles, ncol, vscale);
   else
     hipLaunchKernelGGL(k_multidot1<float>, grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M, w.ntiles,
-                       ncol);
+                       ncol, 1.0);
   DD_HIP(hipGetLastError());
   const int n = k * ncol;
   hipLaunchKernelGGL(k_multidot2, dim3((n + 255) / 256), dim3(256), 0, c->stream, part, d_out, nbM, k, ncol);
@@ -555,6 +584,7 @@ void mv_norm2_buf(ddamg_ctx* c, const MV& a, double* d_out, double* cbuf, double
 template <typename RV, typename RWt>
 __global__ void k_multiaxpy(PtrPack Vs, int k, const double* __restrict__ coef, RWt* __restrict__ w, size_t npairs,
                             int T, int RWp, size_t tile_pairs, int ncol, double sign) {
+  // sign also carries the inverse storage scale of an FP16 basis
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
     const int tile = (int)(i / tile_pairs);
     const int t = (int)((i / RWp) % T);
@@ -609,6 +639,14 @@ void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const
     pk.p[j] = Vs[j].p;
   }
   const size_t n = npairs_of(w);
+  if (Vs[0].prec == P16) {
+    DD_CHECK(w.prec == P32, DDAMG_EINVAL, "mv_multiaxpy: FP16 basis needs FP32 w");
+    hipLaunchKernelGGL((k_multiaxpy<_Float16, float>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<float>(), n, w.T, reals_per_chunk(P32) / 2, tile_pairs_of(w), w.ncol(),
+                       (double)sign / Vs[0].hscale);
+    DD_HIP(hipGetLastError());
+    return;
+  }
   if (Vs[0].prec != w.prec) {
     DD_CHECK(Vs[0].prec == P32 && w.prec == P64, DDAMG_EINVAL, "mv_multiaxpy: precisions");
     hipLaunchKernelGGL(k_multiaxpy_mixed, grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<double>(), n,

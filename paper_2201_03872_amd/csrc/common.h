@@ -48,10 +48,12 @@ struct Error {
     if (!(cond)) throw ::ddamg::Error{(code), (msg)};    \
   } while (0)
 
-enum Prec { P64 = 0, P32 = 1 };
+// P16: FP16 storage in the FP32 layout (two complexes per chunk, 8-byte
+// chunks), used for Krylov bases only; a P16 multivector stores v * hscale.
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
 inline int reals_per_chunk(int prec) { return prec == P64 ? 2 : 4; }
-inline size_t real_size(int prec) { return prec == P64 ? 8 : 4; }
+inline size_t real_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
 // One multivector in the column-tiled layout.
 struct MV {
@@ -63,6 +65,7 @@ struct MV {
   int nsites = 0;
   int dof = 0;      // complex components per site
   bool owned = false;
+  double hscale = 1.0;   // P16: stored value = value * hscale
 
   int ncol() const { return ntiles * T; }
   size_t tile_reals() const { return (size_t)nchunk * nsites * T * reals_per_chunk(prec); }

@@ -77,6 +77,8 @@ struct LW {
   std::vector<MV> V, Z;
   MV zt, rc, ec, res, s, q, rho;
   MV cb, cx, cb2, cx2;           // outer solve: active right-hand sides / solutions (ping-pong)
+  int vprec = -1;                // storage precision of the Arnoldi basis V (P16 or the working precision)
+  MV wt, vi;                     // FP16 basis: working-precision new vector and preconditioner input
   double* d_h = nullptr;         // [KMAX][ncol] complex dots + [ncol] norm
   double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
   int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
@@ -134,10 +136,12 @@ void free_work(ddamg_ctx* c) {
 // for the inner FGMRES of the outer solve (same level, its own basis).
 static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
   LW& w = work(c).lw[{level, prec, role}];
+  // the inner FGMRES of the outer solve may keep its basis in FP16
+  if (w.vprec < 0) w.vprec = (role == 1 && prec == P32 && c->p.inner_fp16) ? P16 : prec;
   if (ntiles > w.cap) {
     for (auto& m : w.V) mv_free(c, m);
     for (auto& m : w.Z) mv_free(c, m);
-    MV* all[] = {&w.zt, &w.rc, &w.ec, &w.res, &w.s, &w.q, &w.rho, &w.cb, &w.cx, &w.cb2, &w.cx2};
+    MV* all[] = {&w.zt, &w.rc, &w.ec, &w.res, &w.s, &w.q, &w.rho, &w.cb, &w.cx, &w.cb2, &w.cx2, &w.wt, &w.vi};
     for (MV* m : all) mv_free(c, *m);
     w.V.clear();
     w.Z.clear();
@@ -199,9 +203,11 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
                        int zprec, int budget, bool fixed, const std::vector<double>& beta, std::vector<char>& done,
                        const std::vector<double>& tol_abs, std::vector<double>& est, const std::vector<double>& bn,
                        Cycle& cy, double* d_n2, int& total) {
-  const int prec = x.prec, ncol = nt * c->T, cap = w.cap, m = cy.m;
-  MV r = basis(c, w.V, 0, level, prec, cap, nt);
+  const int prec = x.prec, ncol = nt * c->T, cap = w.cap, m = cy.m, vprec = w.vprec;
+  const bool half = vprec != prec;   // FP16 basis: new vectors are formed in the working precision
+  MV r = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, 0, level, vprec, cap, nt);
   mv_normalize(c, r, d_n2);
+  if (half) mv_copy(c, r, basis(c, w.V, 0, level, vprec, cap, nt));
   for (int i = 0; i < ncol; ++i) {
     cy.kc[i] = done[i] ? 0 : -1;
     for (int j = 0; j <= m; ++j) cy.g[(size_t)i * (m + 1) + j] = 0;
@@ -209,13 +215,18 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
   }
   int jj = 0;
   for (int j = 0; j < m && j < budget; ++j) {
-    MV vj = basis(c, w.V, j, level, prec, cap, nt);
+    MV vj = basis(c, w.V, j, level, vprec, cap, nt);
+    if (half) {
+      MV v32 = get(c, w.vi, level, prec, cap, nt);
+      mv_copy(c, vj, v32);
+      vj = v32;
+    }
     MV z = vj;
     if (pc) {
       z = basis(c, w.Z, j, level, zprec, cap, nt);
       (*pc)(vj, z, d_mu);
     }
-    MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
+    MV vn = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, j + 1, level, vprec, cap, nt);
     if (z.prec != prec) {
       MV zt = get(c, w.zt, level, prec, cap, nt);
       mv_copy(c, z, zt);
@@ -224,7 +235,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
       operator_apply(c, level, z, vn, d_mu);
     }
     std::vector<MV> Vs(j + 1);
-    for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
+    for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, vprec, cap, nt);
     mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
     mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
     mv_norm2(c, vn, d_n2);
@@ -233,6 +244,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
     copy_to_host(c, d_n2, cy.hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
     mv_normalize(c, vn, d_n2);
+    if (half) mv_copy(c, vn, basis(c, w.V, j + 1, level, vprec, cap, nt));
     ++total;
     jj = j + 1;
     bool alld = true;
@@ -318,7 +330,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
                           c->stream));
     std::vector<MV> B(jj);
     for (int q = 0; q < jj; ++q)
-      B[q] = pc ? basis(c, w.Z, q, level, zprec, cap, nt) : basis(c, w.V, q, level, prec, cap, nt);
+      B[q] = pc ? basis(c, w.Z, q, level, zprec, cap, nt) : basis(c, w.V, q, level, vprec, cap, nt);
     mv_multiaxpy(c, B.data(), jj, w.d_aux, x, +1);
     DD_HIP(hipStreamSynchronize(c->stream));   // coef is a host vector reused next cycle
   }
@@ -329,7 +341,9 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
 static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, const MV& x, const double* d_mu,
                            bool x_is_zero, double* d_n2, std::vector<double>& beta) {
   const int prec = b.prec, ncol = nt * c->T;
-  MV r = basis(c, w.V, 0, level, prec, w.cap, nt);
+  // the residual lands where gmres_cycle normalises it: V[0], or the
+  // working-precision vector when the basis is stored in FP16
+  MV r = w.vprec != prec ? get(c, w.wt, level, prec, w.cap, nt) : basis(c, w.V, 0, level, prec, w.cap, nt);
   if (x_is_zero) {
     mv_copy(c, b, r);
   } else if (level == 0) {
