@@ -245,7 +245,9 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             the block's 2-row links staged in LDS; 1 2 columns, links
                                             read through L1/L2; 2 one column, links through L1/L2
                                             (less LDS per workgroup, more workgroups per CU) */
-#define DDAMG_N_KNOBS 5
+#define DDAMG_KNOB_DSLASH_ORDER      5   /* fine stencil dispatch: 0 (default) storage order of the site
+                                            ranges; 1 ranges sorted by time slice */
+#define DDAMG_N_KNOBS 6
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

@@ -327,7 +327,8 @@ class Context:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2, "coarse_mfma": 3,
-             "sap_variant": 4}
+             "sap_variant": 4,
+             "dslash_order": 5}
 
     # ---- learned smoother ----
     def set_smoother_weights(self, w1, w2):

@@ -550,6 +550,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_FP32_LINKS: return &c->fp32_links;
     case DDAMG_KNOB_COARSE_MFMA: return &c->coarse_mfma;
     case DDAMG_KNOB_SAP_VARIANT: return &c->sap_variant;
+    case DDAMG_KNOB_DSLASH_ORDER: return &c->dslash_order;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -561,6 +562,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
     case DDAMG_KNOB_COARSE_MFMA: return value == 0 || value == 1;
     case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 2;
+    case DDAMG_KNOB_DSLASH_ORDER: return value == 0 || value == 1;
     default: return false;
   }
 }
@@ -586,34 +588,44 @@ int ddamg_get_tuning(ddamg_ctx* c, int knob, int* value) {
 int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
   return guarded([&]() -> int {
     DD_CHECK(c && n_col >= 1, DDAMG_EINVAL, "bad arguments");
-    // FP64 stencil: sites per workgroup
+    // Stencil dispatch order x FP64 sites per workgroup x FP32 (link storage,
+    // sites per workgroup); the order is shared, so it is chosen on the sum of
+    // the best FP64 and FP32 times.
     {
-      double best = 1e30;
-      int bestv = c->dslash_rs[P64];
-      for (int v : {16, 32, 64}) {
-        c->dslash_rs[P64] = v;
-        double sec = 0;
-        const int st = ddamg_time_op(c, 0, 0, DDAMG_FP64, n_col, 10, &sec);
-        if (st != DDAMG_OK) return st;
-        if (sec < best) { best = sec; bestv = v; }
-      }
-      c->dslash_rs[P64] = bestv;
-    }
-    // FP32 stencil: link storage x sites per workgroup
-    {
-      double best = 1e30;
-      int bl = c->fp32_links, bs = c->dslash_rs[P32];
-      for (int lk : {0, 1})
-        for (int v : {32, 64, 128}) {
-          c->fp32_links = lk;
-          c->dslash_rs[P32] = v;
+      double best_all = 1e30;
+      int bo = c->dslash_order, b64 = c->dslash_rs[P64], bl = c->fp32_links, b32 = c->dslash_rs[P32];
+      for (int ord : {0, 1}) {
+        c->dslash_order = ord;
+        double best64 = 1e30, best32 = 1e30;
+        int v64 = b64, l32 = bl, v32 = b32;
+        for (int v : {16, 32, 64}) {
+          c->dslash_rs[P64] = v;
           double sec = 0;
-          const int st = ddamg_time_op(c, 0, 0, DDAMG_FP32, n_col, 10, &sec);
+          const int st = ddamg_time_op(c, 0, 0, DDAMG_FP64, n_col, 10, &sec);
           if (st != DDAMG_OK) return st;
-          if (sec < best) { best = sec; bl = lk; bs = v; }
+          if (sec < best64) { best64 = sec; v64 = v; }
         }
+        for (int lk : {0, 1})
+          for (int v : {32, 64, 128}) {
+            c->fp32_links = lk;
+            c->dslash_rs[P32] = v;
+            double sec = 0;
+            const int st = ddamg_time_op(c, 0, 0, DDAMG_FP32, n_col, 10, &sec);
+            if (st != DDAMG_OK) return st;
+            if (sec < best32) { best32 = sec; l32 = lk; v32 = v; }
+          }
+        if (best64 + best32 < best_all) {
+          best_all = best64 + best32;
+          bo = ord;
+          b64 = v64;
+          bl = l32;
+          b32 = v32;
+        }
+      }
+      c->dslash_order = bo;
+      c->dslash_rs[P64] = b64;
       c->fp32_links = bl;
-      c->dslash_rs[P32] = bs;
+      c->dslash_rs[P32] = b32;
     }
     // FP32 SAP on 4^4 blocks: columns per workgroup x links in LDS or through the caches
     if (c->geom[0].gsize == 256) {

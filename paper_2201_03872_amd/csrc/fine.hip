@@ -13,6 +13,9 @@
 // (bit 31 of the neighbour table), never folded into the links: with 2-row
 // compression the third row is rebuilt as conj(row0 x row1), which would lose
 // a sign stored in the link.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 #include "device.h"
 
@@ -252,14 +255,17 @@ template <typename R, int LK, int MODE, int RS>
 __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x, R* __restrict__ y,
                                                         const R* __restrict__ b, const void* __restrict__ U,
                                                         const int* __restrict__ nbr, const double* __restrict__ mu,
-                                                        int V, size_t tile_reals, R diag, int nsb) {
+                                                        int V, size_t tile_reals, R diag, int nsb,
+                                                        const int* __restrict__ order) {
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW, NCH = 24 / RW;
   __shared__ C lds[NCH * RS * TT];
   const int t = threadIdx.x % TT, sl = threadIdx.x / TT;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = wg / nsb;
-  const int r0 = (wg % nsb) * RS;
+  // site ranges in storage order, or (order) sorted by time slice so that the
+  // ranges in flight on an XCD form a thin t-slab whose neighbours stay in L2
+  const int r0 = order ? order[wg % nsb] : (wg % nsb) * RS;
   const int s = r0 + sl;
   const bool active = s < V;
   const R* xt = x + (size_t)tile * tile_reals;
@@ -492,13 +498,38 @@ static inline int nsb_of(int V) { return (V + SPW - 1) / SPW; }
 // Sites per workgroup of the LDS-staged stencil: a tile-shape knob chosen by
 // the autotuner (more sites = more neighbours served from LDS, fewer
 // workgroups resident per CU).
+// Start sites of the RS-site ranges sorted by the time coordinate of their
+// first site (stable, so block order is kept within a time slice).
+static const int* dslash_order(ddamg_ctx* c, int RS) {
+  int slot = 0;
+  while ((16 << slot) < RS) ++slot;
+  if (!c->d_dslash_order[slot]) {
+    const LevelGeom& g = c->geom[0];
+    const int nsb = (g.V + RS - 1) / RS;
+    std::vector<std::pair<int, int>> key(nsb);
+    for (int q = 0; q < nsb; ++q) {
+      const int can = g.int2can[(size_t)q * RS];
+      const int tcoord = can / (g.dims[0] * g.dims[1] * g.dims[2]);
+      key[q] = {tcoord, q};
+    }
+    std::stable_sort(key.begin(), key.end());
+    std::vector<int> r0(nsb);
+    for (int q = 0; q < nsb; ++q) r0[q] = key[q].second * RS;
+    int* d = (int*)c->pool.alloc(nsb * sizeof(int));
+    DD_HIP(hipMemcpy(d, r0.data(), nsb * sizeof(int), hipMemcpyHostToDevice));
+    c->d_dslash_order[slot] = d;
+  }
+  return c->d_dslash_order[slot];
+}
+
 template <typename R, int LK, int MODE, int RS>
 static void launch_rs(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu, const void* U) {
   const int V = c->geom[0].V;
   const int nsb = (V + RS - 1) / RS;
+  const int* order = c->dslash_order ? dslash_order(c, RS) : nullptr;
   hipLaunchKernelGGL((k_dslash_lds<R, LK, MODE, RS>), dim3(nsb * x.ntiles), dim3(RS * TT), 0, c->stream, x.as<R>(),
                      y.as<R>(), b ? b->as<R>() : nullptr, U, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), (R)c->diag,
-                     nsb);
+                     nsb, order);
 }
 
 bool dslash_rs_valid(int prec, int rs) {

@@ -483,7 +483,7 @@ static void knob_state(ddamg_ctx* c, int (&k)[6]) {
   k[2] = c->fp32_links;
   k[3] = c->coarse_mfma;
   k[4] = c->sap_variant;
-  k[5] = 0;
+  k[5] = c->dslash_order;
 }
 
 static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {

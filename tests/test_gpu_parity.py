@@ -73,18 +73,20 @@ def test_fine_operator_fp64_and_fp32(torch_cuda, dd, dims, blk, ncol):
     xg = torch.from_numpy(x).cuda()
     y64 = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
     assert np.max(relerr_cols(y64, ref)) < 1e-13
-    for links in (0, 1):                      # full FP32 links / 2-row compressed
-        ctx.set_tuning("fp32_links", links)
-        for sites in (32, 64, 128):
-            ctx.set_tuning("dslash_sites_fp32", sites)
-            y32 = ctx.apply_op(0, dd.FP32, mus, xg).cpu().numpy()
-            e32 = np.max(relerr_cols(y32, ref))
-            say("  fp32 relative error", links, sites, e32)
-            assert e32 < 2e-6
-    for sites in (16, 32, 64):
-        ctx.set_tuning("dslash_sites_fp64", sites)
-        y64 = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
-        assert np.max(relerr_cols(y64, ref)) < 1e-13
+    for order in (0, 1):                      # storage order / time-slice order of the site ranges
+        ctx.set_tuning("dslash_order", order)
+        for links in (0, 1):                  # full FP32 links / 2-row compressed
+            ctx.set_tuning("fp32_links", links)
+            for sites in (32, 64, 128):
+                ctx.set_tuning("dslash_sites_fp32", sites)
+                y32 = ctx.apply_op(0, dd.FP32, mus, xg).cpu().numpy()
+                e32 = np.max(relerr_cols(y32, ref))
+                say("  fp32 relative error", order, links, sites, e32)
+                assert e32 < 2e-6
+        for sites in (16, 32, 64):
+            ctx.set_tuning("dslash_sites_fp64", sites)
+            y64 = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
+            assert np.max(relerr_cols(y64, ref)) < 1e-13
     ctx.close()
 
 
