@@ -580,25 +580,34 @@ void mv_norm2_buf(ddamg_ctx* c, const MV& a, double* d_out, double* cbuf, double
   DD_HIP(hipGetLastError());
 }
 
-// w += sign * sum_j coef[j][col] V_j   (coef complex, V_j precision RV, w precision RW_)
-template <typename RV, typename RWt>
-__global__ void k_multiaxpy(PtrPack Vs, int k, const double* __restrict__ coef, RWt* __restrict__ w, size_t npairs,
-                            int T, int RWp, size_t tile_pairs, int ncol, double sign) {
-  // sign also carries the inverse storage scale of an FP16 basis
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
-    const int tile = (int)(i / tile_pairs);
-    const int t = (int)((i / RWp) % T);
-    const int col = tile * T + t;
-    double ar = 0, ai = 0;
+// w += sign * sum_j coef[j][col] V_j, one layout chunk (RW reals of w, the
+// same positions of every V_j) per thread, so each lane moves 16 bytes of w
+// and 16 (FP32/FP64) or 8 (FP16) bytes of every basis vector per load.
+template <typename RV, typename RWt, int RW>
+__global__ void k_multiaxpy_chunk(PtrPack Vs, int k, const double* __restrict__ coef, RWt* __restrict__ w,
+                                  size_t nunits, int T, size_t tile_units, int ncol, double sign) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const int tile = (int)(u / tile_units);
+    const int col = tile * T + (int)(u % T);
+    double acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = 0.0;
     for (int j = 0; j < k; ++j) {
-      const RV* v = reinterpret_cast<const RV*>(Vs.p[j]);
+      const RV* v = reinterpret_cast<const RV*>(Vs.p[j]) + u * RW;
       const double cr = coef[((size_t)j * ncol + col) * 2], ci = coef[((size_t)j * ncol + col) * 2 + 1];
-      const double vr = v[2 * i], vi = v[2 * i + 1];
-      ar += cr * vr - ci * vi;
-      ai += cr * vi + ci * vr;
+      RV vv[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) vv[r] = v[r];
+#pragma unroll
+      for (int r = 0; r < RW; r += 2) {
+        const double vr = vv[r], vi = vv[r + 1];
+        acc[r] += cr * vr - ci * vi;
+        acc[r + 1] += cr * vi + ci * vr;
+      }
     }
-    w[2 * i] = (RWt)((double)w[2 * i] + sign * ar);
-    w[2 * i + 1] = (RWt)((double)w[2 * i + 1] + sign * ai);
+    RWt* wp = w + u * RW;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) wp[r] = (RWt)((double)wp[r] + sign * acc[r]);
   }
 }
 
@@ -639,28 +648,28 @@ void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const
     pk.p[j] = Vs[j].p;
   }
   const size_t n = npairs_of(w);
+  const size_t nunits = (size_t)w.ntiles * w.nchunk * w.nsites * w.T;
+  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
   if (Vs[0].prec == P16) {
     DD_CHECK(w.prec == P32, DDAMG_EINVAL, "mv_multiaxpy: FP16 basis needs FP32 w");
-    hipLaunchKernelGGL((k_multiaxpy<_Float16, float>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef,
-                       w.as<float>(), n, w.T, reals_per_chunk(P32) / 2, tile_pairs_of(w), w.ncol(),
-                       (double)sign / Vs[0].hscale);
+    hipLaunchKernelGGL((k_multiaxpy_chunk<_Float16, float, 4>), grid_for(nunits), dim3(256), 0, c->stream, pk, k,
+                       d_coef, w.as<float>(), nunits, w.T, tile_units, w.ncol(), (double)sign / Vs[0].hscale);
     DD_HIP(hipGetLastError());
     return;
   }
-  if (Vs[0].prec != w.prec) {
-    DD_CHECK(Vs[0].prec == P32 && w.prec == P64, DDAMG_EINVAL, "mv_multiaxpy: precisions");
-    hipLaunchKernelGGL(k_multiaxpy_mixed, grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<double>(), n,
-                       w.T, w.nsites, tile_pairs_of(w), tile_pairs_of(Vs[0]), w.ncol(), (double)sign);
+  if (Vs[0].prec == w.prec) {
+    if (w.prec == P64)
+      hipLaunchKernelGGL((k_multiaxpy_chunk<double, double, 2>), grid_for(nunits), dim3(256), 0, c->stream, pk, k,
+                         d_coef, w.as<double>(), nunits, w.T, tile_units, w.ncol(), (double)sign);
+    else
+      hipLaunchKernelGGL((k_multiaxpy_chunk<float, float, 4>), grid_for(nunits), dim3(256), 0, c->stream, pk, k,
+                         d_coef, w.as<float>(), nunits, w.T, tile_units, w.ncol(), (double)sign);
     DD_HIP(hipGetLastError());
     return;
   }
-  const int RWp = reals_per_chunk(w.prec) / 2;
-  if (w.prec == P64)
-    hipLaunchKernelGGL((k_multiaxpy<double, double>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef,
-                       w.as<double>(), n, w.T, RWp, tile_pairs_of(w), w.ncol(), (double)sign);
-  else
-    hipLaunchKernelGGL((k_multiaxpy<float, float>), grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<float>(),
-                       n, w.T, RWp, tile_pairs_of(w), w.ncol(), (double)sign);
+  DD_CHECK(Vs[0].prec == P32 && w.prec == P64, DDAMG_EINVAL, "mv_multiaxpy: precisions");
+  hipLaunchKernelGGL(k_multiaxpy_mixed, grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<double>(), n, w.T,
+                     w.nsites, tile_pairs_of(w), tile_pairs_of(Vs[0]), w.ncol(), (double)sign);
   DD_HIP(hipGetLastError());
 }
 
