@@ -72,10 +72,12 @@ def measured_traffic(kernel):
 
 
 def sap_flops_per_half_sweep(V, ncol, mr):
-    """Algorithmic flops of one red-black SAP half sweep (half the sites):
-    the block residual (1 stencil) + mr MR steps (1 block stencil, two
-    inner products and two axpys per step), per site and column."""
-    per_site = (1 + mr) * 1320 + mr * (8 * 12 + 2 * 8 * 12)
+    """Algorithmic flops of one red-black SAP half sweep (half the sites),
+    averaged over the two half sweeps of a one-cycle SAP call: mr MR steps
+    (1 block stencil, two inner products and two axpys per step) each, plus
+    the block residual (1 stencil) in the second one only (the first starts
+    from x = 0, where the residual is the right-hand side)."""
+    per_site = 0.5 * 1320 + mr * (1320 + 8 * 12 + 2 * 8 * 12)
     return V / 2 * ncol * per_site
 
 

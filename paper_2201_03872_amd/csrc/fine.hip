@@ -372,7 +372,8 @@ template <typename R, int LK, int K, int BS, bool ULDS>
 __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
-                                                     int V, int ntiles, size_t tile_reals, R diag, int mr_iters) {
+                                                     int V, int ntiles, size_t tile_reals, R diag, int mr_iters,
+                                                     int x_zero) {
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW;
   constexpr int NCH = 24 / RW;
@@ -399,11 +400,15 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   R* xt = x + (size_t)tile * tile_reals;
   const R m = (R)mu[tile * TT + t];
 
-  // 1. block residual
+  // 1. block residual (x_zero: the first half-sweep from x = 0, residual = f)
   int e8[8];
   load_nbrs(nbr, V, s, e8);
   cx<R> rho[12], dl[12], q[12];
-  {
+  if (x_zero) {
+    load_cx<R, 12>(ft, V, TT, s, t, rho);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) dl[k] = {0, 0};
+  } else {
     auto ldg = [&](int, int nb, cx<R>(&p)[12]) {
       load_cx<R, 12>(xt, V, TT, nb, t, p);
       return true;
@@ -485,11 +490,15 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
     }
   }
   // 3. update
-  cx<R> xs[12];
-  load_cx<R, 12>(xt, V, TT, s, t, xs);
+  if (x_zero) {
+    store_cx<R, 12>(xt, V, TT, s, t, dl);
+  } else {
+    cx<R> xs[12];
+    load_cx<R, 12>(xt, V, TT, s, t, xs);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) xs[k] = xs[k] + dl[k];
-  store_cx<R, 12>(xt, V, TT, s, t, xs);
+    for (int k = 0; k < 12; ++k) xs[k] = xs[k] + dl[k];
+    store_cx<R, 12>(xt, V, TT, s, t, xs);
+  }
 }
 
 // ------------------------------------------------------------ wrappers ---
@@ -582,13 +591,13 @@ void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
 }
 
 template <typename R, int LK, int K, int BS, bool ULDS = true>
-static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour) {
+static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
   hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
                      LK == LK_C ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
                      c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
-                     c->p.sap_mr_iters);
+                     c->p.sap_mr_iters, x_zero);
   DD_HIP(hipGetLastError());
 }
 
@@ -597,15 +606,17 @@ void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const
   const int BS = c->geom[0].gsize;
   for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour) {
+      // the first half-sweep starts from x = 0: its block residual is f itself
+      const int xz = (cyc == 0 && colour == 0) ? 1 : 0;
       if (x.prec == P64) {
-        if (BS == 256) launch_sap<double, LK_D, 1, 256>(c, f, x, d_mu, colour);
-        else if (BS == 16) launch_sap<double, LK_D, 4, 16>(c, f, x, d_mu, colour);
+        if (BS == 256) launch_sap<double, LK_D, 1, 256>(c, f, x, d_mu, colour, xz);
+        else if (BS == 16) launch_sap<double, LK_D, 4, 16>(c, f, x, d_mu, colour, xz);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       } else {
-        if (BS == 256 && c->sap_variant == 0) launch_sap<float, LK_C, 2, 256, true>(c, f, x, d_mu, colour);
-        else if (BS == 256 && c->sap_variant == 1) launch_sap<float, LK_C, 2, 256, false>(c, f, x, d_mu, colour);
-        else if (BS == 256) launch_sap<float, LK_C, 1, 256, false>(c, f, x, d_mu, colour);
-        else if (BS == 16) launch_sap<float, LK_C, 8, 16>(c, f, x, d_mu, colour);
+        if (BS == 256 && c->sap_variant == 0) launch_sap<float, LK_C, 2, 256, true>(c, f, x, d_mu, colour, xz);
+        else if (BS == 256 && c->sap_variant == 1) launch_sap<float, LK_C, 2, 256, false>(c, f, x, d_mu, colour, xz);
+        else if (BS == 256) launch_sap<float, LK_C, 1, 256, false>(c, f, x, d_mu, colour, xz);
+        else if (BS == 16) launch_sap<float, LK_C, 8, 16>(c, f, x, d_mu, colour, xz);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};
       }
     }
