@@ -245,9 +245,13 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             the block's 2-row links staged in LDS; 1 2 columns, links
                                             read through L1/L2; 2 one column, links through L1/L2
                                             (less LDS per workgroup, more workgroups per CU) */
-#define DDAMG_KNOB_DSLASH_ORDER      5   /* fine stencil dispatch: 0 (default) storage order of the site
-                                            ranges; 1 ranges sorted by time slice */
-#define DDAMG_N_KNOBS 6
+#define DDAMG_KNOB_DSLASH_ORDER      5   /* fine stencil scheme: 0 (default) site ranges staged in LDS,
+                                            storage order; 1 the same in time-slice order; 2 / 3
+                                            t-walk over columns of 4^4 blocks (psi(t-1..t+1) in
+                                            registers, 4 / 8 columns per workgroup; 4^4 SAP blocks only) */
+#define DDAMG_KNOB_WALK_SEGMENTS     6   /* t-walk stencil: segments of the t direction, one workgroup
+                                            each (1, 2, 4 or 8; must divide Lt, else 1) */
+#define DDAMG_N_KNOBS 7
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

@@ -551,6 +551,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_COARSE_MFMA: return &c->coarse_mfma;
     case DDAMG_KNOB_SAP_VARIANT: return &c->sap_variant;
     case DDAMG_KNOB_DSLASH_ORDER: return &c->dslash_order;
+    case DDAMG_KNOB_WALK_SEGMENTS: return &c->walk_seg;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -562,7 +563,8 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
     case DDAMG_KNOB_COARSE_MFMA: return value == 0 || value == 1;
     case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 2;
-    case DDAMG_KNOB_DSLASH_ORDER: return value == 0 || value == 1;
+    case DDAMG_KNOB_DSLASH_ORDER: return value >= 0 && value <= 3;
+    case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
     default: return false;
   }
 }
@@ -588,41 +590,54 @@ int ddamg_get_tuning(ddamg_ctx* c, int knob, int* value) {
 int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
   return guarded([&]() -> int {
     DD_CHECK(c && n_col >= 1, DDAMG_EINVAL, "bad arguments");
-    // Stencil dispatch order x FP64 sites per workgroup x FP32 (link storage,
-    // sites per workgroup); the order is shared, so it is chosen on the sum of
-    // the best FP64 and FP32 times.
+    // Stencil scheme (LDS-staged site ranges in storage or time-slice order,
+    // or the t-walk with 4 / 8 columns and 1..8 t segments) x FP64 sites per
+    // workgroup x FP32 (link storage, sites per workgroup); the scheme is
+    // shared by both precisions, so it is chosen on the sum of their best times.
     {
+      std::vector<std::pair<int, int>> schemes = {{0, c->walk_seg}, {1, c->walk_seg}};
+      if (c->geom[0].gsize == 256 && c->d_walk_blk)
+        for (int ord : {2, 3})
+          for (int seg : {1, 2, 4, 8})
+            if (c->geom[0].dims[3] % seg == 0) schemes.push_back({ord, seg});
       double best_all = 1e30;
-      int bo = c->dslash_order, b64 = c->dslash_rs[P64], bl = c->fp32_links, b32 = c->dslash_rs[P32];
-      for (int ord : {0, 1}) {
+      int bo = c->dslash_order, bseg = c->walk_seg, b64 = c->dslash_rs[P64], bl = c->fp32_links,
+          b32 = c->dslash_rs[P32];
+      for (auto [ord, seg] : schemes) {
         c->dslash_order = ord;
+        c->walk_seg = seg;
+        const bool walk = ord >= 2;
         double best64 = 1e30, best32 = 1e30;
         int v64 = b64, l32 = bl, v32 = b32;
         for (int v : {16, 32, 64}) {
-          c->dslash_rs[P64] = v;
+          if (walk && v != 16) break;       // sites per workgroup do not apply to the t-walk
+          c->dslash_rs[P64] = walk ? b64 : v;
           double sec = 0;
           const int st = ddamg_time_op(c, 0, 0, DDAMG_FP64, n_col, 10, &sec);
           if (st != DDAMG_OK) return st;
-          if (sec < best64) { best64 = sec; v64 = v; }
+          if (sec < best64) { best64 = sec; v64 = c->dslash_rs[P64]; }
         }
         for (int lk : {0, 1})
           for (int v : {32, 64, 128}) {
+            if (walk && v != 32) break;
             c->fp32_links = lk;
-            c->dslash_rs[P32] = v;
+            c->dslash_rs[P32] = walk ? b32 : v;
             double sec = 0;
             const int st = ddamg_time_op(c, 0, 0, DDAMG_FP32, n_col, 10, &sec);
             if (st != DDAMG_OK) return st;
-            if (sec < best32) { best32 = sec; l32 = lk; v32 = v; }
+            if (sec < best32) { best32 = sec; l32 = lk; v32 = c->dslash_rs[P32]; }
           }
         if (best64 + best32 < best_all) {
           best_all = best64 + best32;
           bo = ord;
+          bseg = seg;
           b64 = v64;
           bl = l32;
           b32 = v32;
         }
       }
       c->dslash_order = bo;
+      c->walk_seg = bseg;
       c->dslash_rs[P64] = b64;
       c->fp32_links = bl;
       c->dslash_rs[P32] = b32;

@@ -162,7 +162,9 @@ struct ddamg_ctx {
   int dslash_rs[2] = {32, 32};  // fine stencil sites per workgroup, per precision (autotuned)
   int fp32_links = 0;           // FP32 fine stencil links: 0 = full 3x3, 1 = 2-row compressed
   int coarse_mfma = 1;          // FP32 coarse stencil on BF16 MFMA (d % 16 == 0)
-  int dslash_order = 0;         // fine stencil dispatch: 0 storage order, 1 time-slice order
+  int dslash_order = 0;         // fine stencil scheme: 0 storage order, 1 time-slice order, 2/3 t-walk (4/8 columns)
+  int* d_walk_blk = nullptr;    // [xyz block column][t block] block numbers (4^4 site blocks)
+  int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
   int* d_dslash_order[4] = {nullptr, nullptr, nullptr, nullptr};   // per sites-per-workgroup 16..128
   int sap_variant = 0;          // FP32 SAP on 4^4 blocks: 0 = 2 columns/WG, links in LDS; 1 = 2 columns, links
                                 // through L1/L2; 2 = 1 column/WG, links through L1/L2

@@ -61,6 +61,19 @@ void build_geometry(ddamg_ctx* c, int level, const int* dims, const int* grp, in
     g.blk_lex[r] = keys[r].second;
     g.blk_num[keys[r].second] = r;
   }
+  // block numbers along t for every xyz column of 4^4 blocks (t-walk stencil)
+  if (fine && grp[0] == 4 && grp[1] == 4 && grp[2] == 4 && grp[3] == 4) {
+    std::vector<int> walk((size_t)nblk);
+    for (int bz = 0; bz < B[2]; ++bz)
+      for (int by = 0; by < B[1]; ++by)
+        for (int bx = 0; bx < B[0]; ++bx)
+          for (int bt = 0; bt < B[3]; ++bt) {
+            const int bb[4] = {bx, by, bz, bt};
+            walk[((size_t)(bx + B[0] * (by + B[1] * bz))) * B[3] + bt] = g.blk_num[lex(bb, B)];
+          }
+    c->d_walk_blk = (int*)c->pool.alloc(walk.size() * sizeof(int));
+    DD_HIP(hipMemcpy(c->d_walk_blk, walk.data(), walk.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   g.int2can.assign(g.V, 0);
   g.can2int.assign(g.V, 0);
   for (int i = 0; i < g.V; ++i) {

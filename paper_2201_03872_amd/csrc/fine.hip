@@ -507,6 +507,111 @@ static inline int nsb_of(int V) { return (V + SPW - 1) / SPW; }
 // Sites per workgroup of the LDS-staged stencil: a tile-shape knob chosen by
 // the autotuner (more sites = more neighbours served from LDS, fewer
 // workgroups resident per CU).
+// t-walk stencil (4^4 site blocks only): a workgroup owns one 4x4x4 xyz patch
+// of a column of blocks along t and TC columns of a tile, and walks the whole
+// time direction.  psi(t-1), psi(t), psi(t+1) of its own sites stay in
+// registers (the t hops), the current slice is exchanged through LDS (x, y, z
+// hops inside the patch); only the x, y, z faces of the patch are read from
+// global memory, while the neighbouring patches, which walk in step, hold the
+// same slice in L2.  Every spinor is thus read from HBM about once.
+template <typename R, int LK, int MODE, int TC>
+__global__ void __launch_bounds__(64 * TC) k_dslash_walk(const R* __restrict__ x, R* __restrict__ y,
+                                                        const R* __restrict__ b, const void* __restrict__ U,
+                                                        const int* __restrict__ nbr, const double* __restrict__ mu,
+                                                        const int* __restrict__ walk_blk, int V, int nbt,
+                                                        int npatch, int nseg, size_t tile_reals, R diag) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW, NCH = 24 / RW, NH = TT / TC;
+  __shared__ C lds[NCH * 64 * TC];
+  const int tc = threadIdx.x % TC, l = threadIdx.x / TC;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int patch = wg % npatch;
+  const int seg = (wg / npatch) % nseg;     // segment of the t direction walked
+  const int th = wg / npatch / nseg;        // tile * NH + half
+  const int tile = th / NH, t = (th % NH) * TC + tc;
+  const R* xt = x + (size_t)tile * tile_reals;
+  R* yt = y + (size_t)tile * tile_reals;
+  const int* wb = walk_blk + (size_t)patch * nbt;
+  const int Lt = 4 * nbt, len = Lt / nseg, g0 = seg * len, g1 = g0 + len;
+  auto site = [&](int gt) { return wb[gt >> 2] * 256 + l + 64 * (gt & 3); };
+  const R m = (R)mu[tile * TT + t];
+  cx<R> prev[12], cur[12], nxt[12];
+  load_cx<R, 12>(xt, V, TT, site((g0 + Lt - 1) % Lt), t, prev);
+  load_cx<R, 12>(xt, V, TT, site(g0), t, cur);
+  load_cx<R, 12>(xt, V, TT, site((g0 + 1) % Lt), t, nxt);
+  const GlobalLinks<R, LK> ll{U, V};
+  for (int gt = g0; gt < g1; ++gt) {
+    const int s = site(gt);
+    const int base = s - l;                 // first site of this patch slice
+    // the current slice of the patch to LDS
+    if constexpr (RW == 2) {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) lds[(k * 64 + l) * TC + tc] = C{cur[k].re, cur[k].im};
+    } else {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k)
+        lds[(k * 64 + l) * TC + tc] = C{cur[2 * k].re, cur[2 * k].im, cur[2 * k + 1].re, cur[2 * k + 1].im};
+    }
+    __syncthreads();
+    int e8[8];
+    load_nbrs(nbr, V, s, e8);
+    auto ld = [&](int h, int nb, cx<R>(&p)[12]) {
+      if (h == 3) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k] = nxt[k];
+        return true;
+      }
+      if (h == 7) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k] = prev[k];
+        return true;
+      }
+      const unsigned q = (unsigned)(nb - base);
+      if (q < 64u) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+          const C v = lds[(k * 64 + (int)q) * TC + tc];
+          if constexpr (RW == 2) p[k] = {v.x, v.y};
+          else { p[2 * k] = {v.x, v.y}; p[2 * k + 1] = {v.z, v.w}; }
+        }
+      } else {
+        load_cx<R, 12>(xt, V, TT, nb, t, p);
+      }
+      return true;
+    };
+    cx<R> acc[12], out[12];
+    all_hops_e<R, LK>(acc, ll, e8, s, ld);
+    site_diag(out, cur, acc, diag, m);
+    if constexpr (MODE == 1) {
+      cx<R> bs[12];
+      load_cx<R, 12>(b + (size_t)tile * tile_reals, V, TT, s, t, bs);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) out[k] = bs[k] - out[k];
+    }
+    store_cx<R, 12>(yt, V, TT, s, t, out);
+    __syncthreads();   // the slice in LDS is replaced next step
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      prev[k] = cur[k];
+      cur[k] = nxt[k];
+    }
+    if (gt + 1 < g1) load_cx<R, 12>(xt, V, TT, site((gt + 2) % Lt), t, nxt);
+  }
+}
+
+template <typename R, int LK, int MODE, int TC>
+static void launch_walk(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu, const void* U) {
+  const LevelGeom& g = c->geom[0];
+  const int npatch = (g.dims[0] / 4) * (g.dims[1] / 4) * (g.dims[2] / 4);
+  const int nbt = g.dims[3] / 4;
+  const int nseg = g.dims[3] % c->walk_seg == 0 ? c->walk_seg : 1;
+  hipLaunchKernelGGL((k_dslash_walk<R, LK, MODE, TC>), dim3(npatch * nseg * x.ntiles * (TT / TC)), dim3(64 * TC), 0,
+                     c->stream, x.as<R>(), y.as<R>(), b ? b->as<R>() : nullptr, U, g.d_nbr, d_mu, c->d_walk_blk, g.V,
+                     nbt, npatch, nseg, x.tile_reals(), (R)c->diag);
+}
+
+bool dslash_walk_ok(ddamg_ctx* c) { return c->geom[0].gsize == 256 && c->d_walk_blk != nullptr; }
+
 // Start sites of the RS-site ranges sorted by the time coordinate of their
 // first site (stable, so block order is kept within a time slice).
 static const int* dslash_order(ddamg_ctx* c, int RS) {
@@ -557,6 +662,22 @@ static void launch_f32(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, cons
 
 template <int MODE>
 static void launch_dslash(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu) {
+  if (c->dslash_order >= 2 && dslash_walk_ok(c)) {   // t-walk kernel, 4 or 8 columns per workgroup
+    const bool tc8 = c->dslash_order == 3;
+    if (x.prec == P64) {
+      if (tc8) launch_walk<double, LK_D, MODE, 8>(c, x, y, b, d_mu, c->d_U64);
+      else launch_walk<double, LK_D, MODE, 4>(c, x, y, b, d_mu, c->d_U64);
+    } else if (c->fp32_links == 0) {
+      if (tc8) launch_walk<float, LK_F, MODE, 8>(c, x, y, b, d_mu, c->d_U32f);
+      else launch_walk<float, LK_F, MODE, 4>(c, x, y, b, d_mu, c->d_U32f);
+    } else {
+      if (tc8) launch_walk<float, LK_C, MODE, 8>(c, x, y, b, d_mu, c->d_U32);
+      else launch_walk<float, LK_C, MODE, 4>(c, x, y, b, d_mu, c->d_U32);
+    }
+    DD_HIP(hipGetLastError());
+    c->st.fine_ops++;
+    return;
+  }
   if (x.prec == P64) {
     switch (c->dslash_rs[P64]) {
       case 16: launch_rs<double, LK_D, MODE, 16>(c, x, y, b, d_mu, c->d_U64); break;

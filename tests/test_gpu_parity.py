@@ -73,8 +73,12 @@ def test_fine_operator_fp64_and_fp32(torch_cuda, dd, dims, blk, ncol):
     xg = torch.from_numpy(x).cuda()
     y64 = ctx.apply_op(0, dd.FP64, mus, xg).cpu().numpy()
     assert np.max(relerr_cols(y64, ref)) < 1e-13
-    for order in (0, 1):                      # storage order / time-slice order of the site ranges
+    schemes = [(0, 2), (1, 2)]                # LDS-staged site ranges: storage / time-slice order
+    if blk == (4, 4, 4, 4):                   # t-walk over 4^4 block columns: 4 / 8 columns, t segments
+        schemes += [(2, 1), (2, 2), (3, 4), (3, 8)]
+    for order, seg in schemes:
         ctx.set_tuning("dslash_order", order)
+        ctx.set_tuning("walk_segments", seg)
         for links in (0, 1):                  # full FP32 links / 2-row compressed
             ctx.set_tuning("fp32_links", links)
             for sites in (32, 64, 128):
@@ -111,6 +115,20 @@ def test_fine_operator_full_lattice_sampled(torch_cuda, dd):
     ref = op.apply_site(xs, mus, sites)
     got = y.cpu().numpy()[:, sites]
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-13
+    # the t-walk schemes give the same result (same hop order and arithmetic)
+    for order, seg in ((2, 2), (3, 4)):
+        ctx.set_tuning("dslash_order", order)
+        ctx.set_tuning("walk_segments", seg)
+        yw = ctx.apply_op(0, dd.FP64, mus, x)
+        assert torch.max(torch.abs(yw - y)).item() <= 1e-13 * torch.max(torch.abs(y)).item()
+        for links in (0, 1):
+            ctx.set_tuning("fp32_links", links)
+            ctx.set_tuning("dslash_order", 0)
+            y32 = ctx.apply_op(0, dd.FP32, mus, x)
+            ctx.set_tuning("dslash_order", order)
+            yw32 = ctx.apply_op(0, dd.FP32, mus, x)
+            assert torch.max(torch.abs(yw32 - y32)).item() <= 1e-6 * torch.max(torch.abs(y32)).item()
+    ctx.set_tuning("dslash_order", 0)
     # gamma5-hermiticity: <phi, g5 D(mu) g5 psi> = <D(-mu) phi, psi>
     g5 = torch.tensor([1, 1, -1, -1], dtype=torch.float64, device="cuda").view(1, 1, 4, 1)
     phi = x.roll(1, dims=0)
