@@ -340,13 +340,19 @@ static int active_columns(ddamg_ctx* c, int ncol) {
   if (c->p.max_active_cols > 0) return std::min(ncol, c->p.max_active_cols);
   const double col64 = (double)c->geom[0].V * 12 * 16;
   const int m = std::min(c->p.outer_restart, 63);
-  const double zfac = c->p.precision == DDAMG_MIXED ? 0.5 : 1.0;
+  const bool mixed = c->p.precision == DDAMG_MIXED;
+  const double zfac = mixed ? 0.5 : 1.0;
   const int mi = std::min(c->p.inner_iters, 63);
-  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8) + (mi > 0 ? 0.5 * (2 * mi + 2) : 0.0));
+  const double vfac = mixed && c->p.inner_fp16 ? 0.25 : (mixed ? 0.5 : 1.0);   // inner basis V
+  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8) + (mi > 0 ? vfac * (mi + 1) + zfac * (mi + 2) : 0.0));
+  // workspaces come in tiles of T columns: count whole tiles
+  const double per_tile = per_col * c->T;
   size_t fre = 0, tot = 0;
   DD_HIP(hipMemGetInfo(&fre, &tot));
-  const int fit = (int)std::max(8.0, 0.85 * (double)fre / per_col);
-  return std::min(ncol, fit);
+  const int tiles = (int)(0.85 * (double)fre / per_tile);
+  DD_CHECK(tiles >= 1, DDAMG_ENOMEM,
+           "device memory holds less than one tile of Krylov workspace: lower outer_restart / inner_iters");
+  return std::min(ncol, tiles * c->T);
 }
 
 // Solve the columns (shift hmu[i], right-hand side b[rhs_of[i]]) together.
