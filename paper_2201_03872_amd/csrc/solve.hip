@@ -60,6 +60,34 @@ void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2) {
   DD_HIP(hipGetLastError());
 }
 
+// dst (FP16 basis, same layout) = src (FP32) / sqrt(n2_col) * hscale: the
+// normalisation and the store of a new basis vector in one pass
+__global__ void k_normalize_f16(const float* __restrict__ src, _Float16* __restrict__ dst,
+                                const double* __restrict__ n2, size_t nunits, int T, size_t tile_units,
+                                double hscale) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(u / tile_units) * T + (int)(u % T);
+    const double v = n2[col];
+    const float sc = (float)(v > 0 ? hscale / sqrt(v) : 0.0);
+    const float4 a = reinterpret_cast<const float4*>(src)[u];
+    _Float16* d = dst + u * 4;
+    d[0] = (_Float16)(a.x * sc);
+    d[1] = (_Float16)(a.y * sc);
+    d[2] = (_Float16)(a.z * sc);
+    d[3] = (_Float16)(a.w * sc);
+  }
+}
+
+static void mv_normalize_into_f16(ddamg_ctx* c, const MV& src, const double* d_n2, const MV& dst) {
+  DD_CHECK(src.prec == P32 && dst.prec == P16 && src.reals() == dst.reals(), DDAMG_EINVAL, "normalize into FP16");
+  const size_t tile_units = (size_t)src.nchunk * src.nsites * src.T, nunits = tile_units * src.ntiles;
+  size_t g = (nunits + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_normalize_f16, dim3((unsigned)g), dim3(256), 0, c->stream, src.as<float>(),
+                     dst.as<_Float16>(), d_n2, nunits, src.T, tile_units, dst.hscale);
+  DD_HIP(hipGetLastError());
+}
+
 // alpha = <q, r> / <q, q> per column (MR step), 0 where <q,q> = 0
 __global__ void k_mr_alpha(const double* __restrict__ qr, const double* __restrict__ qq, double* __restrict__ a,
                            int n) {
@@ -206,8 +234,8 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
   const int prec = x.prec, ncol = nt * c->T, cap = w.cap, m = cy.m, vprec = w.vprec;
   const bool half = vprec != prec;   // FP16 basis: new vectors are formed in the working precision
   MV r = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, 0, level, vprec, cap, nt);
-  mv_normalize(c, r, d_n2);
-  if (half) mv_copy(c, r, basis(c, w.V, 0, level, vprec, cap, nt));
+  if (half) mv_normalize_into_f16(c, r, d_n2, basis(c, w.V, 0, level, vprec, cap, nt));
+  else mv_normalize(c, r, d_n2);
   for (int i = 0; i < ncol; ++i) {
     cy.kc[i] = done[i] ? 0 : -1;
     for (int j = 0; j <= m; ++j) cy.g[(size_t)i * (m + 1) + j] = 0;
@@ -243,8 +271,8 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     const size_t nh = (size_t)(j + 1) * ncol * 2;
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
     copy_to_host(c, d_n2, cy.hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
-    mv_normalize(c, vn, d_n2);
-    if (half) mv_copy(c, vn, basis(c, w.V, j + 1, level, vprec, cap, nt));
+    if (half) mv_normalize_into_f16(c, vn, d_n2, basis(c, w.V, j + 1, level, vprec, cap, nt));
+    else mv_normalize(c, vn, d_n2);
     ++total;
     jj = j + 1;
     bool alld = true;
