@@ -502,16 +502,26 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
   }
 }
 
-__global__ void k_multidot2(const double* __restrict__ part, double* __restrict__ out, int nbM, int k, int ncol) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;   // i = j*ncol + col
-  if (i >= k * ncol) return;
+// second stage: one wavefront per output i = j*ncol + col sums the nbM
+// partials (lane-strided, then a fixed shuffle tree: deterministic)
+__global__ void __launch_bounds__(64) k_multidot2(const double* __restrict__ part, double* __restrict__ out, int nbM,
+                                                  int k, int ncol) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   double a = 0, b = 0;
-  for (int q = 0; q < nbM; ++q) {
+  for (int q = lane; q < nbM; q += 64) {
     a += part[((size_t)q * k * ncol + i) * 2];
     b += part[((size_t)q * k * ncol + i) * 2 + 1];
   }
-  out[2 * i] = a;
-  out[2 * i + 1] = b;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if (lane == 0) {
+    out[2 * i] = a;
+    out[2 * i + 1] = b;
+  }
 }
 
 // workgroups along the vector length of the first reduction stage
@@ -559,7 +569,7 @@ void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_o
                        ncol, 1.0);
   DD_HIP(hipGetLastError());
   const int n = k * ncol;
-  hipLaunchKernelGGL(k_multidot2, dim3((n + 255) / 256), dim3(256), 0, c->stream, part, d_out, nbM, k, ncol);
+  hipLaunchKernelGGL(k_multidot2, dim3(n), dim3(64), 0, c->stream, part, d_out, nbM, k, ncol);
   DD_HIP(hipGetLastError());
 }
 
