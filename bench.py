@@ -75,9 +75,11 @@ def sap_flops_per_half_sweep(V, ncol, mr):
     """Algorithmic flops of one red-black SAP half sweep (half the sites),
     averaged over the two half sweeps of a one-cycle SAP call: mr MR steps
     (1 block stencil, two inner products and two axpys per step) each, plus
-    the block residual (1 stencil) in the second one only (the first starts
-    from x = 0, where the residual is the right-hand side)."""
-    per_site = 0.5 * 1320 + mr * (1320 + 8 * 12 + 2 * 8 * 12)
+    the block residual in the second one only.  The first starts from x = 0
+    (residual = right-hand side); in the second, x is still zero inside its
+    own blocks, so only the hops that leave a 4^4 block (2 of a site's 8 on
+    average, 165 flop each) contribute."""
+    per_site = 0.5 * (2 * 1320 / 8) + mr * (1320 + 8 * 12 + 2 * 8 * 12)
     return V / 2 * ncol * per_site
 
 

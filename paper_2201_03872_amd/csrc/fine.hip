@@ -400,22 +400,31 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   R* xt = x + (size_t)tile * tile_reals;
   const R m = (R)mu[tile * TT + t];
 
-  // 1. block residual (x_zero: the first half-sweep from x = 0, residual = f)
+  // 1. block residual.  x_zero 1: the first half-sweep of a call, x = 0
+  // everywhere, so the residual is f; x_zero 2: the second one, x = 0 on the
+  // blocks of this colour (not yet visited), so in-block hops and the site's
+  // own x drop out and x is never read there.
   int e8[8];
   load_nbrs(nbr, V, s, e8);
   cx<R> rho[12], dl[12], q[12];
-  if (x_zero) {
+  if (x_zero == 1) {
     load_cx<R, 12>(ft, V, TT, s, t, rho);
 #pragma unroll
     for (int k = 0; k < 12; ++k) dl[k] = {0, 0};
   } else {
     auto ldg = [&](int, int nb, cx<R>(&p)[12]) {
+      if (x_zero == 2 && nb / BS == blk) return false;
       load_cx<R, 12>(xt, V, TT, nb, t, p);
       return true;
     };
     cx<R> acc[12], xs[12], fs[12];
     all_hops_e<R, LK>(acc, GlobalLinks<R, LK>{U, V}, e8, s, ldg);
-    load_cx<R, 12>(xt, V, TT, s, t, xs);
+    if (x_zero == 2) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) xs[k] = {0, 0};
+    } else {
+      load_cx<R, 12>(xt, V, TT, s, t, xs);
+    }
     load_cx<R, 12>(ft, V, TT, s, t, fs);
     site_diag(q, xs, acc, diag, m);
 #pragma unroll
@@ -489,7 +498,7 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
       rho[k] = rho[k] - a * q[k];
     }
   }
-  // 3. update
+  // 3. update (x = 0 on this block before the half-sweep: store the correction)
   if (x_zero) {
     store_cx<R, 12>(xt, V, TT, s, t, dl);
   } else {
@@ -722,13 +731,14 @@ static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
   DD_HIP(hipGetLastError());
 }
 
+// x is fully written by the first cycle (each site belongs to one block of
+// one colour), so it needs no clearing beforehand.
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV&) {
-  mv_zero(c, x);
   const int BS = c->geom[0].gsize;
   for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour) {
-      // the first half-sweep starts from x = 0: its block residual is f itself
-      const int xz = (cyc == 0 && colour == 0) ? 1 : 0;
+      // first cycle: x = 0 everywhere (colour 0), then on the colour-1 blocks
+      const int xz = cyc == 0 ? 1 + colour : 0;
       if (x.prec == P64) {
         if (BS == 256) launch_sap<double, LK_D, 1, 256>(c, f, x, d_mu, colour, xz);
         else if (BS == 16) launch_sap<double, LK_D, 4, 16>(c, f, x, d_mu, colour, xz);
