@@ -207,6 +207,7 @@ void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu);
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu);
 void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hop);
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV& work);
+bool sap_takes_f16(ddamg_ctx* c);   // sap_apply accepts an FP16 right-hand side
 bool dslash_rs_valid(int prec, int rs);
 
 // ---- coarse kernels (coarse.hip) ----

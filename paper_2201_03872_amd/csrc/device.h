@@ -74,6 +74,21 @@ __device__ __forceinline__ void load_cx(const R* __restrict__ tile, int nsites, 
   }
 }
 
+// Load NC complexes of one (site, column) from an FP16 multivector in the
+// FP32 layout (two complexes per 8-byte chunk), times `scale`.
+template <int NC>
+__device__ __forceinline__ void load_cx_f16(const _Float16* __restrict__ tile, int nsites, int T, int s, int t,
+                                            float scale, cx<float> (&v)[NC]) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  const h4* b = reinterpret_cast<const h4*>(tile);
+#pragma unroll
+  for (int k = 0; k < NC / 2; ++k) {
+    const h4 c = b[((size_t)k * nsites + s) * T + t];
+    v[2 * k] = {(float)c.x * scale, (float)c.y * scale};
+    v[2 * k + 1] = {(float)c.z * scale, (float)c.w * scale};
+  }
+}
+
 template <typename R, int NC>
 __device__ __forceinline__ void store_cx(R* __restrict__ tile, int nsites, int T, int s, int t,
                                          const cx<R> (&v)[NC]) {

@@ -14,6 +14,7 @@
 // compression the third row is rebuilt as conj(row0 x row1), which would lose
 // a sign stored in the link.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -368,12 +369,12 @@ struct SapLinks {
 //   3. x += delta on the block.
 // Blocks of one colour never neighbour each other, so the in-place update of
 // x is race free.
-template <typename R, int LK, int K, int BS, bool ULDS>
-__global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R* __restrict__ x,
+template <typename R, int LK, int K, int BS, bool ULDS, typename FIN = R>
+__global__ void __launch_bounds__(BS * K) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
                                                      int V, int ntiles, size_t tile_reals, R diag, int mr_iters,
-                                                     int x_zero) {
+                                                     int x_zero, float fscale) {
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW;
   constexpr int NCH = 24 / RW;
@@ -396,7 +397,11 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   const int t = sub * K + kk;
   const int blk = blist[bi];
   const int s = blk * BS + sl;
-  const R* ft = f + (size_t)tile * tile_reals;
+  const FIN* ft = f + (size_t)tile * tile_reals;   // FP16 right-hand sides: same layout, stored * 1/fscale
+  auto load_f = [&](cx<R>(&v)[12]) {
+    if constexpr (std::is_same<FIN, R>::value) load_cx<R, 12>(ft, V, TT, s, t, v);
+    else load_cx_f16<12>(ft, V, TT, s, t, fscale, v);
+  };
   R* xt = x + (size_t)tile * tile_reals;
   const R m = (R)mu[tile * TT + t];
 
@@ -408,7 +413,7 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
   load_nbrs(nbr, V, s, e8);
   cx<R> rho[12], dl[12], q[12];
   if (x_zero == 1) {
-    load_cx<R, 12>(ft, V, TT, s, t, rho);
+    load_f(rho);
 #pragma unroll
     for (int k = 0; k < 12; ++k) dl[k] = {0, 0};
   } else {
@@ -425,7 +430,7 @@ __global__ void __launch_bounds__(BS * K) k_sap_half(const R* __restrict__ f, R*
     } else {
       load_cx<R, 12>(xt, V, TT, s, t, xs);
     }
-    load_cx<R, 12>(ft, V, TT, s, t, fs);
+    load_f(fs);
     site_diag(q, xs, acc, diag, m);
 #pragma unroll
     for (int k = 0; k < 12; ++k) { rho[k] = fs[k] - q[k]; dl[k] = {0, 0}; }
@@ -720,21 +725,31 @@ void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
   DD_HIP(hipGetLastError());
 }
 
-template <typename R, int LK, int K, int BS, bool ULDS = true>
+template <typename R, int LK, int K, int BS, bool ULDS = true, typename FIN = R>
 static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
-  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS>), grid, blk, 0, c->stream, f.as<R>(), x.as<R>(),
+  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS, FIN>), grid, blk, 0, c->stream, f.as<FIN>(), x.as<R>(),
                      LK == LK_C ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
                      c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
-                     c->p.sap_mr_iters, x_zero);
+                     c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
   DD_HIP(hipGetLastError());
 }
 
 // x is fully written by the first cycle (each site belongs to one block of
 // one colour), so it needs no clearing beforehand.
+bool sap_takes_f16(ddamg_ctx* c) { return c->geom[0].gsize == 256 && c->sap_variant == 2; }
+
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV&) {
   const int BS = c->geom[0].gsize;
+  if (f.prec == P16) {   // right-hand sides read straight from an FP16 Krylov basis
+    DD_CHECK(x.prec == P32 && sap_takes_f16(c), DDAMG_EINVAL, "SAP: FP16 input needs the FP32 one-column variant");
+    for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
+      for (int colour = 0; colour < 2; ++colour)
+        launch_sap<float, LK_C, 1, 256, false, _Float16>(c, f, x, d_mu, colour, cyc == 0 ? 1 + colour : 0);
+    c->st.sap_calls++;
+    return;
+  }
   for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour) {
       // first cycle: x = 0 everywhere (colour 0), then on the colour-1 blocks

@@ -230,7 +230,7 @@ struct Cycle {
 static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, const double* d_mu, const Precond* pc,
                        int zprec, int budget, bool fixed, const std::vector<double>& beta, std::vector<char>& done,
                        const std::vector<double>& tol_abs, std::vector<double>& est, const std::vector<double>& bn,
-                       Cycle& cy, double* d_n2, int& total) {
+                       Cycle& cy, double* d_n2, int& total, bool pc_f16 = false) {
   const int prec = x.prec, ncol = nt * c->T, cap = w.cap, m = cy.m, vprec = w.vprec;
   const bool half = vprec != prec;   // FP16 basis: new vectors are formed in the working precision
   MV r = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, 0, level, vprec, cap, nt);
@@ -244,7 +244,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
   int jj = 0;
   for (int j = 0; j < m && j < budget; ++j) {
     MV vj = basis(c, w.V, j, level, vprec, cap, nt);
-    if (half) {
+    if (half && !pc_f16) {
       MV v32 = get(c, w.vi, level, prec, cap, nt);
       mv_copy(c, vj, v32);
       vj = v32;
@@ -707,8 +707,10 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
       if (!done[i]) all = false;
     }
     if ((all && !fixed) || total >= maxit) break;
+    // the inner FGMRES's preconditioner is the fine smoother; SAP reads an FP16 basis directly
+    const bool pc_f16 = role == 1 && c->nlev == 1 && c->p.smoother == DDAMG_SMOOTHER_SAP && sap_takes_f16(c);
     gmres_cycle(c, level, w, nt, x, d_mu, pc, zprec, maxit - total, fixed, beta, done, tol_abs, est, bn, cy, d_n2,
-                total);
+                total, pc_f16);
     for (int i = 0; i < ncol; ++i) iters[i] += cy.kc[i];
     bool all2 = true;
     for (int i = 0; i < ncol; ++i)
