@@ -226,7 +226,10 @@ int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);
  * stencil (level 0), 1 = SAP smoother (level 0), 2 = coarse stencil of
  * `level`, 3 = restriction from `level`, 4 = prolongation to `level`,
  * 5 = plain device copy of the multivector (reads and writes its size; a
- * kernel of known traffic for calibrating memory counters). */
+ * kernel of known traffic for calibrating memory counters), 6 = SAP smoother
+ * reading its right-hand side from FP16 storage (the form used inside the
+ * inner Krylov solve; precision FP32, level 0, 4^4 blocks and SAP variant 2,
+ * else DDAMG_EINVAL). */
 int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int n_iter, double* sec);
 
 /* Tile-shape knobs.  DDAMG_KNOB_DSLASH_SITES_FP64: lattice sites per

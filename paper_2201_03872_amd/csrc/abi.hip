@@ -509,18 +509,27 @@ int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int
     const int lout = (op == 3) ? level + 1 : level;
     DD_CHECK(!(op == 3 || op == 4) || level + 1 < c->nlev, DDAMG_ESTATE, "no such transition");
     DD_CHECK(!(op == 2) || level >= 1, DDAMG_EINVAL, "coarse stencil needs level >= 1");
-    DD_CHECK(op >= 0 && op <= 5, DDAMG_EINVAL, "unknown op");
+    DD_CHECK(op >= 0 && op <= 6, DDAMG_EINVAL, "unknown op");
+    DD_CHECK(op != 6 || (prec == P32 && level == 0 && sap_takes_f16(c)), DDAMG_EINVAL,
+             "the FP16-input smoother needs FP32, level 0, 4^4 blocks and SAP variant 2");
     MV a64 = mv_alloc(c, lin, P64, n_col);
     random_fill(c, lin, a64, a64.ncol(), 99);
     MV a = (prec == P64) ? a64 : mv_like(c, a64, P32);
     if (prec != P64) mv_copy(c, a64, a);
+    if (op == 6) {  // FP64 -> FP32 -> scaled FP16
+      MV a16 = mv_like(c, a64, P16);
+      mv_copy(c, a, a16);
+      mv_free(c, a);
+      a = a16;
+    }
     MV b = mv_alloc(c, lout, prec, n_col);
     std::vector<double> hm(a.ncol(), 0.01);
     double* d_mu = upload_mu(c, hm.data(), a.ncol(), a.ncol());
     auto run = [&]() {
       switch (op) {
         case 0: fine_dslash(c, a, b, d_mu); break;
-        case 1: sap_apply(c, a, b, d_mu, b); break;
+        case 1:
+        case 6: sap_apply(c, a, b, d_mu, b); break;
         case 2: coarse_apply(c, level, a, b, d_mu); break;
         case 3: restrict_mv(c, level, a, b); break;
         case 4: prolong_mv(c, level, a, b, 0); break;

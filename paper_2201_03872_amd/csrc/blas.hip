@@ -502,6 +502,66 @@ __global__ void __launch_bounds__(256) k_multidot1(PtrPack Vs, int k, const R* _
   }
 }
 
+// Stage 1 for an FP16 basis against FP32 w: KH (up to 16) basis vectors per
+// workgroup, so w is read once per group; each lane moves one 16-byte
+// chunk of w and one 8-byte chunk of every basis vector per row.  The
+// per-lane sums run in FP32 (the FP16 basis carries 2^-11 relative error, far
+// above the rounding of a few dozen FP32 additions); the reduction across
+// lanes and workgroups is FP64.
+template <int KH>
+__global__ void __launch_bounds__(256) k_multidot_h(PtrPack Vs, int k, const float* __restrict__ w,
+                                                    double* __restrict__ part, size_t M, int ncol, double vscale) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  constexpr int T = TTB;
+  const int t = threadIdx.x % T, row = threadIdx.x / T;
+  const int tile = blockIdx.y;
+  const int j0 = blockIdx.z * KH;
+  const int kk = min(KH, k - j0);
+  const int nbM = gridDim.x;
+  const size_t tile_chunks = M * T;
+  float accr[KH], acci[KH];
+#pragma unroll
+  for (int j = 0; j < KH; ++j) { accr[j] = 0; acci[j] = 0; }
+  const float4* w4 = reinterpret_cast<const float4*>(w);
+  for (size_t m = (size_t)blockIdx.x * 32 + row; m < M; m += (size_t)nbM * 32) {
+    const size_t off = (size_t)tile * tile_chunks + m * T + t;
+    const float4 wv = w4[off];
+#pragma unroll
+    for (int j = 0; j < KH; ++j) {
+      if (j < kk) {
+        const h4 v = reinterpret_cast<const h4*>(Vs.p[j0 + j])[off];
+        const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z, v3 = (float)v.w;
+        accr[j] += v0 * wv.x + v1 * wv.y + v2 * wv.z + v3 * wv.w;
+        acci[j] += v0 * wv.y - v1 * wv.x + v2 * wv.w - v3 * wv.z;
+      }
+    }
+  }
+  // reduce the 8 rows of a wave that share t, then the 4 waves (FP64)
+  __shared__ double red[4][T][KH][2];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int j = 0; j < KH; ++j) {
+    double a = accr[j], b = acci[j];
+#pragma unroll
+    for (int off = T; off < 64; off <<= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
+    }
+    if (lane < T) { red[wave][lane][j][0] = a; red[wave][lane][j][1] = b; }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kk * T; i += 256) {
+    const int j = i / T, tt = i % T;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int w4i = 0; w4i < 4; ++w4i) { a += red[w4i][tt][j][0]; b += red[w4i][tt][j][1]; }
+    const int col = tile * T + tt;
+    double* pp = part + (((size_t)blockIdx.x * k + j0 + j) * ncol + col) * 2;
+    pp[0] = a * vscale;
+    pp[1] = b * vscale;
+  }
+}
+
 // second stage: one wavefront per output i = j*ncol + col sums the nbM
 // partials (lane-strided, then a fixed shuffle tree: deterministic)
 __global__ void __launch_bounds__(64) k_multidot2(const double* __restrict__ part, double* __restrict__ out, int nbM,
@@ -524,16 +584,23 @@ __global__ void __launch_bounds__(64) k_multidot2(const double* __restrict__ par
   }
 }
 
+// basis vectors per workgroup of the FP16 kernel
+constexpr int KH_MAX = 16;
+
 // workgroups along the vector length of the first reduction stage
-static int multidot_nbm(const MV& w, int k) {
+static int multidot_nbm(const MV& w, int k, bool half) {
   const size_t M = (size_t)w.nchunk * w.nsites;
-  const int ngroups = (k + KB - 1) / KB;
+  const int kb = half ? KH_MAX : KB;
+  const int ngroups = (k + kb - 1) / kb;
   int nbM = (int)std::min<size_t>((M + 31) / 32, 4096 / ((size_t)w.ntiles * ngroups) + 1);
   return nbM < 1 ? 1 : nbM;
 }
 
 // doubles of the partial sums mv_multidot needs for k vectors shaped like w
-size_t multidot_partials(const MV& w, int k) { return (size_t)multidot_nbm(w, k) * k * w.ncol() * 2; }
+// (sized for either basis precision)
+size_t multidot_partials(const MV& w, int k) {
+  return (size_t)std::max(multidot_nbm(w, k, false), multidot_nbm(w, k, true)) * k * w.ncol() * 2;
+}
 
 void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out) {
   mv_multidot_buf(c, Vs, k, w, d_out, nullptr);
@@ -553,17 +620,23 @@ void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_o
   }
   const double vscale = half ? 1.0 / Vs[0].hscale : 1.0;
   const size_t M = (size_t)w.nchunk * w.nsites;
-  const int ngroups = (k + KB - 1) / KB;
-  const int nbM = multidot_nbm(w, k);
+  const int ngroups = (k + (half ? KH_MAX : KB) - 1) / (half ? KH_MAX : KB);
+  const int nbM = multidot_nbm(w, k, half);
   const int ncol = w.ncol();
   if (!part) part = scratch(c, multidot_partials(w, k) * sizeof(double));
   dim3 grid(nbM, w.ntiles, ngroups);
-  if (w.prec == P64)
+  if (half) {
+    // groups of up to 16 basis vectors: 54 VGPRs, 8 waves per SIMD (a single
+    // group of 40 needs 174 VGPRs and ran 10% slower than re-reading w)
+    const int kh = std::min(k, KH_MAX);
+    DD_CHECK(w.nchunk * 4 == 2 * w.dof, DDAMG_EINVAL, "mv_multidot: FP32 chunk width");
+    if (kh <= 8)
+      hipLaunchKernelGGL(k_multidot_h<8>, grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M, ncol, vscale);
+    else
+      hipLaunchKernelGGL(k_multidot_h<16>, grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M, ncol, vscale);
+  } else if (w.prec == P64)
     hipLaunchKernelGGL(k_multidot1<double>, grid, dim3(256), 0, c->stream, pk, k, w.as<double>(), part, M, w.ntiles,
                        ncol, 1.0);
-  else if (half)
-    hipLaunchKernelGGL((k_multidot1<float, _Float16>), grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M,
-                       w.ntiles, ncol, vscale);
   else
     hipLaunchKernelGGL(k_multidot1<float>, grid, dim3(256), 0, c->stream, pk, k, w.as<float>(), part, M, w.ntiles,
                        ncol, 1.0);
@@ -619,6 +692,78 @@ __global__ void k_multiaxpy_chunk(PtrPack Vs, int k, const double* __restrict__ 
 #pragma unroll
     for (int r = 0; r < RW; ++r) wp[r] = (RWt)((double)wp[r] + sign * acc[r]);
   }
+}
+
+// w += sign * scale * sum_j coef[j][col] V_j fused with the squared norms of
+// the updated w: workgroups of one tile (blockIdx.y) stride over its chunks,
+// so each lane keeps one column (t = lane % T) and sums |w|^2 of what it
+// stores; partial[bx][col] gets the workgroup's sum (FP64, fixed shuffle tree).
+// The coefficients of the tile's T columns are staged in LDS in the
+// accumulation type ACC (FP32 for an FP16 basis, whose 2^-11 relative error
+// dominates; FP64 otherwise).
+template <typename RV, typename RWt, int RW, typename ACC>
+__global__ void __launch_bounds__(256) k_multiaxpy_norm(PtrPack Vs, int k, const double* __restrict__ coef,
+                                                        RWt* __restrict__ w, int T, size_t tile_units, int ncol,
+                                                        double scale, double* __restrict__ part) {
+  __shared__ ACC cf[MAXK][TTB][2];
+  __shared__ double red[4][TTB];
+  const int tile = blockIdx.y;
+  for (int i = threadIdx.x; i < k * T; i += blockDim.x) {
+    const int j = i / T, tt = i % T;
+    const size_t ci = ((size_t)j * ncol + tile * T + tt) * 2;
+    cf[j][tt][0] = (ACC)(coef[ci] * scale);
+    cf[j][tt][1] = (ACC)(coef[ci + 1] * scale);
+  }
+  __syncthreads();
+  const int t = threadIdx.x % T;
+  const size_t base = (size_t)tile * tile_units;
+  double n2 = 0;
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < tile_units; u += (size_t)gridDim.x * blockDim.x) {
+    ACC acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = 0;
+    for (int j = 0; j < k; ++j) {
+      const RV* v = reinterpret_cast<const RV*>(Vs.p[j]) + (base + u) * RW;
+      const ACC cr = cf[j][t][0], ci = cf[j][t][1];
+      RV vv[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) vv[r] = v[r];
+#pragma unroll
+      for (int r = 0; r < RW; r += 2) {
+        const ACC vr = (ACC)vv[r], vi = (ACC)vv[r + 1];
+        acc[r] += cr * vr - ci * vi;
+        acc[r + 1] += cr * vi + ci * vr;
+      }
+    }
+    RWt* wp = w + (base + u) * RW;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const RWt o = (RWt)((ACC)wp[r] + acc[r]);
+      wp[r] = o;
+      n2 += (double)o * (double)o;
+    }
+  }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int off = T; off < 64; off <<= 1) n2 += __shfl_xor(n2, off, 64);
+  if (lane < T) red[wave][lane] = n2;
+  __syncthreads();
+  if (threadIdx.x < T) {
+    double a = 0;
+#pragma unroll
+    for (int w4 = 0; w4 < 4; ++w4) a += red[w4][threadIdx.x];
+    part[(size_t)blockIdx.x * ncol + tile * T + threadIdx.x] = a;
+  }
+}
+
+// out[i] = sum over q < nb of part[q][i] (one wavefront per column, fixed tree)
+__global__ void __launch_bounds__(64) k_sum_rows(const double* __restrict__ part, double* __restrict__ out, int nb,
+                                                 int ncol) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  double a = 0;
+  for (int q = lane; q < nb; q += 64) a += part[(size_t)q * ncol + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if (lane == 0) out[i] = a;
 }
 
 // FP64 w += sign * sum_j coef V_j with FP32 V_j (one complex per FP64 chunk,
@@ -680,6 +825,42 @@ void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const
   DD_CHECK(Vs[0].prec == P32 && w.prec == P64, DDAMG_EINVAL, "mv_multiaxpy: precisions");
   hipLaunchKernelGGL(k_multiaxpy_mixed, grid_for(n), dim3(256), 0, c->stream, pk, k, d_coef, w.as<double>(), n, w.T,
                      w.nsites, tile_pairs_of(w), tile_pairs_of(Vs[0]), w.ncol(), (double)sign);
+  DD_HIP(hipGetLastError());
+}
+
+// w += sign * sum_j coef V_j and d_n2[col] = ||w_col||^2 of the result in one
+// pass over w (same-precision or FP16 bases; other pairs take the two-pass form)
+void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
+                        double* d_n2) {
+  DD_CHECK(k >= 1 && k <= MAXK, DDAMG_EINVAL, "mv_multiaxpy_norm2: k");
+  const bool half = Vs[0].prec == P16 && w.prec == P32;
+  if (!(half || Vs[0].prec == w.prec) || w.T != TTB) {
+    mv_multiaxpy(c, Vs, k, d_coef, w, sign);
+    mv_norm2(c, w, d_n2);
+    return;
+  }
+  PtrPack pk;
+  for (int j = 0; j < k; ++j) {
+    DD_CHECK(Vs[j].nsites == w.nsites && Vs[j].dof == w.dof && Vs[j].ntiles == w.ntiles && Vs[j].prec == Vs[0].prec,
+             DDAMG_EINVAL, "mv_multiaxpy_norm2: shape");
+    pk.p[j] = Vs[j].p;
+  }
+  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
+  const int nb = (int)std::max<size_t>(1, std::min<size_t>((tile_units + 255) / 256, 3072 / w.ntiles));
+  const int ncol = w.ncol();
+  double* part = scratch(c, (size_t)nb * ncol * sizeof(double));
+  const dim3 grid(nb, w.ntiles);
+  if (half)
+    hipLaunchKernelGGL((k_multiaxpy_norm<_Float16, float, 4, float>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<float>(), w.T, tile_units, ncol, (double)sign / Vs[0].hscale, part);
+  else if (w.prec == P64)
+    hipLaunchKernelGGL((k_multiaxpy_norm<double, double, 2, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<double>(), w.T, tile_units, ncol, (double)sign, part);
+  else
+    hipLaunchKernelGGL((k_multiaxpy_norm<float, float, 4, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<float>(), w.T, tile_units, ncol, (double)sign, part);
+  DD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncol), dim3(64), 0, c->stream, part, d_n2, nb, ncol);
   DD_HIP(hipGetLastError());
 }
 

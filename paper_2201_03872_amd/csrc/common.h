@@ -190,6 +190,9 @@ void mv_multidot(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out);
 // w -= sum_j coef[j*ncol+c] V_j   (coef complex, device)
 void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign);
 void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out);          // per column, real
+// mv_multiaxpy followed by mv_norm2 of w, fused into one pass where possible
+void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
+                        double* d_n2);
 // variants on caller-owned buffers (no context scratch: safe to capture in a graph)
 size_t multidot_partials(const MV& w, int k);
 void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out, double* part);

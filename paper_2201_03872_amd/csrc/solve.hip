@@ -265,8 +265,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     std::vector<MV> Vs(j + 1);
     for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, vprec, cap, nt);
     mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
-    mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
-    mv_norm2(c, vn, d_n2);
+    mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
     // one copy of the dots and the norm
     const size_t nh = (size_t)(j + 1) * ncol * 2;
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
