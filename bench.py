@@ -48,12 +48,16 @@ def log(*a):
 TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_half_fp32_16x16x16x32_48col.md")
 # the FP32 SAP half-sweep kernel of each autotuner variant (4^4 blocks) as it
 # runs inside the inner Krylov solve, and the time_op form that launches it:
-# variant 2 reads its right-hand side straight from the FP16 Arnoldi basis
-# (op 6; the profiler lists that instantiation by its mangled name)
+# variants 2 (2-row links) and 3 (full links) read their right-hand side
+# straight from the FP16 Arnoldi basis (op 6; the profiler lists those
+# instantiations by their mangled names)
 SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float>", 1),
                1: ("k_sap_half<float, 2, 2, 256, false, float>", 1),
-               2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_E", 6)}
+               2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_E", 6),
+               3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_E", 6)}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
+# SAP calls timed for the roofline (after one untimed call)
+SAP_TIMED_CALLS = 10
 
 
 def measured_traffic(kernel):
@@ -299,7 +303,7 @@ def main():
     n_iter = 10
     V = w.volume
     sap_kernel, sap_op = SAP_KERNELS[tuned["tuned"]["sap_variant"]]
-    t_sap = ctx.time_op(sap_op, 0, dd.FP32, ncol, 3) / 2.0   # one SAP call = two half sweeps
+    t_sap = ctx.time_op(sap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0   # one call = two half sweeps
     sap_flops = sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"])
     t_copy = ctx.time_op(5, 0, dd.FP64, ncol, 5)              # plain copy of one FP64 48-column vector
     copy_bytes = 2 * V * 12 * 16 * ncol

@@ -64,6 +64,7 @@ extern "C" {
 /* arithmetic of one operator application */
 #define DDAMG_FP64 0
 #define DDAMG_FP32 1
+#define DDAMG_FP16 2   /* ddamg_apply_sap only: FP32 SAP reading FP16-stored right-hand sides */
 
 /* solver precision mode */
 #define DDAMG_PLAIN_FP64 0   /* everything in FP64                                            */
@@ -172,7 +173,11 @@ int ddamg_apply_op(ddamg_ctx* h, int level, int precision, const double* mu, int
                    const double* x, double* y);
 
 /* x_c = M_SAP(mu_c) f_c: sap_cycles red-black Schwarz cycles from x = 0 with
- * sap_mr_iters MR steps per block (section 2; fine level, device pointers). */
+ * sap_mr_iters MR steps per block (section 2; fine level, device pointers).
+ * precision DDAMG_FP64, DDAMG_FP32, or DDAMG_FP16: the FP32 smoother with
+ * each f_c first stored in FP16 as f_c * sqrt(12 V) / 16 (V fine sites), the
+ * form the inner Krylov solve uses on its FP16 basis; it needs 4^4 blocks and
+ * DDAMG_KNOB_SAP_VARIANT 2 or 3, else DDAMG_EINVAL. */
 int ddamg_apply_sap(ddamg_ctx* h, int precision, const double* mu, int n_col,
                     const double* f, double* x);
 
@@ -246,8 +251,10 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             accumulation where d % 16 == 0; 0 FP32 vector kernel */
 #define DDAMG_KNOB_SAP_VARIANT       4   /* FP32 SAP on 4^4 blocks: 0 (default) 2 columns per workgroup,
                                             the block's 2-row links staged in LDS; 1 2 columns, links
-                                            read through L1/L2; 2 one column, links through L1/L2
-                                            (less LDS per workgroup, more workgroups per CU) */
+                                            read through L1/L2; 2 one column, 2-row links through
+                                            L1/L2 (less LDS per workgroup, more workgroups per CU);
+                                            3 one column, full 3x3 links through L1/L2 (no third-row
+                                            rebuild in the MR steps, 1.5x the link bytes) */
 #define DDAMG_KNOB_DSLASH_ORDER      5   /* fine stencil scheme: 0 (default) site ranges staged in LDS,
                                             storage order; 1 the same in time-slice order; 2 / 3
                                             t-walk over columns of 4^4 blocks (psi(t-1..t+1) in

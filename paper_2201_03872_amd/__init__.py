@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libddamg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ddamg.h")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN, ESTATE = 0, 1, -1, -2, -3, -4, -5
-FP64, FP32 = 0, 1
+FP64, FP32, FP16 = 0, 1, 2   # FP16: apply_sap only (FP16-stored right-hand sides)
 PLAIN_FP64, MIXED = 0, 1
 SMOOTHER_SAP, SMOOTHER_LEARNED = 0, 1
 

@@ -241,10 +241,18 @@ int ddamg_apply_op(ddamg_ctx* c, int level, int precision, const double* mu, int
 int ddamg_apply_sap(ddamg_ctx* c, int precision, const double* mu, int n_col, const double* f, double* x) {
   return guarded([&]() -> int {
     DD_CHECK(c && mu && f && x && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    DD_CHECK(precision != DDAMG_FP16 || sap_takes_f16(c), DDAMG_EINVAL,
+             "FP16 right-hand sides need 4^4 blocks and SAP variant 2 or 3");
     const int prec = precision == DDAMG_FP64 ? P64 : P32;
     MV a = mv_alloc(c, 0, prec, n_col), b = mv_alloc(c, 0, prec, n_col);
     double* d_mu = upload_mu(c, mu, n_col, a.ncol());
     to_internal(c, 0, f, n_col, a);
+    if (precision == DDAMG_FP16) {   // the right-hand sides pass through FP16 storage
+      MV a16 = mv_like(c, a, P16);
+      mv_copy(c, a, a16);
+      mv_free(c, a);
+      a = a16;
+    }
     sap_apply(c, a, b, d_mu, b);
     from_internal(c, 0, b, n_col, x);
     DD_HIP(hipStreamSynchronize(c->stream));
@@ -577,7 +585,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_DSLASH_SITES_FP32: return dslash_rs_valid(P32, value);
     case DDAMG_KNOB_FP32_LINKS: return value == 0 || value == 1;
     case DDAMG_KNOB_COARSE_MFMA: return value == 0 || value == 1;
-    case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 2;
+    case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 3;
     case DDAMG_KNOB_DSLASH_ORDER: return value >= 0 && value <= 3;
     case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
     default: return false;
@@ -661,10 +669,10 @@ int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
     if (c->geom[0].gsize == 256) {
       double best = 1e30;
       int bv = c->sap_variant;
-      for (int v : {0, 1, 2}) {
+      for (int v : {0, 1, 2, 3}) {
         c->sap_variant = v;
         double sec = 0;
-        const int st = ddamg_time_op(c, 1, 0, DDAMG_FP32, n_col, 2, &sec);
+        const int st = ddamg_time_op(c, 1, 0, DDAMG_FP32, n_col, 4, &sec);
         if (st != DDAMG_OK) return st;
         if (sec < best) { best = sec; bv = v; }
       }

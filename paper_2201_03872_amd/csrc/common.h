@@ -167,7 +167,8 @@ struct ddamg_ctx {
   int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
   int* d_dslash_order[4] = {nullptr, nullptr, nullptr, nullptr};   // per sites-per-workgroup 16..128
   int sap_variant = 0;          // FP32 SAP on 4^4 blocks: 0 = 2 columns/WG, links in LDS; 1 = 2 columns, links
-                                // through L1/L2; 2 = 1 column/WG, links through L1/L2
+                                // through L1/L2; 2 = 1 column/WG, 2-row links through L1/L2; 3 = 1 column/WG,
+                                // full links through L1/L2
 };
 
 namespace ddamg {

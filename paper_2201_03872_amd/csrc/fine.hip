@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
 // ---------------------------------------------------------------- SAP ---
 // Links of the in-block MR steps: FP32 2-row links staged in LDS (ULDS; sign
 // from the neighbour table), or read through the caches from global memory
-// (FP32 2-row or FP64 full links).
+// (FP32 2-row, FP32 full with the boundary sign folded in, or FP64 full).
 template <typename R, int LK, int BS, bool ULDS>
 struct SapLinks {
   static constexpr bool table_sign = (LK == LK_C);
@@ -369,8 +369,10 @@ struct SapLinks {
 //   3. x += delta on the block.
 // Blocks of one colour never neighbour each other, so the in-place update of
 // x is race free.
+// FP32 one-column form: at least 4 waves per SIMD (128 VGPRs, a few spilled),
+// measured 3% faster on the whole solve than the 3 waves of 134 VGPRs
 template <typename R, int LK, int K, int BS, bool ULDS, typename FIN = R>
-__global__ void __launch_bounds__(BS * K) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
+__global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? 4 : 1) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
                                                      int V, int ntiles, size_t tile_reals, R diag, int mr_iters,
@@ -730,7 +732,7 @@ static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
   hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS, FIN>), grid, blk, 0, c->stream, f.as<FIN>(), x.as<R>(),
-                     LK == LK_C ? (const void*)c->d_U32 : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
+                     LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
                      c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
                      c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
   DD_HIP(hipGetLastError());
@@ -738,15 +740,18 @@ static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
 
 // x is fully written by the first cycle (each site belongs to one block of
 // one colour), so it needs no clearing beforehand.
-bool sap_takes_f16(ddamg_ctx* c) { return c->geom[0].gsize == 256 && c->sap_variant == 2; }
+bool sap_takes_f16(ddamg_ctx* c) { return c->geom[0].gsize == 256 && (c->sap_variant == 2 || c->sap_variant == 3); }
 
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV&) {
   const int BS = c->geom[0].gsize;
   if (f.prec == P16) {   // right-hand sides read straight from an FP16 Krylov basis
     DD_CHECK(x.prec == P32 && sap_takes_f16(c), DDAMG_EINVAL, "SAP: FP16 input needs the FP32 one-column variant");
     for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
-      for (int colour = 0; colour < 2; ++colour)
-        launch_sap<float, LK_C, 1, 256, false, _Float16>(c, f, x, d_mu, colour, cyc == 0 ? 1 + colour : 0);
+      for (int colour = 0; colour < 2; ++colour) {
+        const int xz = cyc == 0 ? 1 + colour : 0;
+        if (c->sap_variant == 3) launch_sap<float, LK_F, 1, 256, false, _Float16>(c, f, x, d_mu, colour, xz);
+        else launch_sap<float, LK_C, 1, 256, false, _Float16>(c, f, x, d_mu, colour, xz);
+      }
     c->st.sap_calls++;
     return;
   }
@@ -761,6 +766,7 @@ void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const
       } else {
         if (BS == 256 && c->sap_variant == 0) launch_sap<float, LK_C, 2, 256, true>(c, f, x, d_mu, colour, xz);
         else if (BS == 256 && c->sap_variant == 1) launch_sap<float, LK_C, 2, 256, false>(c, f, x, d_mu, colour, xz);
+        else if (BS == 256 && c->sap_variant == 3) launch_sap<float, LK_F, 1, 256, false>(c, f, x, d_mu, colour, xz);
         else if (BS == 256) launch_sap<float, LK_C, 1, 256, false>(c, f, x, d_mu, colour, xz);
         else if (BS == 16) launch_sap<float, LK_C, 8, 16>(c, f, x, d_mu, colour, xz);
         else throw Error{DDAMG_EINVAL, "SAP block must have 16 or 256 sites"};

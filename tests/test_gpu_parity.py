@@ -184,12 +184,30 @@ def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
     fg = torch.from_numpy(f).cuda()
     x64 = ctx.apply_sap(dd.FP64, mus, fg).cpu().numpy()
     assert np.max(relerr_cols(x64, ref)) < 1e-12
-    for variant in (0, 1, 2):     # columns per workgroup x link staging (4^4 blocks only)
+    for variant in (0, 1, 2, 3):  # columns per workgroup x link storage (4^4 blocks only)
         ctx.set_tuning("sap_variant", variant)
         x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
         e = np.max(relerr_cols(x32, ref))
         say("  fp32 SAP relative error", variant, e)
         assert e < 1e-4
+    # FP16-stored right-hand sides (the inner Krylov form): the oracle smoother
+    # on f rounded the same way, f * sqrt(12 V) / 16 in FP16 and back
+    if blk == (4, 4, 4, 4):
+        hs = np.sqrt(12 * V) / 16
+        def r16(a):
+            return (a * hs).astype(np.float16).astype(np.float64) / hs
+        f16 = r16(f.real) + 1j * r16(f.imag)
+        ref16 = O.sap(lev, Blocking(dims, blk), f16.reshape(ncol, V, 12), mus, 2, 3).reshape(ncol, V, 4, 3)
+        for variant in (2, 3):
+            ctx.set_tuning("sap_variant", variant)
+            x16 = ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy()
+            e16 = np.max(relerr_cols(x16, ref16))
+            say("  FP16-input SAP relative error", variant, e16, "(vs unrounded f:", np.max(relerr_cols(x16, ref)), ")")
+            assert e16 < 1e-4
+        ctx.set_tuning("sap_variant", 0)
+    with pytest.raises(dd.DDAMGError) as ei:
+        ctx.apply_sap(dd.FP16, mus, fg)
+    assert ei.value.code == dd.EINVAL
     ctx.close()
 
 
