@@ -19,6 +19,20 @@ Gamma basis (chiral, Hermitian, Euclidean):
     gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4 = diag(1, 1, -1, -1)
 so chirality +1 is spins {0, 1} and chirality -1 is spins {2, 3}.
 
+Clover term (optional, c_sw != 0).  The paper's ensembles are twisted-mass
+clover but it gives no formula, so the standard Sheikholeslami-Wohlert term is
+taken, in the m0 normalisation above:
+
+    D(mu) += c_sw (i/4) sum_{mu != nu} sigma_{mu nu} F_{mu nu}(x)
+    sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu]
+    F_{mu nu}(x)  = (Q_{mu nu}(x) - Q_{mu nu}(x)^dagger) / 8
+
+where Q_{mu nu}(x) is the sum of the four plaquettes of the (mu, nu) plane
+that start and end at x, all run in the same sense (mu before nu).  Closed
+loops cross the time boundary an even number of times, so the antiperiodic
+sign drops out.  The term is Hermitian and commutes with gamma5, so it keeps
+gamma5-hermiticity and splits into one 6x6 block per chirality.
+
 Arrays: gauge complex128 [V][4][3][3]; spinor multivector complex128
 [n][V][4][3] with site index i = x + Lx*(y + Ly*(z + Lz*t)).
 """
@@ -26,7 +40,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["gammas", "gamma5", "WilsonTM", "lattice_shape"]
+__all__ = ["gammas", "gamma5", "sigma_munu", "clover_field", "WilsonTM", "lattice_shape"]
 
 
 def gammas() -> np.ndarray:
@@ -45,6 +59,48 @@ def gammas() -> np.ndarray:
 def gamma5() -> np.ndarray:
     g = gammas()
     return g[0] @ g[1] @ g[2] @ g[3]
+
+
+def sigma_munu() -> np.ndarray:
+    """sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu], shape (4, 4, 4, 4)."""
+    g = gammas()
+    out = np.zeros((4, 4, 4, 4), dtype=np.complex128)
+    for m in range(4):
+        for n in range(4):
+            out[m, n] = 0.5j * (g[m] @ g[n] - g[n] @ g[m])
+    return out
+
+
+def _dag(a):
+    return np.conj(np.swapaxes(a, -1, -2))
+
+
+def clover_field(U_lat, csw):
+    """The clover term as a per-site 12x12 matrix, shape lat + (4, 3, 4, 3)
+    (spin, colour, spin, colour).  U_lat[mu]: lat + (3, 3)."""
+    def at(a, steps):
+        """a(x + sum_d s_d d) for steps = {direction: s_d}."""
+        for d, k in steps.items():
+            a = np.roll(a, -k, axis=_axis(d))
+        return a
+
+    sig = sigma_munu()
+    lat = U_lat[0].shape[:4]
+    C = np.zeros(lat + (4, 3, 4, 3), dtype=np.complex128)
+    for mu in range(4):
+        for nu in range(4):
+            if mu == nu:
+                continue
+            Um, Un = U_lat[mu], U_lat[nu]
+            # the four leaves: (+mu, +nu, -mu, -nu) and its three rotations
+            l1 = Um @ at(Un, {mu: 1}) @ _dag(at(Um, {nu: 1})) @ _dag(Un)
+            l2 = Un @ _dag(at(Um, {nu: 1, mu: -1})) @ _dag(at(Un, {mu: -1})) @ at(Um, {mu: -1})
+            l3 = _dag(at(Um, {mu: -1})) @ _dag(at(Un, {mu: -1, nu: -1})) @ at(Um, {mu: -1, nu: -1}) @ at(Un, {nu: -1})
+            l4 = _dag(at(Un, {nu: -1})) @ at(Um, {nu: -1}) @ at(Un, {nu: -1, mu: 1}) @ _dag(Um)
+            Q = l1 + l2 + l3 + l4
+            F = (Q - _dag(Q)) / 8.0
+            C += csw * 0.25j * np.einsum("ac,...bd->...abcd", sig[mu, nu], F)
+    return C
 
 
 def lattice_shape(dims):
@@ -81,8 +137,9 @@ def _spin(G, psi):
 class WilsonTM:
     """FP64 twisted-mass Wilson operator on a 4-d lattice."""
 
-    def __init__(self, U: np.ndarray, dims, kappa: float = None, m0: float = None):
+    def __init__(self, U: np.ndarray, dims, kappa: float = None, m0: float = None, csw: float = 0.0):
         self.dims = tuple(int(d) for d in dims)
+        self.csw = float(csw)
         self.V = int(np.prod(self.dims))
         if m0 is None:
             m0 = 1.0 / (2.0 * kappa) - 4.0
@@ -101,6 +158,7 @@ class WilsonTM:
         self.bc_fwd[Lt - 1] = -1.0
         self.bc_bwd = np.ones(self.lat[:1] + (1, 1, 1), dtype=np.float64)
         self.bc_bwd[0] = -1.0
+        self.clover = clover_field(self.U, self.csw) if self.csw != 0.0 else None
 
     # -- shapes --------------------------------------------------------------
     def to_lat(self, psi):
@@ -131,10 +189,24 @@ class WilsonTM:
         t = _colour(Ub[None], nb, dagger=True)
         return -0.5 * _spin(self.one + self.g[mu], t)
 
-    def diag(self, psi_lat, mus):
-        """(4 + m0) psi + i mu gamma5 psi, mu per column."""
-        mus = np.asarray(mus, dtype=np.float64).reshape(-1)
+    def clover_apply(self, psi_lat):
+        """The clover term on lattice-shaped spinors [n] + lat + (4, 3) (zero
+        without a clover term)."""
+        if self.clover is None:
+            return np.zeros_like(psi_lat)
+        return np.einsum("...abcd,n...cd->n...ab", self.clover, psi_lat)
+
+    def site_term(self, psi_lat):
+        """The mu-independent site term (4 + m0) psi + clover psi."""
         out = (4.0 + self.m0) * psi_lat
+        if self.clover is not None:
+            out = out + self.clover_apply(psi_lat)
+        return out
+
+    def diag(self, psi_lat, mus):
+        """(4 + m0 + clover) psi + i mu gamma5 psi, mu per column."""
+        mus = np.asarray(mus, dtype=np.float64).reshape(-1)
+        out = self.site_term(psi_lat)
         tw = _spin(self.g5, psi_lat)
         out = out + 1j * mus.reshape((-1,) + (1,) * (psi_lat.ndim - 1)) * tw
         return out
@@ -174,6 +246,8 @@ class WilsonTM:
             c = [x, y, z, t]
             acc = (4.0 + self.m0) * psi[:, i] + 1j * mus[:, None, None] * np.einsum(
                 "st,ntc->nsc", self.g5, psi[:, i])
+            if self.csw != 0.0:
+                acc = acc + np.einsum("abcd,ncd->nab", self.clover_at_site(i), psi[:, i])
             for mu in range(4):
                 cf = list(c); cf[mu] = (c[mu] + 1) % self.dims[mu]
                 cb = list(c); cb[mu] = (c[mu] - 1) % self.dims[mu]
@@ -187,6 +261,46 @@ class WilsonTM:
                                    + np.einsum("st,ntc->nsc", self.one + self.g[mu], hb))
             out[:, k] = acc
         return out
+
+    def clover_at_site(self, i):
+        """The 12x12 clover matrix (4, 3, 4, 3) of site i, evaluated loop by
+        loop from the links around the site (independent of the field form)."""
+        Lx, Ly, Lz, Lt = self.dims
+        Uflat = [u.reshape(self.V, 3, 3) for u in self.U]
+        c0 = [i % Lx, (i // Lx) % Ly, (i // (Lx * Ly)) % Lz, i // (Lx * Ly * Lz)]
+
+        def idx(c):
+            return (c[0] % Lx) + Lx * ((c[1] % Ly) + Ly * ((c[2] % Lz) + Lz * (c[3] % Lt)))
+
+        def link(c, d, forward):
+            """the parallel transporter of one step from site c along +d
+            (forward) or -d (backward)."""
+            if forward:
+                return Uflat[d][idx(c)]
+            cb = list(c); cb[d] -= 1
+            return np.conj(Uflat[d][idx(cb)]).T
+
+        sig = sigma_munu()
+        C = np.zeros((4, 3, 4, 3), dtype=np.complex128)
+        for mu in range(4):
+            for nu in range(4):
+                if mu == nu:
+                    continue
+                Q = np.zeros((3, 3), dtype=np.complex128)
+                for first, second in ((mu, nu), (nu, -mu - 1), (-mu - 1, -nu - 1), (-nu - 1, mu)):
+                    # walk first, second, -first, -second (negative codes: backward)
+                    path = [first, second, (-first - 1), (-second - 1)]
+                    c = list(c0)
+                    M = np.eye(3, dtype=np.complex128)
+                    for step in path:
+                        d, fw = (step, True) if step >= 0 else (-step - 1, False)
+                        M = M @ link(c, d, fw)
+                        c[d] += 1 if fw else -1
+                    assert [a % n for a, n in zip(c, self.dims)] == [a % n for a, n in zip(c0, self.dims)]
+                    Q += M
+                F = (Q - Q.conj().T) / 8.0
+                C += self.csw * 0.25j * np.einsum("ac,bd->abcd", sig[mu, nu], F)
+        return C
 
     def gamma5_apply(self, psi):
         return np.einsum("st,nvtc->nvsc", self.g5, psi)

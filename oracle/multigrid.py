@@ -98,8 +98,11 @@ class FineLevel:
         return self.op.apply(x.reshape(x.shape[0], self.V, 4, 3), mus).reshape(x.shape[0], self.V, 12)
 
     def diag0(self, x):
-        """The mu-independent diagonal (4 + m0) x."""
-        return (4.0 + self.op.m0) * x
+        """The mu-independent site term (4 + m0) x, plus the clover term when
+        the operator has one."""
+        if self.op.clover is None:
+            return (4.0 + self.op.m0) * x
+        return self._flat(self.op.site_term(self._lat(x)))
 
     def twist(self, x):
         """gamma5 x (the twist is i*mu times this)."""
