@@ -51,10 +51,10 @@ TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_half_fp32_16x16x16x32_48col
 # variants 2 (2-row links) and 3 (full links) read their right-hand side
 # straight from the FP16 Arnoldi basis (op 6; the profiler lists those
 # instantiations by their mangled names)
-SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float>", 1),
-               1: ("k_sap_half<float, 2, 2, 256, false, float>", 1),
-               2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_E", 6),
-               3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_E", 6)}
+SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
+               1: ("k_sap_half<float, 2, 2, 256, false, float, false>", 1),
+               2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_Lb0EEE", 6),
+               3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_Lb0EEE", 6)}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
 # SAP calls timed for the roofline (after one untimed call)
 SAP_TIMED_CALLS = 10

@@ -117,6 +117,8 @@ typedef struct ddamg_params {
                              /* the others wait and join as converged columns leave             */
   uint64_t seed;             /* counter-based RNG seed of the setup vectors when none are given */
   int    verbose;            /* 0 = silent                                                      */
+  double csw;                /* clover coefficient c_sw of the site term c_sw (i/4) sum          */
+                             /* sigma_{mu nu} F_{mu nu} (clover-leaf F); 0 = no clover term       */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

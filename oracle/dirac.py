@@ -158,7 +158,14 @@ class WilsonTM:
         self.bc_fwd[Lt - 1] = -1.0
         self.bc_bwd = np.ones(self.lat[:1] + (1, 1, 1), dtype=np.float64)
         self.bc_bwd[0] = -1.0
-        self.clover = clover_field(self.U, self.csw) if self.csw != 0.0 else None
+        self._clover = None
+
+    @property
+    def clover(self):
+        """The clover field (computed on first use; None without a clover term)."""
+        if self.csw != 0.0 and self._clover is None:
+            self._clover = clover_field(self.U, self.csw)
+        return self._clover
 
     # -- shapes --------------------------------------------------------------
     def to_lat(self, psi):

@@ -69,6 +69,7 @@ class Params(ctypes.Structure):
         ("max_active_cols", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
+        ("csw", ctypes.c_double),
     ]
 
 

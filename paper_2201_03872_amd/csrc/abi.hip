@@ -97,12 +97,14 @@ void ddamg_default_params(ddamg_params* p) {
   p->col_tile = 8;
   p->seed = 12345;
   p->verbose = 0;
+  p->csw = 0.0;
 }
 
 static void validate(const ddamg_params* p) {
   DD_CHECK(p, DDAMG_EINVAL, "null params");
   DD_CHECK(p->n_levels >= 1 && p->n_levels <= 3, DDAMG_EINVAL, "n_levels must be 1, 2 or 3");
   DD_CHECK(p->kappa > 0, DDAMG_EINVAL, "kappa must be positive");
+  DD_CHECK(std::isfinite(p->csw), DDAMG_EINVAL, "csw must be finite");
   DD_CHECK(p->col_tile == 0 || p->col_tile == 8, DDAMG_EINVAL, "col_tile must be 8");
   int dims[4];
   for (int m = 0; m < 4; ++m) {
@@ -169,6 +171,7 @@ int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
       }
       build_sap_lists(c);
       upload_gauge(c, gauge, gauge_on_device);
+      if (p->csw != 0.0) build_clover(c);
       build_hierarchy(c, tv_init);
       DD_HIP(hipStreamSynchronize(c->stream));
     } catch (...) {

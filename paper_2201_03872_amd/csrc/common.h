@@ -145,6 +145,8 @@ struct ddamg_ctx {
   double* d_U64 = nullptr;    // [4 mu][9 chunk][V] double2
   float* d_U32 = nullptr;     // [4 mu][3 chunk][V] float4, rows 0 and 1 (no boundary sign)
   float* d_U32f = nullptr;    // [4 mu][5 chunk][V] float4, full links, boundary sign folded in
+  double* d_clov64 = nullptr; // clover site term (c_sw != 0): [36 chunk][V] double2, two packed 6x6 blocks
+  float* d_clov32 = nullptr;  // the same in FP32: [18 chunk][V] float4
   int* d_sap_list[2] = {nullptr, nullptr};   // block ids of each colour
   int n_sap[2] = {0, 0};
   double* d_scratch = nullptr;  // reduction partials
@@ -211,7 +213,8 @@ void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu);
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu);
 void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hop);
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV& work);
-bool sap_takes_f16(ddamg_ctx* c);   // sap_apply accepts an FP16 right-hand side
+bool sap_takes_f16(ddamg_ctx* c);
+void build_clover(ddamg_ctx* c);   // clover site term from the FP64 links (c_sw != 0)   // sap_apply accepts an FP16 right-hand side
 bool dslash_rs_valid(int prec, int rs);
 
 // ---- coarse kernels (coarse.hip) ----

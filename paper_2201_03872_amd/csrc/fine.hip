@@ -215,6 +215,190 @@ __device__ __forceinline__ void site_diag(cx<R> (&out)[12], const cx<R> (&x)[12]
   }
 }
 
+// ------------------------------------------------------- clover term ---
+// Site term with a clover (Sheikholeslami-Wohlert form, the reading taken for
+// the twisted-mass clover operator): A(x) = (4 + m0) + c_sw (i/4)
+// sum_{mu != nu} sigma_{mu nu} F_{mu nu}(x), sigma_{mu nu} = (i/2)[gamma_mu,
+// gamma_nu], F = (Q - Q^dagger) / 8 with Q the four plaquettes at x.  In the
+// chiral basis sigma_{kl} = -eps_{klm} diag(s_m, s_m) and sigma_{k4} =
+// diag(s_k, -s_k) (s = Pauli matrices), so A has one 6x6 block per chirality
+// c = +1 (spins 0, 1) and c = -1 (spins 2, 3), with row 3 * spin + colour:
+//   A_c = (4 + m0) + c_sw (i/2) [[E3, E1 - i E2], [E1 + i E2, -E3]],
+//   E1 = -F_yz + c F_xt,  E2 = F_xz + c F_yt,  E3 = -F_xy + c F_zt.
+// Each Hermitian block is packed as its 6 real diagonal entries and the 15
+// complex entries above the diagonal, row by row (36 reals); a site's 72 reals
+// are stored as chunks of the working precision, [72 / RW][V] like the links.
+constexpr int CLOV_REALS = 72;
+
+__host__ __device__ constexpr int clov_upper(int i, int j) { return 6 + 2 * (i * (11 - i) / 2 + (j - i - 1)); }
+
+// y = A(x) v at site s, streamed chunk by chunk (one chunk of the packed
+// block live at a time; complexes never straddle a chunk since the 6 diagonal
+// reals are an even count)
+__device__ constexpr int CLOV_I[15] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4};
+__device__ constexpr int CLOV_J[15] = {1, 2, 3, 4, 5, 2, 3, 4, 5, 3, 4, 5, 4, 5, 5};
+template <typename R>
+__device__ __forceinline__ void clover_mul(const R* __restrict__ clov, int V, int s, const cx<R> (&v)[12],
+                                           cx<R> (&y)[12]) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW, NB = 36 / RW;
+  const C* cc = reinterpret_cast<const C*>(clov);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) y[k] = {0, 0};
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int o = 6 * b;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const C ch = cc[(size_t)(b * NB + k) * V + s];
+      R e[RW];
+      if constexpr (RW == 2) {
+        e[0] = ch.x;
+        e[1] = ch.y;
+      } else {
+        e[0] = ch.x;
+        e[1] = ch.y;
+        e[2] = ch.z;
+        e[3] = ch.w;
+      }
+#pragma unroll
+      for (int h = 0; h < RW; h += 2) {
+        const int r = k * RW + h;
+        if (r < 6) {   // two real diagonal entries
+          y[o + r] = y[o + r] + e[h] * v[o + r];
+          y[o + r + 1] = y[o + r + 1] + e[h + 1] * v[o + r + 1];
+        } else {       // A_ij (i < j): y_i += A_ij v_j, y_j += conj(A_ij) v_i
+          const int q = (r - 6) / 2, i = CLOV_I[q], j = CLOV_J[q];
+          const cx<R> u{e[h], e[h + 1]};
+          cmac(y[o + i], u, v[o + j]);
+          cmac_conj(y[o + j], u, v[o + i]);
+        }
+      }
+    }
+  }
+}
+
+// out = A(x) x + i mu gamma5 x - 1/2 acc
+template <typename R>
+__device__ __forceinline__ void site_diag_cl(cx<R> (&out)[12], const cx<R> (&x)[12], const cx<R> (&acc)[12],
+                                             const R* __restrict__ clov, int V, int s, R mu) {
+  clover_mul(clov, V, s, x, out);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const R g = k < 6 ? mu : -mu;
+    out[k].re += -g * x[k].im - (R)0.5 * acc[k].re;
+    out[k].im += g * x[k].re - (R)0.5 * acc[k].im;
+  }
+}
+
+// The packed clover term of every site from the FP64 links (the boundary sign
+// folded into them cancels: a closed loop crosses the time boundary an even
+// number of times).  One thread per site; writes FP64 and FP32 copies.
+__device__ __forceinline__ void m3_load(const double* __restrict__ U, int mu, int s, int V, cx<double> (&m)[9]) {
+  const double2* u = reinterpret_cast<const double2*>(U);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 e = u[((size_t)mu * 9 + k) * V + s];
+    m[k] = {e.x, e.y};
+  }
+}
+__device__ __forceinline__ void m3_mul(const cx<double> (&a)[9], const cx<double> (&b)[9], bool da, bool db,
+                                       cx<double> (&c)[9]) {
+  // c = op(a) op(b), op = dagger when flagged
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<double> acc{0, 0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const cx<double> x = da ? conj_(a[k * 3 + i]) : a[i * 3 + k];
+        const cx<double> y = db ? conj_(b[j * 3 + k]) : b[k * 3 + j];
+        acc = acc + x * y;
+      }
+      c[i * 3 + j] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(128) k_clover_build(const double* __restrict__ U, const int* __restrict__ nbr, int V,
+                                                      double csw, double diag, double* __restrict__ out64,
+                                                      float* __restrict__ out32) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  auto nb = [&](int h, int site) { return nbr[(size_t)h * V + site] & 0x7fffffff; };
+  // F[p] for the planes xy, xz, xt, yz, yt, zt
+  cx<double> F[6][9];
+  const int PM[6] = {0, 0, 0, 1, 1, 2}, PN[6] = {1, 2, 3, 2, 3, 3};
+#pragma unroll 1
+  for (int p = 0; p < 6; ++p) {
+    const int mu = PM[p], nu = PN[p];
+    const int xpm = nb(mu, s), xpn = nb(nu, s), xmm = nb(4 + mu, s), xmn = nb(4 + nu, s);
+    const int xpn_mm = nb(4 + mu, xpn), xmm_mn = nb(4 + nu, xmm), xmn_pm = nb(mu, xmn);
+    cx<double> A[9], B[9], T1[9], T2[9], Q[9];
+    for (int k = 0; k < 9; ++k) Q[k] = {0, 0};
+    // leaf (+mu, +nu, -mu, -nu): U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+    m3_load(U, mu, s, V, A); m3_load(U, nu, xpm, V, B); m3_mul(A, B, false, false, T1);
+    m3_load(U, mu, xpn, V, A); m3_mul(T1, A, false, true, T2);
+    m3_load(U, nu, s, V, A); m3_mul(T2, A, false, true, T1);
+    for (int k = 0; k < 9; ++k) Q[k] = Q[k] + T1[k];
+    // leaf (+nu, -mu, -nu, +mu): U_nu(x) U_mu(x+nu-mu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+    m3_load(U, nu, s, V, A); m3_load(U, mu, xpn_mm, V, B); m3_mul(A, B, false, true, T1);
+    m3_load(U, nu, xmm, V, A); m3_mul(T1, A, false, true, T2);
+    m3_load(U, mu, xmm, V, A); m3_mul(T2, A, false, false, T1);
+    for (int k = 0; k < 9; ++k) Q[k] = Q[k] + T1[k];
+    // leaf (-mu, -nu, +mu, +nu): U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+    m3_load(U, mu, xmm, V, A); m3_load(U, nu, xmm_mn, V, B); m3_mul(A, B, true, true, T1);
+    m3_load(U, mu, xmm_mn, V, A); m3_mul(T1, A, false, false, T2);
+    m3_load(U, nu, xmn, V, A); m3_mul(T2, A, false, false, T1);
+    for (int k = 0; k < 9; ++k) Q[k] = Q[k] + T1[k];
+    // leaf (-nu, +mu, +nu, -mu): U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
+    m3_load(U, nu, xmn, V, A); m3_load(U, mu, xmn, V, B); m3_mul(A, B, true, false, T1);
+    m3_load(U, nu, xmn_pm, V, A); m3_mul(T1, A, false, false, T2);
+    m3_load(U, mu, s, V, A); m3_mul(T2, A, false, true, T1);
+    for (int k = 0; k < 9; ++k) Q[k] = Q[k] + T1[k];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const cx<double> q = Q[i * 3 + j], qt = conj_(Q[j * 3 + i]);
+        F[p][i * 3 + j] = {(q.re - qt.re) / 8.0, (q.im - qt.im) / 8.0};
+      }
+  }
+  enum { XY = 0, XZ = 1, XT = 2, YZ = 3, YT = 4, ZT = 5 };
+  for (int b = 0; b < 2; ++b) {
+    const double c = b == 0 ? 1.0 : -1.0;
+    cx<double> E1[9], E2[9], E3[9];
+    for (int k = 0; k < 9; ++k) {
+      E1[k] = (-1.0) * F[YZ][k] + c * F[XT][k];
+      E2[k] = F[XZ][k] + c * F[YT][k];
+      E3[k] = (-1.0) * F[XY][k] + c * F[ZT][k];
+    }
+    // the 6x6 block M = c_sw (i/2) [[E3, E1 - i E2], [E1 + i E2, -E3]] + diag
+    auto elem = [&](int r, int q) {
+      const int sr = r / 3, cr = r % 3, sq = q / 3, cq = q % 3, k = cr * 3 + cq;
+      cx<double> m;
+      if (sr == 0 && sq == 0) m = E3[k];
+      else if (sr == 1 && sq == 1) m = {-E3[k].re, -E3[k].im};
+      else if (sr == 0) m = E1[k] - mul_i(E2[k]);
+      else m = E1[k] + mul_i(E2[k]);
+      m = (0.5 * csw) * mul_i(m);
+      if (r == q) m.re += diag;
+      return m;
+    };
+    double a[36];
+    for (int i = 0; i < 6; ++i) a[i] = elem(i, i).re;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j) {
+        const cx<double> m = elem(i, j);
+        a[clov_upper(i, j)] = m.re;
+        a[clov_upper(i, j) + 1] = m.im;
+      }
+    for (int r = 0; r < 36; ++r) {
+      const int g = 36 * b + r;
+      out64[((size_t)(g / 2) * V + s) * 2 + g % 2] = a[r];
+      out32[((size_t)(g / 4) * V + s) * 4 + g % 4] = (float)a[r];
+    }
+  }
+}
+
 // ------------------------------------------------------------ dslash ---
 // MODE 0: y = D x ; MODE 1: y = b - D x
 template <typename R, int LK, int MODE>
@@ -252,12 +436,12 @@ __global__ void __launch_bounds__(256) k_dslash(const R* __restrict__ x, R* __re
 // LDS; only the neighbours outside the range go through L1/L2.  A site's
 // spinor is then fetched from the cache hierarchy about 3.5 times instead of
 // 9, which is what lets the kernel run at HBM speed rather than L2 speed.
-template <typename R, int LK, int MODE, int RS>
+template <typename R, int LK, int MODE, int RS, bool CL = false>
 __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x, R* __restrict__ y,
                                                         const R* __restrict__ b, const void* __restrict__ U,
                                                         const int* __restrict__ nbr, const double* __restrict__ mu,
                                                         int V, size_t tile_reals, R diag, int nsb,
-                                                        const int* __restrict__ order) {
+                                                        const int* __restrict__ order, const R* __restrict__ clov) {
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW, NCH = 24 / RW;
   __shared__ C lds[NCH * RS * TT];
@@ -294,7 +478,8 @@ __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x,
   cx<R> acc[12], out[12], xs[12];
   all_hops<R, LK>(acc, U, nbr, V, s, ld);
   from_lds(sl, xs);
-  site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
+  if constexpr (CL) site_diag_cl(out, xs, acc, clov, V, s, (R)mu[tile * TT + t]);
+  else site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
   if constexpr (MODE == 1) {
     cx<R> bs[12];
     load_cx<R, 12>(b + (size_t)tile * tile_reals, V, TT, s, t, bs);
@@ -312,7 +497,7 @@ __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x,
 __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict__ x, double* __restrict__ y,
                                                        const void* __restrict__ U, const int* __restrict__ nbr,
                                                        int V, size_t tile_reals, double diag, int nsb, int gsize,
-                                                       int mode, int hopi) {
+                                                       int mode, int hopi, const double* __restrict__ clov) {
   using R = double;
   const int t = threadIdx.x % TT, sl = threadIdx.x / TT;
   const int wg = blockIdx.x;
@@ -333,9 +518,15 @@ __global__ void __launch_bounds__(256) k_dslash_masked(const double* __restrict_
   cx<R> out[12];
   cx<R> xs[12];
   load_cx<R, 12>(xt, V, TT, s, t, xs);
-  const double dg = mode == 0 ? diag : 0.0;
+  if (mode == 0 && clov) {
+    clover_mul(clov, V, s, xs, out);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) out[k] = dg * xs[k] - 0.5 * acc[k];
+    for (int k = 0; k < 12; ++k) out[k] = out[k] - 0.5 * acc[k];
+  } else {
+    const double dg = mode == 0 ? diag : 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k] = dg * xs[k] - 0.5 * acc[k];
+  }
   store_cx<R, 12>(y + (size_t)tile * tile_reals, V, TT, s, t, out);
 }
 
@@ -371,12 +562,12 @@ struct SapLinks {
 // x is race free.
 // FP32 one-column form: at least 4 waves per SIMD (128 VGPRs, a few spilled),
 // measured 3% faster on the whole solve than the 3 waves of 134 VGPRs
-template <typename R, int LK, int K, int BS, bool ULDS, typename FIN = R>
-__global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? 4 : 1) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
+template <typename R, int LK, int K, int BS, bool ULDS, typename FIN = R, bool CL = false>
+__global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1 && !CL) ? 4 : 1) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
                                                      int V, int ntiles, size_t tile_reals, R diag, int mr_iters,
-                                                     int x_zero, float fscale) {
+                                                     int x_zero, float fscale, const R* __restrict__ clov) {
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW;
   constexpr int NCH = 24 / RW;
@@ -433,7 +624,8 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? 4 : 1) k_
       load_cx<R, 12>(xt, V, TT, s, t, xs);
     }
     load_f(fs);
-    site_diag(q, xs, acc, diag, m);
+    if constexpr (CL) site_diag_cl(q, xs, acc, clov, V, s, m);
+    else site_diag(q, xs, acc, diag, m);
 #pragma unroll
     for (int k = 0; k < 12; ++k) { rho[k] = fs[k] - q[k]; dl[k] = {0, 0}; }
   }
@@ -479,7 +671,8 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? 4 : 1) k_
     __syncthreads();
     cx<R> acc[12];
     all_hops_e<R, LK>(acc, lll, e8, s, ldl);
-    site_diag(q, rho, acc, diag, m);
+    if constexpr (CL) site_diag_cl(q, rho, acc, clov, V, s, m);
+    else site_diag(q, rho, acc, diag, m);
     R nr = 0, ni = 0, dd = 0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -652,14 +845,16 @@ static const int* dslash_order(ddamg_ctx* c, int RS) {
   return c->d_dslash_order[slot];
 }
 
-template <typename R, int LK, int MODE, int RS>
+template <typename R, int LK, int MODE, int RS, bool CL = false>
 static void launch_rs(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu, const void* U) {
   const int V = c->geom[0].V;
   const int nsb = (V + RS - 1) / RS;
-  const int* order = c->dslash_order ? dslash_order(c, RS) : nullptr;
-  hipLaunchKernelGGL((k_dslash_lds<R, LK, MODE, RS>), dim3(nsb * x.ntiles), dim3(RS * TT), 0, c->stream, x.as<R>(),
-                     y.as<R>(), b ? b->as<R>() : nullptr, U, c->geom[0].d_nbr, d_mu, V, x.tile_reals(), (R)c->diag,
-                     nsb, order);
+  const int* order = (c->dslash_order && !CL) ? dslash_order(c, RS) : nullptr;
+  const R* clov = nullptr;
+  if constexpr (CL) clov = (const R*)(sizeof(R) == 8 ? (const void*)c->d_clov64 : (const void*)c->d_clov32);
+  hipLaunchKernelGGL((k_dslash_lds<R, LK, MODE, RS, CL>), dim3(nsb * x.ntiles), dim3(RS * TT), 0, c->stream,
+                     x.as<R>(), y.as<R>(), b ? b->as<R>() : nullptr, U, c->geom[0].d_nbr, d_mu, V, x.tile_reals(),
+                     (R)c->diag, nsb, order, clov);
 }
 
 bool dslash_rs_valid(int prec, int rs) {
@@ -678,6 +873,14 @@ static void launch_f32(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, cons
 
 template <int MODE>
 static void launch_dslash(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, const double* d_mu) {
+  if (c->d_clov64) {   // with a clover term: the LDS-range kernel, 32 sites per workgroup, storage order
+    if (x.prec == P64) launch_rs<double, LK_D, MODE, 32, true>(c, x, y, b, d_mu, c->d_U64);
+    else if (c->fp32_links == 0) launch_rs<float, LK_F, MODE, 32, true>(c, x, y, b, d_mu, c->d_U32f);
+    else launch_rs<float, LK_C, MODE, 32, true>(c, x, y, b, d_mu, c->d_U32);
+    DD_HIP(hipGetLastError());
+    c->st.fine_ops++;
+    return;
+  }
   if (c->dslash_order >= 2 && dslash_walk_ok(c)) {   // t-walk kernel, 4 or 8 columns per workgroup
     const bool tc8 = c->dslash_order == 3;
     if (x.prec == P64) {
@@ -723,27 +926,70 @@ void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {
   const int nsb = nsb_of(V);
   dim3 grid(nsb * x.ntiles), blk(256);
   hipLaunchKernelGGL(k_dslash_masked, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->d_U64,
-                     c->geom[0].d_nbr, V, x.tile_reals(), c->diag, nsb, c->geom[0].gsize, mode, hopi);
+                     c->geom[0].d_nbr, V, x.tile_reals(), c->diag, nsb, c->geom[0].gsize, mode, hopi,
+                     c->d_clov64);
   DD_HIP(hipGetLastError());
 }
 
-template <typename R, int LK, int K, int BS, bool ULDS = true, typename FIN = R>
+template <typename R, int LK, int K, int BS, bool ULDS = true, typename FIN = R, bool CL = false>
 static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
   const int nb = c->n_sap[colour];
   dim3 grid(nb * x.ntiles * (TT / K)), blk(BS * K);
-  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS, FIN>), grid, blk, 0, c->stream, f.as<FIN>(), x.as<R>(),
-                     LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64, c->geom[0].d_nbr, d_mu,
-                     c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(), (R)c->diag,
-                     c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
+  const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
+  const R* clov = nullptr;
+  if constexpr (CL) clov = (const R*)(sizeof(R) == 8 ? (const void*)c->d_clov64 : (const void*)c->d_clov32);
+  hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS, FIN, CL>), grid, blk, 0, c->stream, f.as<FIN>(), x.as<R>(), U,
+                     c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(),
+                     (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale), clov);
   DD_HIP(hipGetLastError());
+}
+
+// SAP with a clover term: one column per workgroup on 4^4 blocks (full or
+// 2-row FP32 links by the variant knob), the 16-site forms otherwise
+static void sap_clover(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu) {
+  const int BS = c->geom[0].gsize;
+  const bool full = c->sap_variant == 3;
+  DD_CHECK(BS == 256 || BS == 16, DDAMG_EINVAL, "SAP block must have 16 or 256 sites");
+  for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
+    for (int colour = 0; colour < 2; ++colour) {
+      const int xz = cyc == 0 ? 1 + colour : 0;
+      if (f.prec == P16) {
+        if (full) launch_sap<float, LK_F, 1, 256, false, _Float16, true>(c, f, x, d_mu, colour, xz);
+        else launch_sap<float, LK_C, 1, 256, false, _Float16, true>(c, f, x, d_mu, colour, xz);
+      } else if (x.prec == P64) {
+        if (BS == 256) launch_sap<double, LK_D, 1, 256, true, double, true>(c, f, x, d_mu, colour, xz);
+        else launch_sap<double, LK_D, 4, 16, true, double, true>(c, f, x, d_mu, colour, xz);
+      } else if (BS == 256) {
+        if (full) launch_sap<float, LK_F, 1, 256, false, float, true>(c, f, x, d_mu, colour, xz);
+        else launch_sap<float, LK_C, 1, 256, false, float, true>(c, f, x, d_mu, colour, xz);
+      } else {
+        launch_sap<float, LK_C, 8, 16, true, float, true>(c, f, x, d_mu, colour, xz);
+      }
+    }
+  c->st.sap_calls++;
 }
 
 // x is fully written by the first cycle (each site belongs to one block of
 // one colour), so it needs no clearing beforehand.
+void build_clover(ddamg_ctx* c) {
+  const int V = c->geom[0].V;
+  c->d_clov64 = (double*)c->pool.alloc((size_t)V * CLOV_REALS * sizeof(double));
+  c->d_clov32 = (float*)c->pool.alloc((size_t)V * CLOV_REALS * sizeof(float));
+  hipLaunchKernelGGL(k_clover_build, dim3((V + 127) / 128), dim3(128), 0, c->stream, c->d_U64, c->geom[0].d_nbr, V,
+                     c->p.csw, c->diag, c->d_clov64, c->d_clov32);
+  DD_HIP(hipGetLastError());
+}
+
 bool sap_takes_f16(ddamg_ctx* c) { return c->geom[0].gsize == 256 && (c->sap_variant == 2 || c->sap_variant == 3); }
 
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV&) {
   const int BS = c->geom[0].gsize;
+  if (c->d_clov64) {
+    DD_CHECK(f.prec != P16 || (x.prec == P32 && sap_takes_f16(c)), DDAMG_EINVAL,
+             "SAP: FP16 input needs the FP32 one-column variant");
+    sap_clover(c, f, x, d_mu);
+    return;
+  }
   if (f.prec == P16) {   // right-hand sides read straight from an FP16 Krylov basis
     DD_CHECK(x.prec == P32 && sap_takes_f16(c), DDAMG_EINVAL, "SAP: FP16 input needs the FP32 one-column variant");
     for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
