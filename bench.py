@@ -10,8 +10,9 @@ before it, as it is shared by every solve on this gauge field.
 
 Printed JSON: value = converged rhs x shift solves per second of the tuned
 form; the plain FP64 GPU form of the same method; the roofline of the
-dominant kernel measured live with HIP events on the library's stream; and
-the FP64 oracle timed on the host on a bounded sample.
+dominant kernel measured live with HIP events on the library's stream; the
+same workload with a clover term (c_sw = 1.0); and the FP64 oracle timed on
+the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -58,6 +59,8 @@ SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
 # SAP calls timed for the roofline (after one untimed call)
 SAP_TIMED_CALLS = 10
+# clover coefficient of the twisted-mass clover form measured beside the headline
+CLOVER_CSW = 1.0
 
 
 def measured_traffic(kernel):
@@ -80,7 +83,7 @@ def measured_traffic(kernel):
         return None
 
 
-def sap_flops_per_half_sweep(V, ncol, mr):
+def sap_flops_per_half_sweep(V, ncol, mr, clover=False):
     """Algorithmic flops of one red-black SAP half sweep (half the sites),
     averaged over the two half sweeps of a one-cycle SAP call.
 
@@ -91,9 +94,14 @@ def sap_flops_per_half_sweep(V, ncol, mr):
     |q|^2 (12 flop per complex, 144) and the two complex axpys (8 flop per
     complex each, 192).  The block residual costs nothing in the first half
     sweep (x = 0, residual = right-hand side); in the second, x is still zero
-    inside its own blocks, so only the 2 block-leaving hops per site count."""
+    inside its own blocks, so only the 2 block-leaving hops per site count.
+    With a clover term the site term is two Hermitian 6x6 blocks (6 real
+    diagonal entries, 15 complex pairs: 504 flop) plus the twist and the
+    hop sum (72) in place of the 96 of the scalar diagonal; the second half
+    sweep's residual applies it to x = 0 and is not counted."""
     hop = 1320 / 8
-    per_site = 0.5 * (2 * hop) + mr * (6 * hop + 96 + 144 + 192)
+    site = 504 + 72 if clover else 96
+    per_site = 0.5 * (2 * hop) + mr * (6 * hop + site + 144 + 192)
     return V / 2 * ncol * per_site
 
 
@@ -245,6 +253,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-clover", action="store_true", help="skip the twisted-mass clover measurement")
     ap.add_argument("--learned", action="store_true",
                     help="instead of the solve benchmark, train the learned smoother on 8 gauge fields and "
                          "compare it with SAP on 4 held-out fields")
@@ -332,6 +341,29 @@ def main():
     cctx.close()
     log("coarse stencil", coarse)
 
+    # the twisted-mass clover operator on the same workload and solver
+    # (c_sw = CLOVER_CSW): one warm-up and one timed solve, the clover forms
+    # of the fine stencil and of the FP16-input SAP half sweep (HIP events)
+    clover = None
+    if not args.no_clover:
+        cctx, cl = run_form(dd.MIXED, 1, 1, dict(TUNED, csw=CLOVER_CSW))
+        log("clover form", cl)
+        t32c = cctx.time_op(0, 0, dd.FP32, ncol, n_iter)
+        t64c = cctx.time_op(0, 0, dd.FP64, ncol, n_iter)
+        csap_kernel, csap_op = SAP_KERNELS[cl["tuned"]["sap_variant"]]
+        tsc = cctx.time_op(csap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0
+        cctx.close()
+        links32c = 288 if cl["tuned"]["fp32_links"] == 0 else 192
+        bytes32c = V * (links32c + 288 + ncol * 48 * 4)      # + the FP32 clover blocks
+        bytes64c = V * (576 + 576 + ncol * 48 * 8)
+        csap_flops = sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"], clover=True)
+        clover = {"csw": CLOVER_CSW, "solves_per_s": ncol / cl["elapsed"] if cl["allconv"] else 0.0,
+                  "all_converged": cl["allconv"], "worst_true_rel_res": cl["worst"],
+                  "outer_iters": cl["stats"]["outer_iters"], "inner_iters": cl["stats"]["n_inner_iters"],
+                  "dslash_fp32_us": t32c * 1e6, "dslash_fp32_GBs": bytes32c / t32c / 1e9,
+                  "dslash_fp64_us": t64c * 1e6, "dslash_fp64_GBs": bytes64c / t64c / 1e9,
+                  "sap_half_sweep_us": tsc * 1e6, "sap_TFLOPs": csap_flops / tsc / 1e12}
+
     plain = None
     if not args.no_plain:
         pctx, plain = run_form(dd.PLAIN_FP64, 1, 0, SOLVER)
@@ -383,6 +415,7 @@ def main():
                      "us_per_launch": t_sap * 1e6},
         "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
         "coarse_stencil_48col": coarse,
+        "clover": clover,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -561,9 +561,10 @@ struct SapLinks {
 // Blocks of one colour never neighbour each other, so the in-place update of
 // x is race free.
 // FP32 one-column form: at least 4 waves per SIMD (128 VGPRs, a few spilled),
-// measured 3% faster on the whole solve than the 3 waves of 134 VGPRs
+// measured 3% faster on the whole solve than the 3 waves of 134 VGPRs; with a
+// clover term 3 waves (3% faster than the 2 of the unconstrained build)
 template <typename R, int LK, int K, int BS, bool ULDS, typename FIN = R, bool CL = false>
-__global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1 && !CL) ? 4 : 1) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
+__global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? (CL ? 3 : 4) : 1) k_sap_half(const FIN* __restrict__ f, R* __restrict__ x,
                                                      const void* __restrict__ U, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, const int* __restrict__ blist,
                                                      int V, int ntiles, size_t tile_reals, R diag, int mr_iters,
