@@ -20,8 +20,8 @@ Gamma basis (chiral, Hermitian, Euclidean):
 so chirality +1 is spins {0, 1} and chirality -1 is spins {2, 3}.
 
 Clover term (optional, c_sw != 0).  The paper's ensembles are twisted-mass
-clover but it gives no formula, so the standard Sheikholeslami-Wohlert term is
-taken, in the m0 normalisation above:
+clover (section 2, Fig. 1 caption) but it gives no formula, so the standard
+Sheikholeslami-Wohlert term is taken, in the m0 normalisation above:
 
     D(mu) += c_sw (i/4) sum_{mu != nu} sigma_{mu nu} F_{mu nu}(x)
     sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu]
