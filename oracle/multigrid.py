@@ -293,16 +293,72 @@ def block_mr(level, blocking: Blocking, r, mus, iters):
     return delta
 
 
-def sap(level, blocking: Blocking, f, mus, cycles, mr_iters, x0=None):
+def site_parity(dims):
+    """(x + y + z + t) mod 2 per site (lexicographic site order)."""
+    Lx, Ly, Lz, Lt = dims
+    i = np.arange(int(np.prod(dims)))
+    return ((i % Lx) + (i // Lx) % Ly + (i // (Lx * Ly)) % Lz + i // (Lx * Ly * Lz)) % 2
+
+
+def block_mr_oddeven(level, blocking: Blocking, r, mus, iters):
+    """Block solves by minimal residual on the odd-even reduced block systems.
+
+    Inside a block with even extents every hop joins an even and an odd site,
+    so with the site term D_ee (on even sites) and D_oo (odd sites) and the
+    hop parts D_eo, D_oe of D_BB:
+        D_BB x = r  <=>  S x_o = r_o - D_oe D_ee^{-1} r_e,   S = D_oo - D_oe D_ee^{-1} D_eo,
+                         x_e = D_ee^{-1} (r_e - D_eo x_o).
+    `iters` MR steps on S from zero (alpha per column and block), then the
+    even half by back substitution.  D_ee = (4 + m0) + i mu gamma5 is
+    inverted per chirality (no clover term)."""
+    assert getattr(level.op, "clover", None) is None, "odd-even block solves are for the clover-free operator"
+    mus = np.asarray(mus, dtype=np.float64).reshape(-1, 1, 1)
+    odd = site_parity(level.dims)[None, :, None].astype(np.float64)
+    even = 1.0 - odd
+    d0 = 4.0 + level.op.m0
+    g5 = np.concatenate([np.ones(6), -np.ones(6)])[None, None, :]
+
+    def site(v):               # D_ee or D_oo on a vector (site-local)
+        return (d0 + 1j * mus * g5) * v
+
+    def site_inv(v):
+        return v / (d0 + 1j * mus * g5)
+
+    def hops(v):               # the hop part of D_BB (in-block hops only)
+        return level.apply_block_diag(v, mus.reshape(-1), blocking) - site(v)
+
+    r_e, r_o = r * even, r * odd
+    rhs = r_o - odd * hops(site_inv(r_e))
+
+    def schur(v):
+        return odd * (site(v) - hops(site_inv(even * hops(v))))
+
+    x_o = np.zeros_like(r)
+    rho = rhs.copy()
+    for _ in range(iters):
+        q = schur(rho)
+        num = _dot_block(blocking, q, rho)
+        den = _dot_block(blocking, q, q).real
+        alpha = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+        a = blocking.per_site(alpha)[:, :, None]
+        x_o = x_o + a * rho
+        rho = rho - a * q
+    x_e = even * site_inv(r_e - even * hops(x_o))
+    return x_o + x_e
+
+
+def sap(level, blocking: Blocking, f, mus, cycles, mr_iters, x0=None, oddeven=False):
     """Red-black Schwarz alternating procedure (paper section 2): for each
     colour in turn, the residual on that colour's blocks is reduced by an
-    approximate local inversion (block MR), all blocks of one colour at once."""
+    approximate local inversion (block MR, on the plain or the odd-even
+    reduced block systems), all blocks of one colour at once."""
     x = np.zeros_like(f) if x0 is None else x0.copy()
+    solve = block_mr_oddeven if oddeven else block_mr
     for _ in range(cycles):
         for colour in (0, 1):
             on = (blocking.colour_of_block[blocking.id] == colour).astype(np.float64)
             r = (f - level.apply(x, mus)) * on[None, :, None]
-            x = x + block_mr(level, blocking, r, mus, mr_iters)
+            x = x + solve(level, blocking, r, mus, mr_iters)
     return x
 
 

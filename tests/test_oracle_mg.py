@@ -7,7 +7,9 @@ by the mathematics:
 * coarse twist D_c(mu) - D_c(0) = i mu gamma5_c and coarse gamma5-hermiticity;
 * Galerkin projector: with an exact coarse solve R(r - D P D_c^-1 R r) = 0;
 * SAP with converged block solves == the dense two-colour Schwarz formula
-  x = K_r f, x += K_b (f - D x) with K = inverse of the block principal submatrix;
+  x = K_r f, x += K_b (f - D x) with K = inverse of the block principal submatrix,
+  for plain block MR and for MR on the odd-even reduced block systems, whose
+  back substitution leaves no residual on even sites;
 * GMRES / block GMRES at full dimension == dense LU;
 * the MG-preconditioned solve reaches the 1e-10 true residual and agrees with
   dense LU within cond * 1e-10.
@@ -212,3 +214,50 @@ def test_mg_solve_small_lattice_matches_dense_lu():
         xs = np.linalg.solve(D, b[c].reshape(-1))
         cond = np.linalg.cond(D)
         assert np.linalg.norm(x[c].reshape(-1) - xs) <= cond * 1e-10 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("dims,block", [((4, 4, 2, 2), (2, 2, 2, 2)), ((8, 4, 4, 4), (4, 4, 4, 4))])
+def test_oddeven_sap_equals_dense_schwarz(dims, block):
+    """SAP whose block solves run MR on the odd-even reduced (Schur complement)
+    systems converges to the same dense two-colour Schwarz formula."""
+    V = S.volume(dims)
+    U = S.gauge_field(dims, 0.3, 33)
+    op = O.WilsonTM(U, dims, kappa=0.1)
+    lev = FineLevel(op)
+    blk = Blocking(dims, block)
+    mu = 0.07
+    D = dense_of(lambda E: op.apply(E.reshape(-1, V, 4, 3), np.full(E.shape[0], mu)), V * 12, (V, 12))
+    f = S.gaussian_spinors(1, V, 34).reshape(1, V, 12)
+    x = O.sap(lev, blk, f, [mu], cycles=1, mr_iters=150, oddeven=True)
+    xd = np.zeros(V * 12, dtype=np.complex128)
+    fv = f.reshape(-1)
+    for colour in (0, 1):
+        r = fv - D @ xd
+        for b in np.nonzero(blk.colour_of_block == colour)[0]:
+            idx = (np.nonzero(blk.id == b)[0][:, None] * 12 + np.arange(12)).reshape(-1)
+            xd[idx] += np.linalg.solve(D[np.ix_(idx, idx)], r[idx])
+    assert np.max(np.abs(x.reshape(-1) - xd)) < 1e-10 * np.max(np.abs(xd))
+
+
+def test_oddeven_block_solve_back_substitution():
+    """After any number of odd-even MR steps the even sites of every block
+    satisfy their equations exactly: (r - D_BB x)_e = 0, and the odd-site
+    residual equals r_o - D_oe D_ee^-1 r_e - S x_o (checked against the
+    block operator itself)."""
+    dims, block = (8, 4, 4, 4), (4, 4, 4, 4)
+    V = S.volume(dims)
+    op = O.WilsonTM(S.gauge_field(dims, 0.3, 35), dims, kappa=0.15)
+    lev = FineLevel(op)
+    blk = Blocking(dims, block)
+    mus = np.array([0.01, 0.3])
+    r = S.gaussian_spinors(2, V, 36).reshape(2, V, 12)
+    even = (1 - O.multigrid.site_parity(dims))[None, :, None]
+    for iters in (1, 3):
+        x = O.block_mr_oddeven(lev, blk, r, mus, iters)
+        res = r - lev.apply_block_diag(x, mus, blk)
+        assert np.max(np.abs(res * even)) < 1e-13 * np.max(np.abs(r))
+        assert np.max(np.abs(res * (1 - even))) > 1e-3      # the odd half is only approximate
+    # more steps: the odd residual falls (MR minimises it step by step)
+    n1 = np.linalg.norm(r - lev.apply_block_diag(O.block_mr_oddeven(lev, blk, r, mus, 2), mus, blk))
+    n2 = np.linalg.norm(r - lev.apply_block_diag(O.block_mr_oddeven(lev, blk, r, mus, 6), mus, blk))
+    assert n2 < n1
