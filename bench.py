@@ -35,11 +35,15 @@ WORKLOAD = "tm_16x16x16x32_12rhs_4shift"
 # aggregation hierarchy does not reduce the outer iteration count there.
 SOLVER = dict(n_levels=1, sap_cycles=1, sap_mr_iters=12, outer_restart=40, max_outer=3000)
 # The tuned form: FP64 FGMRES(4) whose every step is an FP32 inner FGMRES of
-# up to 40 steps (to 1e-2, Arnoldi basis stored in FP16) around FP32 SAP with
-# 10 MR steps per block (the measured optimum under the inner FGMRES); the
-# outer FP64 iteration wins the accuracy back, and its restart every 4 steps
-# lets converged columns leave the batch.
-TUNED = dict(SOLVER, outer_restart=4, inner_iters=40, inner_tol=1e-2, inner_fp16=1, sap_mr_iters=10)
+# up to 40 steps (to 1e-2, Arnoldi basis stored in FP16) around FP32 SAP whose
+# block solves take 4 MR steps on the odd-even reduced block systems (the
+# measured optimum: as few FGMRES steps as 10 MR steps on the full blocks);
+# the outer FP64 iteration wins the accuracy back, and its restart every 4
+# steps lets converged columns leave the batch.
+TUNED = dict(SOLVER, outer_restart=4, inner_iters=40, inner_tol=1e-2, inner_fp16=1, sap_mr_iters=4, sap_oddeven=1)
+# the clover form: odd-even block solves are for the clover-free operator, so
+# its SAP takes 10 MR steps on the full blocks
+CLOVER_SOLVER = dict(TUNED, sap_oddeven=0, sap_mr_iters=10)
 
 
 def log(*a):
@@ -51,11 +55,20 @@ TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_half_fp32_16x16x16x32_48col
 # runs inside the inner Krylov solve, and the time_op form that launches it:
 # variants 2 (2-row links) and 3 (full links) read their right-hand side
 # straight from the FP16 Arnoldi basis (op 6; the profiler lists those
-# instantiations by their mangled names)
+# instantiations by their mangled names); with odd-even block solves one
+# kernel serves every variant, with full links for variant 3 only
 SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
                1: ("k_sap_half<float, 2, 2, 256, false, float, false>", 1),
                2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_Lb0EEE", 6),
                3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_Lb0EEE", 6)}
+SAP_OE_KERNELS = {False: ("_ZN5ddamg8k_sap_oeIfLi2EDF16_EE", 6), True: ("_ZN5ddamg8k_sap_oeIfLi1EDF16_EE", 6)}
+
+
+def sap_kernel(solver, variant):
+    """(kernel name, time_op form) of the SAP half sweep a solver runs."""
+    if solver.get("sap_oddeven"):
+        return SAP_OE_KERNELS[variant == 3]
+    return SAP_KERNELS[variant]
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
 # SAP calls timed for the roofline (after one untimed call)
 SAP_TIMED_CALLS = 10
@@ -83,6 +96,26 @@ def measured_traffic(kernel):
         return None
 
 
+def sap_oe_flops_per_half_sweep(V, ncol, mr):
+    """Algorithmic flops of one half sweep of SAP with odd-even reduced block
+    solves, averaged over the two half sweeps of a one-cycle call, counted per
+    pair of an even and an odd site of the active blocks (V / 4 pairs):
+
+    * each MR step applies the Schur complement: the in-block hops of the even
+      site (6 on average, 165 flop each), D_ee^-1 (72), the in-block hops of
+      the odd site, D_oo (72) and the hop sum (48); then the inner products
+      (144) and the two axpys (192) on the odd site: 2508;
+    * once: the right-hand side r_o - D_oe D_ee^-1 r_e and the back
+      substitution of x_e (6 hops, 48 and 72 each: 2220), and the block
+      residual (none in the first half sweep; the 2 block-leaving hops of each
+      of the two sites in the second: 660, counted once although the kernel
+      evaluates the even one twice)."""
+    hop = 1320 / 8
+    step = 12 * hop + 72 + 72 + 48 + 144 + 192
+    per_pair = mr * step + 2 * (6 * hop + 48 + 72) + 0.5 * (2 * 2 * hop)
+    return V / 4 * ncol * per_pair
+
+
 def sap_flops_per_half_sweep(V, ncol, mr, clover=False):
     """Algorithmic flops of one red-black SAP half sweep (half the sites),
     averaged over the two half sweeps of a one-cycle SAP call.
@@ -105,7 +138,7 @@ def sap_flops_per_half_sweep(V, ncol, mr, clover=False):
     return V / 2 * ncol * per_site
 
 
-def cpu_baseline(w, U, outer_iters, sap_mr):
+def cpu_baseline(w, U, outer_iters, sap_mr, oddeven=False):
     """The FP64 oracle on a bounded sample of the same workload: one column of
     the 16^3x32 problem, one oracle application of each operation of an outer
     iteration (fine operator, one-cycle SAP, 20-vector Gram-Schmidt step),
@@ -118,10 +151,10 @@ def cpu_baseline(w, U, outer_iters, sap_mr):
     import synthetic as S
     from oracle.multigrid import Blocking, FineLevel
     with threadpool_limits(limits=1):
-        return _cpu_baseline(w, U, outer_iters, sap_mr, np, O, S, Blocking, FineLevel)
+        return _cpu_baseline(w, U, outer_iters, sap_mr, oddeven, np, O, S, Blocking, FineLevel)
 
 
-def _cpu_baseline(w, U, outer_iters, sap_mr, np, O, S, Blocking, FineLevel):
+def _cpu_baseline(w, U, outer_iters, sap_mr, oddeven, np, O, S, Blocking, FineLevel):
     t_all = time.time()
     lev = FineLevel(O.WilsonTM(U, w.dims, kappa=w.kappa))
     V = w.volume
@@ -136,8 +169,8 @@ def _cpu_baseline(w, U, outer_iters, sap_mr, np, O, S, Blocking, FineLevel):
 
     t_fine = timed(lambda: lev.apply(x, mus))
     sb = Blocking(w.dims, w.sap_block)
-    t_s1 = timed(lambda: O.sap(lev, sb, x, mus, 1, 1))
-    t_s2 = timed(lambda: O.sap(lev, sb, x, mus, 1, 2))
+    t_s1 = timed(lambda: O.sap(lev, sb, x, mus, 1, 1, oddeven=oddeven))
+    t_s2 = timed(lambda: O.sap(lev, sb, x, mus, 1, 2, oddeven=oddeven))
     t_sap = t_s1 + (sap_mr - 1) * max(t_s2 - t_s1, 0.0)
     basis = [x * (k + 1) for k in range(20)]
 
@@ -152,7 +185,8 @@ def _cpu_baseline(w, U, outer_iters, sap_mr, np, O, S, Blocking, FineLevel):
     per_col = outer_iters * (t_fine + t_sap + t_gram)
     return dict(value=1.0 / per_col, unit="rhs*shift solves/s", cores=1, kind="oracle",
                 sample=(f"one column of {w.name}: one numpy-FP64 oracle application each of the fine operator "
-                        f"({t_fine:.2f}s), one-cycle SAP with {sap_mr} MR steps ({t_sap:.2f}s, from 1- and 2-step "
+                        f"({t_fine:.2f}s), one-cycle SAP with {sap_mr} MR steps{' (odd-even)' if oddeven else ''} "
+                        f"({t_sap:.2f}s, from 1- and 2-step "
                         f"timings {t_s1:.2f}s/{t_s2:.2f}s) and a 20-vector "
                         f"Gram-Schmidt step ({t_gram:.2f}s), times the {outer_iters} FGMRES iterations (outer + "
                         f"inner) the GPU solve needed; sampling took {time.time() - t_all:.0f}s"))
@@ -311,9 +345,10 @@ def main():
     # sweep) and of the fine stencil, timed with HIP events on the context stream
     n_iter = 10
     V = w.volume
-    sap_kernel, sap_op = SAP_KERNELS[tuned["tuned"]["sap_variant"]]
+    sap_name, sap_op = sap_kernel(TUNED, tuned["tuned"]["sap_variant"])
     t_sap = ctx.time_op(sap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0   # one call = two half sweeps
-    sap_flops = sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"])
+    sap_flops = (sap_oe_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"]) if TUNED.get("sap_oddeven")
+                 else sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"]))
     t_copy = ctx.time_op(5, 0, dd.FP64, ncol, 5)              # plain copy of one FP64 48-column vector
     copy_bytes = 2 * V * 12 * 16 * ncol
     t32 = ctx.time_op(0, 0, dd.FP32, ncol, n_iter)
@@ -346,17 +381,17 @@ def main():
     # of the fine stencil and of the FP16-input SAP half sweep (HIP events)
     clover = None
     if not args.no_clover:
-        cctx, cl = run_form(dd.MIXED, 1, 1, dict(TUNED, csw=CLOVER_CSW))
+        cctx, cl = run_form(dd.MIXED, 1, 1, dict(CLOVER_SOLVER, csw=CLOVER_CSW))
         log("clover form", cl)
         t32c = cctx.time_op(0, 0, dd.FP32, ncol, n_iter)
         t64c = cctx.time_op(0, 0, dd.FP64, ncol, n_iter)
-        csap_kernel, csap_op = SAP_KERNELS[cl["tuned"]["sap_variant"]]
+        _, csap_op = sap_kernel(CLOVER_SOLVER, cl["tuned"]["sap_variant"])
         tsc = cctx.time_op(csap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0
         cctx.close()
         links32c = 288 if cl["tuned"]["fp32_links"] == 0 else 192
         bytes32c = V * (links32c + 288 + ncol * 48 * 4)      # + the FP32 clover blocks
         bytes64c = V * (576 + 576 + ncol * 48 * 8)
-        csap_flops = sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"], clover=True)
+        csap_flops = sap_flops_per_half_sweep(V, ncol, CLOVER_SOLVER["sap_mr_iters"], clover=True)
         clover = {"csw": CLOVER_CSW, "solves_per_s": ncol / cl["elapsed"] if cl["allconv"] else 0.0,
                   "all_converged": cl["allconv"], "worst_true_rel_res": cl["worst"],
                   "outer_iters": cl["stats"]["outer_iters"], "inner_iters": cl["stats"]["n_inner_iters"],
@@ -374,7 +409,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle sample")
         cpu = cpu_baseline(w, U, tuned["stats"]["outer_iters"] + tuned["stats"]["n_inner_iters"],
-                           TUNED["sap_mr_iters"])
+                           TUNED["sap_mr_iters"], bool(TUNED.get("sap_oddeven")))
 
     sap_tf = sap_flops / t_sap / 1e12
     out = {
@@ -393,7 +428,7 @@ def main():
         "config": {"workload": w.name, "lattice": "16x16x16x32", "kappa": w.kappa, "n_rhs": w.n_rhs,
                    "shifts": list(w.mus), "columns": ncol, "tol": 1e-10,
                    "solver": "FP64 FGMRES(4) over FP32 FGMRES(40, to 1e-2, FP16 basis) over FP32 red-black "
-                             "SAP (4^4 blocks, 1 cycle, 10 MR steps)",
+                             "SAP (4^4 blocks, 1 cycle, 4 MR steps on the odd-even reduced blocks)",
                    "plain_solver": "FP64 FGMRES(40) over FP64 red-black SAP (4^4 blocks, 1 cycle, 12 MR steps)"},
         "all_converged": tuned["allconv"],
         "worst_true_rel_res": tuned["worst"],
@@ -409,9 +444,9 @@ def main():
                    "fp64_us": t64 * 1e6, "fp64_GBs": bytes64 / t64 / 1e9,
                    "fp64_GFLOPs": 1320 * V * ncol / t64 / 1e9,
                    "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": sap_kernel + " (FP32 red-black SAP half sweep, 48 columns)",
+        "roofline": {"kernel": sap_name + " (FP32 red-black SAP half sweep, 48 columns)",
                      "bound": "alu", "achieved": sap_tf, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": sap_tf / 157.3, "traffic": measured_traffic(sap_kernel),
+                     "frac": sap_tf / 157.3, "traffic": measured_traffic(sap_name),
                      "us_per_launch": t_sap * 1e6},
         "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
         "coarse_stencil_48col": coarse,

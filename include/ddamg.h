@@ -119,6 +119,8 @@ typedef struct ddamg_params {
   int    verbose;            /* 0 = silent                                                      */
   double csw;                /* clover coefficient c_sw of the site term c_sw (i/4) sum          */
                              /* sigma_{mu nu} F_{mu nu} (clover-leaf F); 0 = no clover term       */
+  int    sap_oddeven;        /* 1: SAP block solves run MR on the odd-even reduced block systems */
+                             /* (4^4 blocks, c_sw = 0); 0: MR on the full block systems         */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

@@ -70,6 +70,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
         ("csw", ctypes.c_double),
+        ("sap_oddeven", ctypes.c_int),
     ]
 
 

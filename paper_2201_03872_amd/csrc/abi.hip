@@ -98,6 +98,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->seed = 12345;
   p->verbose = 0;
   p->csw = 0.0;
+  p->sap_oddeven = 0;
 }
 
 static void validate(const ddamg_params* p) {
@@ -105,6 +106,10 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->n_levels >= 1 && p->n_levels <= 3, DDAMG_EINVAL, "n_levels must be 1, 2 or 3");
   DD_CHECK(p->kappa > 0, DDAMG_EINVAL, "kappa must be positive");
   DD_CHECK(std::isfinite(p->csw), DDAMG_EINVAL, "csw must be finite");
+  DD_CHECK(p->sap_oddeven == 0 || p->sap_oddeven == 1, DDAMG_EINVAL, "sap_oddeven must be 0 or 1");
+  DD_CHECK(!p->sap_oddeven || (p->csw == 0.0 && p->sap_block[0] == 4 && p->sap_block[1] == 4 &&
+                               p->sap_block[2] == 4 && p->sap_block[3] == 4),
+           DDAMG_EINVAL, "odd-even SAP needs 4^4 blocks and no clover term");
   DD_CHECK(p->col_tile == 0 || p->col_tile == 8, DDAMG_EINVAL, "col_tile must be 8");
   int dims[4];
   for (int m = 0; m < 4; ++m) {

@@ -711,6 +711,203 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? (CL ? 3 :
   }
 }
 
+// --------------------------------------------------- odd-even SAP ---
+// One colour half-sweep of red-black SAP whose block solves run MR on the
+// odd-even reduced block systems (4^4 blocks, no clover term).  Inside a
+// block every hop joins an even and an odd site, so with the site term
+// D_ee, D_oo = (4 + m0) + i mu gamma5 and the hop parts D_eo, D_oe of D_BB:
+//   S x_o = r_o - D_oe D_ee^{-1} r_e,   S = D_oo - D_oe D_ee^{-1} D_eo,
+//   x_e = D_ee^{-1} (r_e - D_eo x_o).
+// A workgroup of 128 lanes owns one block and one column; lane i owns the
+// i-th even and the i-th odd site of the block (local site 2i + b, with b
+// fixing the parity), so neither half of an MR step leaves lanes idle.  Per
+// step the even half gathers the odd in-block neighbours (D_eo, then
+// D_ee^{-1}) and the odd half the even ones (D_oe), both from LDS; one
+// reduction per column and block follows.  The first cycle of a call uses
+// that x is zero as the plain kernel does (x_zero 1 and 2).
+template <typename R, int LK, typename FIN = R>
+__global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FIN* __restrict__ f, R* __restrict__ x,
+                                                const void* __restrict__ U, const int* __restrict__ nbr,
+                                                const double* __restrict__ mu, const int* __restrict__ blist, int V,
+                                                int ntiles, size_t tile_reals, R diag, int mr_iters, int x_zero,
+                                                float fscale) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW, NCH = 24 / RW, BS = 256, NH = 128;
+  __shared__ C lodd[NCH * NH];    // odd-site vectors by parity index
+  __shared__ C leven[NCH * NH];   // even-site vectors
+  __shared__ R red[2][3];
+
+  int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = wg % TT;
+  wg /= TT;
+  const int tile = wg % ntiles;
+  const int bi = wg / ntiles;
+  const int i = threadIdx.x;
+  const int blk = blist[bi];
+  const int par = ((i >> 1) ^ (i >> 3) ^ (i >> 5)) & 1;   // parity of y + z + t of local sites 2i, 2i+1
+  const int se = blk * BS + 2 * i + par, so = blk * BS + 2 * i + (par ^ 1);
+  const FIN* ft = f + (size_t)tile * tile_reals;
+  R* xt = x + (size_t)tile * tile_reals;
+  const R m = (R)mu[tile * TT + t];
+  const R den = diag * diag + m * m;
+  const GlobalLinks<R, LK> gl{U, V};
+
+  // (diag + i mu gamma5) v and its inverse, in place
+  auto site_mul = [&](cx<R>(&v)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const R g = k < 6 ? m : -m;
+      v[k] = {diag * v[k].re - g * v[k].im, diag * v[k].im + g * v[k].re};
+    }
+  };
+  auto site_inv = [&](cx<R>(&v)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const R g = k < 6 ? -m : m;
+      v[k] = {(diag * v[k].re - g * v[k].im) / den, (diag * v[k].im + g * v[k].re) / den};
+    }
+  };
+  auto to_lds = [&](C* arr, const cx<R>(&v)[12]) {
+    if constexpr (RW == 2) {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) arr[k * NH + i] = C{v[k].re, v[k].im};
+    } else {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) arr[k * NH + i] = C{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+    }
+  };
+  auto from_lds = [&](const C* arr, int pi, cx<R>(&p)[12]) {
+    if constexpr (RW == 2) {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) { const C c = arr[k * NH + pi]; p[k] = {c.x, c.y}; }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) {
+        const C c = arr[k * NH + pi];
+        p[2 * k] = {c.x, c.y};
+        p[2 * k + 1] = {c.z, c.w};
+      }
+    }
+  };
+  // in-block neighbours from an LDS array of the other parity; hops that
+  // leave the block are dropped (Dirichlet block)
+  auto gather = [&](const C* arr, const int (&e8)[8], int s, cx<R>(&acc)[12]) {
+    auto ld = [&](int, int nb, cx<R>(&p)[12]) {
+      if (nb / BS != blk) return false;
+      from_lds(arr, (nb - blk * BS) >> 1, p);
+      return true;
+    };
+    all_hops_e<R, LK>(acc, gl, e8, s, ld);
+  };
+  // block residual at one site (as in the plain kernel)
+  auto residual = [&](int s, const int (&e8)[8], cx<R>(&r)[12]) {
+    if constexpr (std::is_same<FIN, R>::value) load_cx<R, 12>(ft, V, TT, s, t, r);
+    else load_cx_f16<12>(ft, V, TT, s, t, fscale, r);
+    if (x_zero == 1) return;
+    auto ldg = [&](int, int nb, cx<R>(&p)[12]) {
+      if (x_zero == 2 && nb / BS == blk) return false;
+      load_cx<R, 12>(xt, V, TT, nb, t, p);
+      return true;
+    };
+    cx<R> acc[12], xs[12], q[12];
+    all_hops_e<R, LK>(acc, gl, e8, s, ldg);
+    if (x_zero == 2) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) xs[k] = {0, 0};
+    } else {
+      load_cx<R, 12>(xt, V, TT, s, t, xs);
+    }
+    site_diag(q, xs, acc, diag, m);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r[k] = r[k] - q[k];
+  };
+
+  int ee[8], eo[8];
+  load_nbrs(nbr, V, se, ee);
+  load_nbrs(nbr, V, so, eo);
+  cx<R> rho[12], dl[12], q[12], acc[12];
+  residual(se, ee, q);
+  site_inv(q);                    // D_ee^{-1} r_e
+  to_lds(leven, q);
+  residual(so, eo, rho);
+  __syncthreads();
+  // right-hand side of the Schur system: r_o - D_oe D_ee^{-1} r_e (D_oe = -1/2 hops)
+  gather(leven, eo, so, acc);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    rho[k] = rho[k] + (R)0.5 * acc[k];
+    dl[k] = {0, 0};
+  }
+  const int lane = i % 64, wave = i / 64;
+  for (int it = 0; it < mr_iters; ++it) {
+    to_lds(lodd, rho);
+    __syncthreads();
+    // even half: u = D_ee^{-1} D_eo rho
+    gather(lodd, ee, se, acc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = (R)-0.5 * acc[k];
+    site_inv(q);
+    to_lds(leven, q);
+    __syncthreads();
+    // odd half: q = S rho = D_oo rho - D_oe u
+    gather(leven, eo, so, acc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = rho[k];
+    site_mul(q);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q[k] = q[k] + (R)0.5 * acc[k];
+    R nr = 0, ni = 0, dd = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      nr += q[k].re * rho[k].re + q[k].im * rho[k].im;
+      ni += q[k].re * rho[k].im - q[k].im * rho[k].re;
+      dd += q[k].re * q[k].re + q[k].im * q[k].im;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      nr += __shfl_xor(nr, off, 64);
+      ni += __shfl_xor(ni, off, 64);
+      dd += __shfl_xor(dd, off, 64);
+    }
+    if (lane == 0) { red[wave][0] = nr; red[wave][1] = ni; red[wave][2] = dd; }
+    __syncthreads();
+    nr = red[0][0] + red[1][0];
+    ni = red[0][1] + red[1][1];
+    dd = red[0][2] + red[1][2];
+    const cx<R> a = dd > 0 ? cx<R>{nr / dd, ni / dd} : cx<R>{0, 0};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      dl[k] = dl[k] + a * rho[k];
+      rho[k] = rho[k] - a * q[k];
+    }
+  }
+  // back substitution: x_e = D_ee^{-1} r_e - D_ee^{-1} D_eo x_o (the even
+  // residual is recomputed: x outside the block and on it is unchanged so far)
+  to_lds(lodd, dl);
+  __syncthreads();
+  cx<R> xe[12];
+  gather(lodd, ee, se, acc);
+  residual(se, ee, xe);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) xe[k] = xe[k] + (R)0.5 * acc[k];
+  site_inv(xe);
+  __syncthreads();                // every read of x on the block precedes the writes below
+  if (x_zero) {
+    store_cx<R, 12>(xt, V, TT, so, t, dl);
+    store_cx<R, 12>(xt, V, TT, se, t, xe);
+  } else {
+    cx<R> xs[12];
+    load_cx<R, 12>(xt, V, TT, so, t, xs);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) xs[k] = xs[k] + dl[k];
+    store_cx<R, 12>(xt, V, TT, so, t, xs);
+    load_cx<R, 12>(xt, V, TT, se, t, xs);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) xs[k] = xs[k] + xe[k];
+    store_cx<R, 12>(xt, V, TT, se, t, xs);
+  }
+}
+
 // ------------------------------------------------------------ wrappers ---
 static inline int nsb_of(int V) { return (V + SPW - 1) / SPW; }
 
@@ -972,6 +1169,38 @@ static void sap_clover(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
 
 // x is fully written by the first cycle (each site belongs to one block of
 // one colour), so it needs no clearing beforehand.
+template <typename R, int LK, typename FIN = R>
+static void launch_sap_oe(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
+  const int nb = c->n_sap[colour];
+  const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
+  hipLaunchKernelGGL((k_sap_oe<R, LK, FIN>), dim3(nb * x.ntiles * TT), dim3(128), 0, c->stream, f.as<FIN>(), x.as<R>(),
+                     U, c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(),
+                     (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
+  DD_HIP(hipGetLastError());
+}
+
+// SAP with odd-even reduced block solves (4^4 blocks; FP32 links full for
+// SAP variant 3, else 2-row)
+static void sap_oddeven(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu) {
+  DD_CHECK(c->geom[0].gsize == 256 && !c->d_clov64, DDAMG_EINVAL, "odd-even SAP needs 4^4 blocks and no clover term");
+  const bool full = c->sap_variant == 3;
+  for (int cyc = 0; cyc < c->p.sap_cycles; ++cyc)
+    for (int colour = 0; colour < 2; ++colour) {
+      const int xz = cyc == 0 ? 1 + colour : 0;
+      if (f.prec == P16) {
+        if (full) launch_sap_oe<float, LK_F, _Float16>(c, f, x, d_mu, colour, xz);
+        else launch_sap_oe<float, LK_C, _Float16>(c, f, x, d_mu, colour, xz);
+      } else if (x.prec == P64) {
+        launch_sap_oe<double, LK_D>(c, f, x, d_mu, colour, xz);
+      } else if (full) {
+        launch_sap_oe<float, LK_F>(c, f, x, d_mu, colour, xz);
+      } else {
+        launch_sap_oe<float, LK_C>(c, f, x, d_mu, colour, xz);
+      }
+    }
+  c->st.sap_calls++;
+}
+
 void build_clover(ddamg_ctx* c) {
   const int V = c->geom[0].V;
   c->d_clov64 = (double*)c->pool.alloc((size_t)V * CLOV_REALS * sizeof(double));
@@ -981,14 +1210,17 @@ void build_clover(ddamg_ctx* c) {
   DD_HIP(hipGetLastError());
 }
 
-bool sap_takes_f16(ddamg_ctx* c) { return c->geom[0].gsize == 256 && (c->sap_variant == 2 || c->sap_variant == 3); }
+bool sap_takes_f16(ddamg_ctx* c) {
+  return c->geom[0].gsize == 256 && (c->p.sap_oddeven || c->sap_variant == 2 || c->sap_variant == 3);
+}
 
 void sap_apply(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, const MV&) {
   const int BS = c->geom[0].gsize;
-  if (c->d_clov64) {
+  if (c->d_clov64 || c->p.sap_oddeven) {
     DD_CHECK(f.prec != P16 || (x.prec == P32 && sap_takes_f16(c)), DDAMG_EINVAL,
              "SAP: FP16 input needs the FP32 one-column variant");
-    sap_clover(c, f, x, d_mu);
+    if (c->p.sap_oddeven) sap_oddeven(c, f, x, d_mu);
+    else sap_clover(c, f, x, d_mu);
     return;
   }
   if (f.prec == P16) {   // right-hand sides read straight from an FP16 Krylov basis

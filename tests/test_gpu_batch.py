@@ -132,8 +132,9 @@ def test_single_column_and_argument_checks(torch_cuda, dd):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision,fp16", [("MIXED", 0), ("MIXED", 1), ("PLAIN_FP64", 0)])
-def test_inner_fgmres_refinement(torch_cuda, dd, precision, fp16):
+@pytest.mark.parametrize("precision,fp16,oddeven", [("MIXED", 0, 0), ("MIXED", 1, 0), ("PLAIN_FP64", 0, 0),
+                                                     ("MIXED", 1, 1), ("PLAIN_FP64", 0, 1)])
+def test_inner_fgmres_refinement(torch_cuda, dd, precision, fp16, oddeven):
     """Outer FP64 FGMRES preconditioned by an inner FGMRES (FP32 in the mixed
     form, optionally with its Arnoldi basis stored in FP16) around SAP: every
     column reaches the FP64 oracle residual 1e-10 within a few outer steps."""
@@ -142,13 +143,14 @@ def test_inner_fgmres_refinement(torch_cuda, dd, precision, fp16):
     U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
     mus = np.array(w.mus)
     b = torch.from_numpy(S.rhs_for(w)).cuda()
-    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block, sap_cycles=1,
-                          sap_mr_iters=8, outer_restart=10, max_outer=200, inner_iters=30, inner_tol=1e-2,
-                          inner_fp16=fp16, precision=getattr(dd, precision))
+    blk = (4, 4, 4, 4) if oddeven else w.sap_block      # odd-even block solves need 4^4 blocks
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=blk, sap_cycles=1, outer_restart=10, max_outer=200, inner_iters=30, inner_tol=1e-2,
+                          inner_fp16=fp16, precision=getattr(dd, precision), sap_oddeven=oddeven)
     ctx = dd.Context(p, U)
     x, info, st = ctx.solve(mus, b)
     s = ctx.stats()
-    say(f"inner FGMRES ({precision}, FP16 basis {fp16}): outer {s['outer_iters']}, inner {s['n_inner_iters']}")
+    say(f"inner FGMRES ({precision}, FP16 basis {fp16}, odd-even SAP {oddeven}): outer {s['outer_iters']}, "
+        f"inner {s['n_inner_iters']}")
     op = O.WilsonTM(U, w.dims, kappa=w.kappa)
     check_batch(op, [(mus, S.rhs_for(w))], [x], [info])
     assert st == dd.OK and s["n_inner_iters"] > s["outer_iters"] and s["outer_iters"] <= 20

@@ -506,3 +506,45 @@ def test_captured_gmres_steps_match_host_path(torch_cuda, dd):
             assert np.all(rel <= (1.5 * tol if prec == dd.FP64 else 1e-2))
     for ctx in ctxs:
         ctx.close()
+
+
+def test_sap_oddeven_parity(torch_cuda, dd):
+    """SAP with odd-even reduced block solves (4^4 blocks): FP64 against the
+    oracle's odd-even SAP (1e-12), FP32 with both link formats and with
+    FP16-stored right-hand sides (1e-4)."""
+    torch = torch_cuda
+    dims, blk = (8, 8, 4, 8), (4, 4, 4, 4)
+    say("odd-even SAP", dims, blk)
+    ctx, U = ctx_for(dd, dims, 0.15, blk, sap_cycles=2, sap_mr_iters=3, sap_oddeven=1)
+    V = S.volume(dims)
+    ncol = 11
+    f = S.gaussian_spinors(ncol, V, 81)
+    mus = np.linspace(0.001, 0.2, ncol)
+    lev = FineLevel(O.WilsonTM(U, dims, kappa=0.15))
+    ref = O.sap(lev, Blocking(dims, blk), f.reshape(ncol, V, 12), mus, 2, 3, oddeven=True).reshape(ncol, V, 4, 3)
+    plain = O.sap(lev, Blocking(dims, blk), f.reshape(ncol, V, 12), mus, 2, 3).reshape(ncol, V, 4, 3)
+    assert np.max(relerr_cols(plain, ref)) > 1e-2          # a different block solver
+    fg = torch.from_numpy(f).cuda()
+    e64 = np.max(relerr_cols(ctx.apply_sap(dd.FP64, mus, fg).cpu().numpy(), ref))
+    say("  fp64", e64)
+    assert e64 < 1e-12
+    hs = np.sqrt(12 * V) / 16
+
+    def r16(a):
+        return (a * hs).astype(np.float16).astype(np.float64) / hs
+    f16 = r16(f.real) + 1j * r16(f.imag)
+    ref16 = O.sap(lev, Blocking(dims, blk), f16.reshape(ncol, V, 12), mus, 2, 3, oddeven=True).reshape(ncol, V, 4, 3)
+    for variant in (2, 3):
+        ctx.set_tuning("sap_variant", variant)
+        e32 = np.max(relerr_cols(ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy(), ref))
+        e16 = np.max(relerr_cols(ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy(), ref16))
+        say("  variant", variant, "fp32", e32, "fp16 input", e16)
+        assert e32 < 1e-4 and e16 < 1e-4
+    ctx.close()
+    # 2^4 blocks, or a clover term, are rejected on the host
+    with pytest.raises(dd.DDAMGError) as ei:
+        ctx_for(dd, dims, 0.15, (2, 2, 2, 2), sap_oddeven=1)
+    assert ei.value.code == dd.EINVAL
+    with pytest.raises(dd.DDAMGError) as ei:
+        ctx_for(dd, dims, 0.15, blk, sap_oddeven=1, csw=1.0)
+    assert ei.value.code == dd.EINVAL
