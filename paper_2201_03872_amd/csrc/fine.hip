@@ -829,6 +829,10 @@ __global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FI
   residual(se, ee, q);
   site_inv(q);                    // D_ee^{-1} r_e
   to_lds(leven, q);
+  // second half sweep of the first cycle: x is zero on the block, so
+  // D_ee^{-1} r_e waits where x_e goes for the back substitution (its block-
+  // leaving hops are not gathered twice)
+  if (x_zero == 2) store_cx<R, 12>(xt, V, TT, se, t, q);
   residual(so, eo, rho);
   __syncthreads();
   // right-hand side of the Schur system: r_o - D_oe D_ee^{-1} r_e (D_oe = -1/2 hops)
@@ -882,16 +886,25 @@ __global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FI
     }
   }
   // back substitution: x_e = D_ee^{-1} r_e - D_ee^{-1} D_eo x_o (the even
-  // residual is recomputed: x outside the block and on it is unchanged so far)
+  // residual is recomputed unless it was kept: x is unchanged so far)
   to_lds(lodd, dl);
   __syncthreads();
   cx<R> xe[12];
   gather(lodd, ee, se, acc);
-  residual(se, ee, xe);
+  if (x_zero == 2) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) xe[k] = xe[k] + (R)0.5 * acc[k];
-  site_inv(xe);
-  __syncthreads();                // every read of x on the block precedes the writes below
+    for (int k = 0; k < 12; ++k) q[k] = (R)0.5 * acc[k];
+    site_inv(q);
+    load_cx<R, 12>(xt, V, TT, se, t, xe);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) xe[k] = xe[k] + q[k];
+  } else {
+    residual(se, ee, xe);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) xe[k] = xe[k] + (R)0.5 * acc[k];
+    site_inv(xe);
+    if (x_zero == 0) __syncthreads();   // every read of x on the block precedes the writes below
+  }
   if (x_zero) {
     store_cx<R, 12>(xt, V, TT, so, t, dl);
     store_cx<R, 12>(xt, V, TT, se, t, xe);
@@ -1173,9 +1186,9 @@ template <typename R, int LK, typename FIN = R>
 static void launch_sap_oe(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
   const int nb = c->n_sap[colour];
   const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
-  hipLaunchKernelGGL((k_sap_oe<R, LK, FIN>), dim3(nb * x.ntiles * TT), dim3(128), 0, c->stream, f.as<FIN>(), x.as<R>(),
-                     U, c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(),
-                     (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
+  hipLaunchKernelGGL((k_sap_oe<R, LK, FIN>), dim3(nb * x.ntiles * TT), dim3(128), 0, c->stream, f.as<FIN>(),
+                     x.as<R>(), U, c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles,
+                     x.tile_reals(), (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
   DD_HIP(hipGetLastError());
 }
 
