@@ -50,7 +50,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_half_fp32_16x16x16x32_48col.md")
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_oe_fp32_16x16x16x32_48col.md")
 # the FP32 SAP half-sweep kernel of each autotuner variant (4^4 blocks) as it
 # runs inside the inner Krylov solve, and the time_op form that launches it:
 # variants 2 (2-row links) and 3 (full links) read their right-hand side
