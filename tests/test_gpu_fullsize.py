@@ -1,5 +1,6 @@
-"""GPU parity at the full sizes of the 32^3x64 batching workload and the
-40^3x80 large-volume workload, through the C ABI.
+"""GPU parity at the full sizes of the 32^3x64 batching workload, the
+40^3x80 large-volume workload and (for the tuned path's smoother) the 16^3x32
+bench workload, through the C ABI.
 
 The oracle cannot apply the operator to whole fields of this size column by
 column in test time, so it is evaluated site by site on sampled sites (its
@@ -15,6 +16,7 @@ import pytest
 
 import synthetic as S
 import oracle as O
+from oracle.multigrid import Blocking, FineLevel
 
 pytestmark = pytest.mark.gpu
 
@@ -74,8 +76,10 @@ def test_batched_workload_full_size(torch_cuda, dd):
     say("32^3x64: generating the gauge field")
     U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
     op = O.WilsonTM(U, w.dims, kappa=w.kappa)
-    p = dd.params_for_workload(w, n_levels=1, sap_cycles=1, sap_mr_iters=10, outer_restart=12, max_outer=3000,
-                               inner_iters=40, inner_tol=1e-2, inner_fp16=1, precision=dd.MIXED)
+    # the bench's tuned solver: FP64 FGMRES(4) over FP32 FGMRES(40, FP16 basis)
+    # over SAP with 4 MR steps on the odd-even reduced blocks
+    p = dd.params_for_workload(w, n_levels=1, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, outer_restart=4,
+                               max_outer=3000, inner_iters=40, inner_tol=1e-2, inner_fp16=1, precision=dd.MIXED)
     ctx = dd.Context(p, U)
     operator_checks(torch, dd, ctx, op, w.dims, np.array([1e-3, 0.02, 0.3, 1.0]))
     # a small uneven batch of the workload's systems (1 rhs x 2 shifts, 1 rhs x 1 shift)
@@ -109,4 +113,30 @@ def test_large_volume_operator_full_size(torch_cuda, dd):
     op = O.WilsonTM(U, w.dims, kappa=w.kappa)
     ctx = dd.Context(dd.params_for_workload(w, n_levels=1, precision=dd.MIXED), U)
     operator_checks(torch, dd, ctx, op, w.dims, np.array([w.mus[0], w.mus[-1]]))
+    ctx.close()
+
+
+def test_oddeven_sap_bench_lattice(torch_cuda, dd):
+    """The tuned path's smoother at the bench's full size (16^3x32, 4^4
+    blocks): FP64 odd-even SAP against the oracle on two columns, and the
+    FP32 form with FP16-stored right-hand sides (as the inner solve runs it)
+    on the same columns."""
+    torch = torch_cuda
+    w = S.workload("tm_16x16x16x32_12rhs_4shift")
+    say("16^3x32 odd-even SAP")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    V = S.volume(w.dims)
+    ctx = dd.Context(dd.params_for_workload(w, n_levels=1, sap_cycles=1, sap_mr_iters=2, sap_oddeven=1), U)
+    f = S.gaussian_spinors(2, V, 611)
+    mus = np.array([0.002, 0.1])
+    lev = FineLevel(O.WilsonTM(U, w.dims, kappa=w.kappa))
+    ref = O.sap(lev, Blocking(w.dims, (4, 4, 4, 4)), f.reshape(2, V, 12), mus, 1, 2, oddeven=True).reshape(2, V, 4, 3)
+    fg = torch.from_numpy(f).cuda()
+    x64 = ctx.apply_sap(dd.FP64, mus, fg).cpu().numpy()
+    rel = lambda a: np.max(np.linalg.norm((a - ref).reshape(2, -1), axis=1) / np.linalg.norm(ref.reshape(2, -1), axis=1))
+    say(f"  fp64 {rel(x64):.2e}")
+    assert rel(x64) < 1e-12
+    x16 = ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy()
+    say(f"  fp32 with FP16 right-hand sides {rel(x16):.2e}")
+    assert rel(x16) < 2e-3          # FP16 storage of f: 2^-11 relative per entry
     ctx.close()
