@@ -587,12 +587,13 @@ __global__ void __launch_bounds__(64) k_multidot2(const double* __restrict__ par
 // basis vectors per workgroup of the FP16 kernel
 constexpr int KH_MAX = 16;
 
-// workgroups along the vector length of the first reduction stage
+// workgroups along the vector length of the first reduction stage (about
+// 4096 in all, 8192 for the FP16 kernel, whose lanes finish a row sooner)
 static int multidot_nbm(const MV& w, int k, bool half) {
   const size_t M = (size_t)w.nchunk * w.nsites;
   const int kb = half ? KH_MAX : KB;
   const int ngroups = (k + kb - 1) / kb;
-  int nbM = (int)std::min<size_t>((M + 31) / 32, 4096 / ((size_t)w.ntiles * ngroups) + 1);
+  int nbM = (int)std::min<size_t>((M + 31) / 32, (half ? 8192 : 4096) / ((size_t)w.ntiles * ngroups) + 1);
   return nbM < 1 ? 1 : nbM;
 }
 
