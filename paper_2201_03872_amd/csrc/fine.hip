@@ -400,37 +400,8 @@ __global__ void __launch_bounds__(128) k_clover_build(const double* __restrict__
 }
 
 // ------------------------------------------------------------ dslash ---
-// MODE 0: y = D x ; MODE 1: y = b - D x
-template <typename R, int LK, int MODE>
-__global__ void __launch_bounds__(256) k_dslash(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ b,
-                                                const void* __restrict__ U, const int* __restrict__ nbr,
-                                                const double* __restrict__ mu, int V, size_t tile_reals, R diag,
-                                                int nsb) {
-  const int t = threadIdx.x % TT, sl = threadIdx.x / TT;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = wg / nsb;
-  const int s = (wg % nsb) * SPW + sl;
-  if (s >= V) return;
-  const R* xt = x + (size_t)tile * tile_reals;
-  auto ld = [&](int, int nb, cx<R>(&p)[12]) {
-    load_cx<R, 12>(xt, V, TT, nb, t, p);
-    return true;
-  };
-  cx<R> acc[12];
-  all_hops<R, LK>(acc, U, nbr, V, s, ld);
-  cx<R> xs[12], out[12];
-  load_cx<R, 12>(xt, V, TT, s, t, xs);
-  site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
-  if constexpr (MODE == 1) {
-    cx<R> bs[12];
-    load_cx<R, 12>(b + (size_t)tile * tile_reals, V, TT, s, t, bs);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) out[k] = bs[k] - out[k];
-  }
-  store_cx<R, 12>(y + (size_t)tile * tile_reals, V, TT, s, t, out);
-}
-
-// Same operator with LDS staging: a workgroup owns RS consecutive sites of the
+// The fine stencil, MODE 0: y = D x ; MODE 1: y = b - D x.
+// With LDS staging: a workgroup owns RS consecutive sites of the
 // internal (block-major) order for one column tile, copies their spinors
 // into LDS once, and reads every neighbour that falls inside its range from
 // LDS; only the neighbours outside the range go through L1/L2.  A site's
