@@ -56,18 +56,18 @@ TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_oe_fp32_16x16x16x32_48col.m
 # variants 2 (2-row links) and 3 (full links) read their right-hand side
 # straight from the FP16 Arnoldi basis (op 6; the profiler lists those
 # instantiations by their mangled names); with odd-even block solves one
-# kernel serves every variant, with full links for variant 3 only
+# kernel (2-row links) serves every variant
 SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
                1: ("k_sap_half<float, 2, 2, 256, false, float, false>", 1),
                2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_Lb0EEE", 6),
                3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_Lb0EEE", 6)}
-SAP_OE_KERNELS = {False: ("_ZN5ddamg8k_sap_oeIfLi2EDF16_EE", 6), True: ("_ZN5ddamg8k_sap_oeIfLi1EDF16_EE", 6)}
+SAP_OE_KERNEL = ("_ZN5ddamg8k_sap_oeIfLi2EDF16_EE", 6)
 
 
 def sap_kernel(solver, variant):
     """(kernel name, time_op form) of the SAP half sweep a solver runs."""
     if solver.get("sap_oddeven"):
-        return SAP_OE_KERNELS[variant == 3]
+        return SAP_OE_KERNEL
     return SAP_KERNELS[variant]
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
 # SAP calls timed for the roofline (after one untimed call)

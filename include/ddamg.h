@@ -258,7 +258,8 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             read through L1/L2; 2 one column, 2-row links through
                                             L1/L2 (less LDS per workgroup, more workgroups per CU);
                                             3 one column, full 3x3 links through L1/L2 (no third-row
-                                            rebuild in the MR steps, 1.5x the link bytes) */
+                                            rebuild in the MR steps, 1.5x the link bytes).  The
+                                            odd-even form (sap_oddeven) has one kernel, 2-row links */
 #define DDAMG_KNOB_DSLASH_ORDER      5   /* fine stencil scheme: 0 (default) site ranges staged in LDS,
                                             storage order; 1 the same in time-slice order; 2 / 3
                                             t-walk over columns of 4^4 blocks (psi(t-1..t+1) in
