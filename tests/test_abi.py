@@ -74,3 +74,22 @@ def test_default_params_are_the_papers_tolerances():
     assert p.tol == 1e-10
     assert abs(p.r_m - 7e-2) < 1e-15 and abs(p.r_b - 1e-1) < 1e-15
     assert p.coarse_mu_factor == 1.0
+
+
+@pytest.mark.parametrize("kw,reason", [
+    (dict(sap_oddeven=1, sap_block=(2, 2, 2, 2)), "odd-even SAP"),
+    (dict(sap_oddeven=1, csw=1.0), "odd-even SAP"),
+    (dict(sap_oddeven=2), "sap_oddeven"),
+    (dict(csw=float("nan")), "csw"),
+])
+def test_setup_rejects_bad_parameters_on_the_host(kw, reason):
+    """Parameter validation is host logic: ddamg_setup returns DDAMG_EINVAL
+    with a message before it touches the device."""
+    lib = dd.load()
+    p = dd.default_params(**dict(dict(dims=(8, 8, 8, 8), kappa=0.15, n_levels=1, sap_block=(4, 4, 4, 4)), **kw))
+    gauge = (ctypes.c_double * 8)()
+    h = ctypes.c_void_p()
+    st = lib.ddamg_setup(ctypes.byref(p), gauge, 0, None, None, ctypes.byref(h))
+    assert st == dd.EINVAL
+    assert reason in lib.ddamg_last_error().decode()
+    assert not h.value

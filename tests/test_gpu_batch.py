@@ -155,3 +155,24 @@ def test_inner_fgmres_refinement(torch_cuda, dd, precision, fp16, oddeven):
     check_batch(op, [(mus, S.rhs_for(w))], [x], [info])
     assert st == dd.OK and s["n_inner_iters"] > s["outer_iters"] and s["outer_iters"] <= 20
     ctx.close()
+
+
+def test_two_level_solve_with_oddeven_smoother(torch_cuda, dd):
+    """The odd-even SAP as the fine smoother of the two-level K-cycle (4^4 SAP
+    blocks = aggregates): every column reaches the oracle's FP64 residual."""
+    torch = torch_cuda
+    dims = (8, 8, 8, 8)
+    U = S.gauge_field(dims, 0.3, 221)
+    V = S.volume(dims)
+    mus = np.array([0.005, 0.05])
+    b = S.gaussian_spinors(2, V, 222)
+    p = dd.default_params(dims=dims, kappa=0.14, n_levels=2, sap_block=(4, 4, 4, 4), agg=[(4, 4, 4, 4), (2, 2, 2, 2)],
+                          n_tv=[16, 8], setup_rounds=2, sap_cycles=2, sap_mr_iters=3, sap_oddeven=1,
+                          precision=dd.MIXED, max_outer=300)
+    ctx = dd.Context(p, U)
+    x, info, st = ctx.solve(mus, torch.from_numpy(b).cuda())
+    s = ctx.stats()
+    say(f"two-level, odd-even SAP: status {st}, outer {s['outer_iters']}, bottom solves {s['n_bottom_solves']}")
+    check_batch(O.WilsonTM(U, dims, kappa=0.14), [(mus, b)], [x], [info])
+    assert st == dd.OK and s["n_bottom_solves"] > 0
+    ctx.close()
