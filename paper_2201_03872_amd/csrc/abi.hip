@@ -354,18 +354,27 @@ int ddamg_set_test_vectors(ddamg_ctx* c, int level, const double* tv) {
 // solutions and the smoother's temporaries.
 static int active_columns(ddamg_ctx* c, int ncol) {
   if (c->p.max_active_cols > 0) return std::min(ncol, c->p.max_active_cols);
+  // fine-level vectors per column, in units of one FP64 vector (ps: size of
+  // the preconditioner precision, vs: of the inner basis):
+  //   outer FGMRES: b and x ping-pong (4), basis V (m + 1), residual (1), Z (m);
+  //   mixed: the FP32 input of the preconditioner and the FP64 copy of z (1 + ps);
+  //   inner FGMRES: basis V (mi + 1), Z (mi), residual, and the FP32 forms of
+  //   new and FP16-read vectors (up to 3).
   const double col64 = (double)c->geom[0].V * 12 * 16;
   const int m = std::min(c->p.outer_restart, 63);
   const bool mixed = c->p.precision == DDAMG_MIXED;
-  const double zfac = mixed ? 0.5 : 1.0;
+  const double ps = mixed ? 0.5 : 1.0;
   const int mi = std::min(c->p.inner_iters, 63);
-  const double vfac = mixed && c->p.inner_fp16 ? 0.25 : (mixed ? 0.5 : 1.0);   // inner basis V
-  const double per_col = col64 * ((m + 1) + 6 + zfac * (m + 8) + (mi > 0 ? vfac * (mi + 1) + zfac * (mi + 2) : 0.0));
-  // workspaces come in tiles of T columns: count whole tiles
+  const bool half = mixed && c->p.inner_fp16;
+  const double vs = half ? 0.25 : ps;
+  const double per_col = col64 * (6 + m + m * ps + (mixed ? 1 + ps : 0.0) +
+                                   (mi > 0 ? (mi + 1) * vs + (mi + 1 + (half ? 2 : 0)) * ps : 0.0));
+  // workspaces come in tiles of T columns: count whole tiles, with a 10%
+  // margin for the hierarchy's coarse levels and small buffers
   const double per_tile = per_col * c->T;
   size_t fre = 0, tot = 0;
   DD_HIP(hipMemGetInfo(&fre, &tot));
-  const int tiles = (int)(0.85 * (double)fre / per_tile);
+  const int tiles = (int)(0.9 * (double)fre / per_tile);
   DD_CHECK(tiles >= 1, DDAMG_ENOMEM,
            "device memory holds less than one tile of Krylov workspace: lower outer_restart / inner_iters");
   return std::min(ncol, tiles * c->T);
