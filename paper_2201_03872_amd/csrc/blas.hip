@@ -756,6 +756,61 @@ __global__ void __launch_bounds__(256) k_multiaxpy_norm(PtrPack Vs, int k, const
   }
 }
 
+// The FP16-basis form that writes the next basis vector directly: the basis
+// vectors V_j are stored unnormalised (entry scale c_j per column), so the
+// coefficients are h'_j / c_j^2 with h'_j the dots with the stored vectors;
+// w' = w - sum_j h_j v_j is formed in FP32 and stored as w' * osc[col] in FP16
+// (osc: hscale over a norm estimate), with |w'|^2 per column as above.
+__global__ void __launch_bounds__(256) k_multiaxpy_norm_h(PtrPack Vs, int k, const double* __restrict__ coef,
+                                                          const double* __restrict__ cinv2,
+                                                          const float* __restrict__ w, _Float16* __restrict__ out,
+                                                          const double* __restrict__ osc, int T, size_t tile_units,
+                                                          int ncol, double scale, double* __restrict__ part) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  __shared__ float cf[MAXK][TTB][2];
+  __shared__ double red[4][TTB];
+  const int tile = blockIdx.y;
+  for (int i = threadIdx.x; i < k * T; i += blockDim.x) {
+    const int j = i / T, tt = i % T;
+    const size_t ji = (size_t)j * ncol + tile * T + tt;
+    const double f = scale * cinv2[ji];
+    cf[j][tt][0] = (float)(coef[2 * ji] * f);
+    cf[j][tt][1] = (float)(coef[2 * ji + 1] * f);
+  }
+  __syncthreads();
+  const int t = threadIdx.x % T;
+  const float os = (float)osc[tile * T + t];
+  const size_t base = (size_t)tile * tile_units;
+  double n2 = 0;
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < tile_units; u += (size_t)gridDim.x * blockDim.x) {
+    float acc[4] = {0, 0, 0, 0};
+    for (int j = 0; j < k; ++j) {
+      const h4 v = reinterpret_cast<const h4*>(Vs.p[j])[base + u];
+      const float cr = cf[j][t][0], ci = cf[j][t][1];
+      const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z, v3 = (float)v.w;
+      acc[0] += cr * v0 - ci * v1;
+      acc[1] += cr * v1 + ci * v0;
+      acc[2] += cr * v2 - ci * v3;
+      acc[3] += cr * v3 + ci * v2;
+    }
+    const float4 wv = reinterpret_cast<const float4*>(w)[base + u];
+    const float o0 = wv.x + acc[0], o1 = wv.y + acc[1], o2 = wv.z + acc[2], o3 = wv.w + acc[3];
+    n2 += (double)o0 * o0 + (double)o1 * o1 + (double)o2 * o2 + (double)o3 * o3;
+    reinterpret_cast<h4*>(out)[base + u] = h4{(_Float16)(o0 * os), (_Float16)(o1 * os), (_Float16)(o2 * os),
+                                              (_Float16)(o3 * os)};
+  }
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  for (int off = T; off < 64; off <<= 1) n2 += __shfl_xor(n2, off, 64);
+  if (lane < T) red[wave][lane] = n2;
+  __syncthreads();
+  if (threadIdx.x < T) {
+    double a = 0;
+#pragma unroll
+    for (int w4 = 0; w4 < 4; ++w4) a += red[w4][threadIdx.x];
+    part[(size_t)blockIdx.x * ncol + tile * T + threadIdx.x] = a;
+  }
+}
+
 // out[i] = sum over q < nb of part[q][i] (one wavefront per column, fixed tree)
 __global__ void __launch_bounds__(64) k_sum_rows(const double* __restrict__ part, double* __restrict__ out, int nb,
                                                  int ncol) {
@@ -860,6 +915,30 @@ void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef,
   else
     hipLaunchKernelGGL((k_multiaxpy_norm<float, float, 4, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
                        w.as<float>(), w.T, tile_units, ncol, (double)sign, part);
+  DD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncol), dim3(64), 0, c->stream, part, d_n2, nb, ncol);
+  DD_HIP(hipGetLastError());
+}
+
+// w' = w - sum_j (coef_j / c_j^2) V_j for an FP16 basis stored unnormalised
+// (d_cinv2[j][col] = 1 / c_j^2), written into the FP16 vector `out` as
+// w' * d_osc[col] (in units of out.hscale), and d_n2[col] = |w'|^2
+void mv_multiaxpy_norm2_into_f16(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const double* d_cinv2,
+                                 const MV& w, const MV& out, const double* d_osc, double* d_n2) {
+  DD_CHECK(k >= 1 && k <= MAXK && w.prec == P32 && out.prec == P16 && w.T == TTB, DDAMG_EINVAL,
+           "mv_multiaxpy_norm2_into_f16: forms");
+  PtrPack pk;
+  for (int j = 0; j < k; ++j) {
+    DD_CHECK(Vs[j].prec == P16 && Vs[j].reals() == w.reals(), DDAMG_EINVAL, "mv_multiaxpy_norm2_into_f16: shape");
+    pk.p[j] = Vs[j].p;
+  }
+  DD_CHECK(out.reals() == w.reals(), DDAMG_EINVAL, "mv_multiaxpy_norm2_into_f16: output shape");
+  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
+  const int nb = (int)std::max<size_t>(1, std::min<size_t>((tile_units + 255) / 256, 3072 / w.ntiles));
+  const int ncol = w.ncol();
+  double* part = scratch(c, (size_t)nb * ncol * sizeof(double));
+  hipLaunchKernelGGL(k_multiaxpy_norm_h, dim3(nb, w.ntiles), dim3(256), 0, c->stream, pk, k, d_coef, d_cinv2,
+                     w.as<float>(), out.as<_Float16>(), d_osc, w.T, tile_units, ncol, -1.0 / Vs[0].hscale, part);
   DD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sum_rows, dim3(ncol), dim3(64), 0, c->stream, part, d_n2, nb, ncol);
   DD_HIP(hipGetLastError());

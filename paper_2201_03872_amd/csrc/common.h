@@ -196,6 +196,9 @@ void mv_norm2(ddamg_ctx* c, const MV& a, double* d_out);          // per column,
 // mv_multiaxpy followed by mv_norm2 of w, fused into one pass where possible
 void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
                         double* d_n2);
+// the same for an unnormalised FP16 basis, writing the result into an FP16 vector
+void mv_multiaxpy_norm2_into_f16(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const double* d_cinv2,
+                                 const MV& w, const MV& out, const double* d_osc, double* d_n2);
 // variants on caller-owned buffers (no context scratch: safe to capture in a graph)
 size_t multidot_partials(const MV& w, int k);
 void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out, double* part);

@@ -109,6 +109,7 @@ struct LW {
   MV wt, vi;                     // FP16 basis: working-precision new vector and preconditioner input
   double* d_h = nullptr;         // [KMAX][ncol] complex dots + [ncol] norm
   double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
+  double* d_vsc = nullptr;       // FP16 basis: [KMAX+1][ncol] 1/c_j^2 of the stored vectors + [ncol] store scale
   int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
   double* d_muc = nullptr;       // [ncol] shifts of the active columns
   struct GraphState* gs = nullptr;   // captured GMRES steps (unpreconditioned solves)
@@ -175,6 +176,7 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     w.Z.clear();
     if (w.d_h) c->pool.release(w.d_h);
     if (w.d_aux) c->pool.release(w.d_aux);
+    if (w.d_vsc) c->pool.release(w.d_vsc);
     if (w.d_map) c->pool.release(w.d_map);
     if (w.d_muc) c->pool.release(w.d_muc);
     w.d_map = nullptr;
@@ -186,6 +188,7 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     const int ncol = ntiles * c->T;
     w.d_h = (double*)c->pool.alloc(((size_t)KMAX * ncol * 2 + ncol) * sizeof(double));
     w.d_aux = (double*)c->pool.alloc((size_t)KMAX * ncol * 2 * sizeof(double));
+    w.d_vsc = (double*)c->pool.alloc((size_t)(KMAX + 2) * ncol * sizeof(double));
   }
   return w;
 }
@@ -216,8 +219,12 @@ struct Cycle {
   std::vector<cd> H, g, sn;
   std::vector<double> cs, hbuf, coef;
   std::vector<int> kc;          // Arnoldi steps used per column (-1: all of the cycle)
+  // FP16 basis stored unnormalised: entry scale c_j of each stored vector,
+  // 1/c_j^2 and the store scale of the next vector (uploaded each step)
+  std::vector<double> cj, vsc, nstore;
   Cycle(int ncol, int m_) : m(m_), H((size_t)ncol * (m_ + 1) * m_), g((size_t)ncol * (m_ + 1)), sn((size_t)ncol * m_),
-                            cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol) {}
+                            cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol),
+                            cj((size_t)(m_ + 1) * ncol, 1.0), vsc((size_t)(KMAX + 2) * ncol, 1.0), nstore(ncol, 1.0) {}
 };
 
 // One (F)GMRES cycle on the first nt tiles of the level's workspace: V[0]
@@ -236,6 +243,25 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
   MV r = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, 0, level, vprec, cap, nt);
   if (half) mv_normalize_into_f16(c, r, d_n2, basis(c, w.V, 0, level, vprec, cap, nt));
   else mv_normalize(c, r, d_n2);
+  // FP16 basis: later vectors are stored unnormalised, as w' / nstore (nstore:
+  // a prediction of |w'| made before it is known), and carry the entry scale
+  // c_j = |w'| / nstore; the first one is normalised (c_0 = 1).  The stored
+  // vectors are used as they are (preconditioner and operator inputs, Z):
+  // the Arnoldi relation then holds with H_qj = <v_q, A z_j>, v_q = V_q / c_q
+  const double hscale = half ? basis(c, w.V, 0, level, vprec, cap, nt).hscale : 1.0;
+  double* d_cinv2 = w.d_vsc;
+  double* d_osc = w.d_vsc + (size_t)(KMAX + 1) * ncol;
+  if (half) {
+    for (int i = 0; i < ncol; ++i) {
+      cy.cj[i] = 1.0;
+      cy.nstore[i] = 1.0;
+      cy.vsc[i] = 1.0;
+      cy.vsc[(size_t)(KMAX + 1) * ncol + i] = hscale;
+    }
+    DD_HIP(hipMemcpyAsync(d_cinv2, cy.vsc.data(), ncol * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    DD_HIP(hipMemcpyAsync(d_osc, cy.vsc.data() + (size_t)(KMAX + 1) * ncol, ncol * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+  }
   for (int i = 0; i < ncol; ++i) {
     cy.kc[i] = done[i] ? 0 : -1;
     for (int j = 0; j <= m; ++j) cy.g[(size_t)i * (m + 1) + j] = 0;
@@ -265,20 +291,42 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     std::vector<MV> Vs(j + 1);
     for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, vprec, cap, nt);
     mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
-    mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
+    if (half)   // w' straight into the next FP16 basis vector, unnormalised
+      mv_multiaxpy_norm2_into_f16(c, Vs.data(), j + 1, w.d_h, d_cinv2, vn, basis(c, w.V, j + 1, level, vprec, cap, nt),
+                                  d_osc, d_n2);
+    else
+      mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
     // one copy of the dots and the norm
     const size_t nh = (size_t)(j + 1) * ncol * 2;
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
     copy_to_host(c, d_n2, cy.hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
-    if (half) mv_normalize_into_f16(c, vn, d_n2, basis(c, w.V, j + 1, level, vprec, cap, nt));
-    else mv_normalize(c, vn, d_n2);
+    if (!half) mv_normalize(c, vn, d_n2);
     ++total;
     jj = j + 1;
     bool alld = true;
+    if (half) {   // entry scale of the vector just stored, and the store scale of the next
+      for (int i = 0; i < ncol; ++i) {
+        const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+        const double cn = hn > 0 ? hn / cy.nstore[i] : 1.0;
+        // the next norm is predicted as c_{j+1} times this step's norm for a
+        // unit input (hn / c_j), which keeps the entry scales near 1
+        if (hn > 0) cy.nstore[i] = cn * hn / cy.cj[(size_t)j * ncol + i];
+        cy.cj[(size_t)(j + 1) * ncol + i] = cn;
+        cy.vsc[(size_t)(j + 1) * ncol + i] = 1.0 / (cn * cn);
+        cy.vsc[(size_t)(KMAX + 1) * ncol + i] = hscale / cy.nstore[i];
+      }
+      DD_HIP(hipMemcpyAsync(d_cinv2 + (size_t)(j + 1) * ncol, cy.vsc.data() + (size_t)(j + 1) * ncol,
+                            ncol * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      DD_HIP(hipMemcpyAsync(d_osc, cy.vsc.data() + (size_t)(KMAX + 1) * ncol, ncol * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+    }
     for (int i = 0; i < ncol; ++i) {
       cd* Hc = &cy.H[(size_t)i * (m + 1) * m];
-      for (int q = 0; q <= j; ++q)
-        Hc[(size_t)q * m + j] = cd(cy.hbuf[((size_t)q * ncol + i) * 2], cy.hbuf[((size_t)q * ncol + i) * 2 + 1]);
+      for (int q = 0; q <= j; ++q) {   // dots with the stored vectors, over their entry scale
+        const double cq = half ? cy.cj[(size_t)q * ncol + i] : 1.0;
+        Hc[(size_t)q * m + j] =
+            cd(cy.hbuf[((size_t)q * ncol + i) * 2], cy.hbuf[((size_t)q * ncol + i) * 2 + 1]) / cq;
+      }
       const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
       Hc[(size_t)(j + 1) * m + j] = hn;
       if (done[i] && cy.kc[i] >= 0) continue;
