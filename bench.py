@@ -61,7 +61,7 @@ SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
                1: ("k_sap_half<float, 2, 2, 256, false, float, false>", 1),
                2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_Lb0EEE", 6),
                3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_Lb0EEE", 6)}
-SAP_OE_KERNEL = ("_ZN5ddamg8k_sap_oeIfLi2EDF16_EE", 6)
+SAP_OE_KERNEL = ("_ZN5ddamg8k_sap_oeIfLi2EDF16_Li2EEE", 6)
 
 
 def sap_kernel(solver, variant):

@@ -689,31 +689,35 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? (CL ? 3 :
 // D_ee, D_oo = (4 + m0) + i mu gamma5 and the hop parts D_eo, D_oe of D_BB:
 //   S x_o = r_o - D_oe D_ee^{-1} r_e,   S = D_oo - D_oe D_ee^{-1} D_eo,
 //   x_e = D_ee^{-1} (r_e - D_eo x_o).
-// A workgroup of 128 lanes owns one block and one column; lane i owns the
-// i-th even and the i-th odd site of the block (local site 2i + b, with b
-// fixing the parity), so neither half of an MR step leaves lanes idle.  Per
+// A workgroup of 128 K lanes owns one block and K columns of a tile (the
+// column index runs fastest over the lanes, so the K lanes of one site touch
+// adjacent bytes of every chunk); the lanes of site pair i own the i-th even
+// and the i-th odd site of the block (local site 2i + b, with b fixing the
+// parity), so neither half of an MR step leaves lanes idle.  Per
 // step the even half gathers the odd in-block neighbours (D_eo, then
 // D_ee^{-1}) and the odd half the even ones (D_oe), both from LDS; one
 // reduction per column and block follows.  The first cycle of a call uses
 // that x is zero as the plain kernel does (x_zero 1 and 2).
-template <typename R, int LK, typename FIN = R>
-__global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FIN* __restrict__ f, R* __restrict__ x,
+template <typename R, int LK, typename FIN = R, int K = 1>
+__global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FIN* __restrict__ f, R* __restrict__ x,
                                                 const void* __restrict__ U, const int* __restrict__ nbr,
                                                 const double* __restrict__ mu, const int* __restrict__ blist, int V,
                                                 int ntiles, size_t tile_reals, R diag, int mr_iters, int x_zero,
                                                 float fscale) {
   using C = typename Chunk<R>::type;
-  constexpr int RW = Chunk<R>::RW, NCH = 24 / RW, BS = 256, NH = 128;
-  __shared__ C lodd[NCH * NH];    // odd-site vectors by parity index
-  __shared__ C leven[NCH * NH];   // even-site vectors
-  __shared__ R red[2][3];
+  constexpr int RW = Chunk<R>::RW, NCH = 24 / RW, BS = 256, NH = 128, NW = 2 * K;
+  static_assert(TT % K == 0 && 64 % K == 0, "columns per workgroup");
+  __shared__ C lodd[NCH * NH * K];    // odd-site vectors by parity index, [chunk][pair][column]
+  __shared__ C leven[NCH * NH * K];   // even-site vectors
+  __shared__ R red[NW][K][3];
 
   int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int t = wg % TT;
-  wg /= TT;
+  const int kk = threadIdx.x % K;
+  const int t = (wg % (TT / K)) * K + kk;
+  wg /= TT / K;
   const int tile = wg % ntiles;
   const int bi = wg / ntiles;
-  const int i = threadIdx.x;
+  const int i = threadIdx.x / K;
   const int blk = blist[bi];
   const int par = ((i >> 1) ^ (i >> 3) ^ (i >> 5)) & 1;   // parity of y + z + t of local sites 2i, 2i+1
   const int se = blk * BS + 2 * i + par, so = blk * BS + 2 * i + (par ^ 1);
@@ -741,20 +745,21 @@ __global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FI
   auto to_lds = [&](C* arr, const cx<R>(&v)[12]) {
     if constexpr (RW == 2) {
 #pragma unroll
-      for (int k = 0; k < NCH; ++k) arr[k * NH + i] = C{v[k].re, v[k].im};
+      for (int k = 0; k < NCH; ++k) arr[(k * NH + i) * K + kk] = C{v[k].re, v[k].im};
     } else {
 #pragma unroll
-      for (int k = 0; k < NCH; ++k) arr[k * NH + i] = C{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+      for (int k = 0; k < NCH; ++k)
+        arr[(k * NH + i) * K + kk] = C{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
     }
   };
   auto from_lds = [&](const C* arr, int pi, cx<R>(&p)[12]) {
     if constexpr (RW == 2) {
 #pragma unroll
-      for (int k = 0; k < NCH; ++k) { const C c = arr[k * NH + pi]; p[k] = {c.x, c.y}; }
+      for (int k = 0; k < NCH; ++k) { const C c = arr[(k * NH + pi) * K + kk]; p[k] = {c.x, c.y}; }
     } else {
 #pragma unroll
       for (int k = 0; k < NCH; ++k) {
-        const C c = arr[k * NH + pi];
+        const C c = arr[(k * NH + pi) * K + kk];
         p[2 * k] = {c.x, c.y};
         p[2 * k + 1] = {c.z, c.w};
       }
@@ -813,7 +818,7 @@ __global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FI
     rho[k] = rho[k] + (R)0.5 * acc[k];
     dl[k] = {0, 0};
   }
-  const int lane = i % 64, wave = i / 64;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   for (int it = 0; it < mr_iters; ++it) {
     to_lds(lodd, rho);
     __syncthreads();
@@ -839,16 +844,22 @@ __global__ void __launch_bounds__(128, sizeof(R) == 4 ? 3 : 1) k_sap_oe(const FI
       dd += q[k].re * q[k].re + q[k].im * q[k].im;
     }
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
+    for (int off = K; off < 64; off <<= 1) {
       nr += __shfl_xor(nr, off, 64);
       ni += __shfl_xor(ni, off, 64);
       dd += __shfl_xor(dd, off, 64);
     }
-    if (lane == 0) { red[wave][0] = nr; red[wave][1] = ni; red[wave][2] = dd; }
+    if (lane < K) { red[wave][lane][0] = nr; red[wave][lane][1] = ni; red[wave][lane][2] = dd; }
     __syncthreads();
-    nr = red[0][0] + red[1][0];
-    ni = red[0][1] + red[1][1];
-    dd = red[0][2] + red[1][2];
+    nr = 0;
+    ni = 0;
+    dd = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      nr += red[w][kk][0];
+      ni += red[w][kk][1];
+      dd += red[w][kk][2];
+    }
     const cx<R> a = dd > 0 ? cx<R>{nr / dd, ni / dd} : cx<R>{0, 0};
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -1151,13 +1162,18 @@ static void sap_clover(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
   c->st.sap_calls++;
 }
 
+// Columns per workgroup of the FP32 odd-even SAP kernel (LDS: 24.6 KB per
+// column, so three workgroups of two columns fit a CU).
+constexpr int SAP_OE_COLS = 2;
+
 // x is fully written by the first cycle (each site belongs to one block of
 // one colour), so it needs no clearing beforehand.
 template <typename R, int LK, typename FIN = R>
 static void launch_sap_oe(ddamg_ctx* c, const MV& f, const MV& x, const double* d_mu, int colour, int x_zero) {
+  constexpr int K = sizeof(R) == 4 ? SAP_OE_COLS : 1;   // FP64: the LDS of one column already limits residency
   const int nb = c->n_sap[colour];
   const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
-  hipLaunchKernelGGL((k_sap_oe<R, LK, FIN>), dim3(nb * x.ntiles * TT), dim3(128), 0, c->stream, f.as<FIN>(),
+  hipLaunchKernelGGL((k_sap_oe<R, LK, FIN, K>), dim3(nb * x.ntiles * (TT / K)), dim3(128 * K), 0, c->stream, f.as<FIN>(),
                      x.as<R>(), U, c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles,
                      x.tile_reals(), (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
   DD_HIP(hipGetLastError());
