@@ -775,11 +775,18 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
     };
     all_hops_e<R, LK>(acc, gl, e8, s, ld);
   };
-  // block residual at one site (as in the plain kernel)
+  // block residual at one site, as in the plain kernel, except that the
+  // right-hand side is loaded after the hops (it holds no registers while
+  // they run)
   auto residual = [&](int s, const int (&e8)[8], cx<R>(&r)[12]) {
-    if constexpr (std::is_same<FIN, R>::value) load_cx<R, 12>(ft, V, TT, s, t, r);
-    else load_cx_f16<12>(ft, V, TT, s, t, fscale, r);
-    if (x_zero == 1) return;
+    auto load_f = [&]() {
+      if constexpr (std::is_same<FIN, R>::value) load_cx<R, 12>(ft, V, TT, s, t, r);
+      else load_cx_f16<12>(ft, V, TT, s, t, fscale, r);
+    };
+    if (x_zero == 1) {
+      load_f();
+      return;
+    }
     auto ldg = [&](int, int nb, cx<R>(&p)[12]) {
       if (x_zero == 2 && nb / BS == blk) return false;
       load_cx<R, 12>(xt, V, TT, nb, t, p);
@@ -787,6 +794,7 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
     };
     cx<R> acc[12], xs[12], q[12];
     all_hops_e<R, LK>(acc, gl, e8, s, ldg);
+    asm volatile("" ::: "memory");
     if (x_zero == 2) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) xs[k] = {0, 0};
@@ -794,6 +802,7 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
       load_cx<R, 12>(xt, V, TT, s, t, xs);
     }
     site_diag(q, xs, acc, diag, m);
+    load_f();
 #pragma unroll
     for (int k = 0; k < 12; ++k) r[k] = r[k] - q[k];
   };
@@ -810,9 +819,11 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
   // leaving hops are not gathered twice)
   if (x_zero == 2) store_cx<R, 12>(xt, V, TT, se, t, q);
   residual(so, eo, rho);
+  to_lds(lodd, rho);   // parked in LDS (not yet in use) during the gather
   __syncthreads();
   // right-hand side of the Schur system: r_o - D_oe D_ee^{-1} r_e (D_oe = -1/2 hops)
   gather(leven, eo, so, acc);
+  from_lds(lodd, i, rho);
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     rho[k] = rho[k] + (R)0.5 * acc[k];
@@ -829,8 +840,11 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
     site_inv(q);
     to_lds(leven, q);
     __syncthreads();
-    // odd half: q = S rho = D_oo rho - D_oe u
+    // odd half: q = S rho = D_oo rho - D_oe u (rho is read back from LDS,
+    // where it waits unchanged since the step began, so that it holds no
+    // registers through the two gathers)
     gather(leven, eo, so, acc);
+    from_lds(lodd, i, rho);
 #pragma unroll
     for (int k = 0; k < 12; ++k) q[k] = rho[k];
     site_mul(q);
@@ -870,8 +884,12 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
   // back substitution: x_e = D_ee^{-1} r_e - D_ee^{-1} D_eo x_o (the even
   // residual is recomputed unless it was kept: x is unchanged so far)
   to_lds(lodd, dl);
-  __syncthreads();
+  // the even residual first (it reads x, which the barrier below then orders
+  // before every write of x on the block), the gather after it, so that
+  // neither holds registers during the other
   cx<R> xe[12];
+  if (x_zero != 2) residual(se, ee, xe);
+  __syncthreads();
   gather(lodd, ee, se, acc);
   if (x_zero == 2) {
 #pragma unroll
@@ -881,12 +899,11 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
 #pragma unroll
     for (int k = 0; k < 12; ++k) xe[k] = xe[k] + q[k];
   } else {
-    residual(se, ee, xe);
 #pragma unroll
     for (int k = 0; k < 12; ++k) xe[k] = xe[k] + (R)0.5 * acc[k];
     site_inv(xe);
-    if (x_zero == 0) __syncthreads();   // every read of x on the block precedes the writes below
   }
+  from_lds(lodd, i, dl);   // x_o waited in LDS through the back substitution
   if (x_zero) {
     store_cx<R, 12>(xt, V, TT, so, t, dl);
     store_cx<R, 12>(xt, V, TT, se, t, xe);
