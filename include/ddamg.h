@@ -142,6 +142,8 @@ typedef struct ddamg_stats {
   int    learned_fallbacks;  /* learned-smoother calls replaced by SAP (last solve)             */
   int    col_removals;       /* compactions of the active column set (last solve)               */
   long long n_inner_iters;   /* FP32 inner FGMRES steps over all outer steps (last solve)       */
+  long long n_fp16_restores; /* inner steps whose FP16 basis vector was stored again at its exact
+                                norm (entry scale outside the DDAMG_KNOB_FP16_RESCALE bound)     */
 } ddamg_stats;
 
 /* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */
@@ -266,7 +268,12 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             registers, 4 / 8 columns per workgroup; 4^4 SAP blocks only) */
 #define DDAMG_KNOB_WALK_SEGMENTS     6   /* t-walk stencil: segments of the t direction, one workgroup
                                             each (1, 2, 4 or 8; must divide Lt, else 1) */
-#define DDAMG_N_KNOBS 7
+#define DDAMG_KNOB_FP16_RESCALE      7   /* inner FGMRES with an FP16 basis: new basis vectors are
+                                            stored unnormalised, at a predicted norm; when the ratio
+                                            c of the true norm to the prediction leaves [1/B, B]
+                                            the vector is stored again at its exact norm.  B: 1 to
+                                            1024 (default 4; 1 stores every vector at its norm) */
+#define DDAMG_N_KNOBS 8
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

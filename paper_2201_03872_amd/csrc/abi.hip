@@ -389,6 +389,7 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
   c->st.learned_fallbacks = 0;
   c->st.col_removals = 0;
   c->st.inner_iters = 0;
+  c->st.fp16_restores = 0;
   const int ncol = (int)hmu.size();
   for (double m : hmu) DD_CHECK(std::isfinite(m), DDAMG_EINVAL, "twisted mass is NaN/Inf");
   // NaN guard on the right-hand sides (canonical, one field per distinct rhs)
@@ -516,6 +517,7 @@ int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
     s->learned_fallbacks = c->st.learned_fallbacks;
     s->col_removals = c->st.col_removals;
     s->n_inner_iters = c->st.inner_iters;
+    s->n_fp16_restores = c->st.fp16_restores;
     return DDAMG_OK;
   });
 }
@@ -592,6 +594,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_SAP_VARIANT: return &c->sap_variant;
     case DDAMG_KNOB_DSLASH_ORDER: return &c->dslash_order;
     case DDAMG_KNOB_WALK_SEGMENTS: return &c->walk_seg;
+    case DDAMG_KNOB_FP16_RESCALE: return &c->fp16_rescale;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -605,6 +608,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_SAP_VARIANT: return value >= 0 && value <= 3;
     case DDAMG_KNOB_DSLASH_ORDER: return value >= 0 && value <= 3;
     case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
+    case DDAMG_KNOB_FP16_RESCALE: return value >= 1 && value <= 1024;
     default: return false;
   }
 }

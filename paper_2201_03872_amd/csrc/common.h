@@ -128,6 +128,7 @@ struct Stats {
   int learned_fallbacks = 0;
   int col_removals = 0;
   long long inner_iters = 0;
+  long long fp16_restores = 0;
 };
 
 }  // namespace ddamg
@@ -167,6 +168,7 @@ struct ddamg_ctx {
   int dslash_order = 0;         // fine stencil scheme: 0 storage order, 1 time-slice order, 2/3 t-walk (4/8 columns)
   int* d_walk_blk = nullptr;    // [xyz block column][t block] block numbers (4^4 site blocks)
   int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
+  int fp16_rescale = 4;         // FP16 Arnoldi basis: bound on the entry scales of the stored vectors
   int* d_dslash_order[4] = {nullptr, nullptr, nullptr, nullptr};   // per sites-per-workgroup 16..128
   int sap_variant = 0;          // FP32 SAP on 4^4 blocks: 0 = 2 columns/WG, links in LDS; 1 = 2 columns, links
                                 // through L1/L2; 2 = 1 column/WG, 2-row links through L1/L2; 3 = 1 column/WG,

@@ -221,10 +221,11 @@ struct Cycle {
   std::vector<int> kc;          // Arnoldi steps used per column (-1: all of the cycle)
   // FP16 basis stored unnormalised: entry scale c_j of each stored vector,
   // 1/c_j^2 and the store scale of the next vector (uploaded each step)
-  std::vector<double> cj, vsc, nstore;
+  std::vector<double> cj, vsc, nstore, osc_exact;
   Cycle(int ncol, int m_) : m(m_), H((size_t)ncol * (m_ + 1) * m_), g((size_t)ncol * (m_ + 1)), sn((size_t)ncol * m_),
                             cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol),
-                            cj((size_t)(m_ + 1) * ncol, 1.0), vsc((size_t)(KMAX + 2) * ncol, 1.0), nstore(ncol, 1.0) {}
+                            cj((size_t)(m_ + 1) * ncol, 1.0), vsc((size_t)(KMAX + 2) * ncol, 1.0), nstore(ncol, 1.0),
+                            osc_exact(ncol, 1.0) {}
 };
 
 // One (F)GMRES cycle on the first nt tiles of the level's workspace: V[0]
@@ -305,9 +306,30 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     jj = j + 1;
     bool alld = true;
     if (half) {   // entry scale of the vector just stored, and the store scale of the next
+      // an entry scale far from 1 (a norm far from its prediction) would
+      // leave the stored FP16 entries near the subnormal range or waste
+      // their range: the pass is then run again (w and the dots are still
+      // intact) with each column stored at its exact norm (c = 1)
+      const double bound = c->fp16_rescale;
+      bool redo = false;
       for (int i = 0; i < ncol; ++i) {
         const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
-        const double cn = hn > 0 ? hn / cy.nstore[i] : 1.0;
+        const double cn = hn / cy.nstore[i];
+        if (hn > 0 && (cn * bound < 1.0 || cn > bound)) redo = true;
+      }
+      if (redo) {
+        for (int i = 0; i < ncol; ++i) {
+          const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+          cy.osc_exact[i] = hscale / (hn > 0 ? hn : cy.nstore[i]);
+        }
+        DD_HIP(hipMemcpyAsync(d_osc, cy.osc_exact.data(), ncol * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        mv_multiaxpy_norm2_into_f16(c, Vs.data(), j + 1, w.d_h, d_cinv2, vn,
+                                    basis(c, w.V, j + 1, level, vprec, cap, nt), d_osc, d_n2);
+        c->st.fp16_restores++;
+      }
+      for (int i = 0; i < ncol; ++i) {
+        const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+        const double cn = hn > 0 && !redo ? hn / cy.nstore[i] : 1.0;
         // the next norm is predicted as c_{j+1} times this step's norm for a
         // unit input (hn / c_j), which keeps the entry scales near 1
         if (hn > 0) cy.nstore[i] = cn * hn / cy.cj[(size_t)j * ncol + i];

@@ -157,6 +157,40 @@ def test_inner_fgmres_refinement(torch_cuda, dd, precision, fp16, oddeven):
     ctx.close()
 
 
+@pytest.mark.parametrize("bound", [1, 4, 1024])
+def test_fp16_basis_entry_scale_bound(torch_cuda, dd, bound):
+    """The FP16 inner basis is stored unnormalised at a predicted norm; a
+    vector whose entry scale leaves [1/B, B] is stored again at its exact
+    norm.  B = 1 takes that path at every step (every vector normalised),
+    B = 1024 almost never; every form reaches the FP64 oracle residual
+    1e-10, and B = 1 restores at least one vector per inner step."""
+    torch = torch_cuda
+    w = S.workload("tm_8x8x8x8_3level")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    mus = np.array(w.mus)
+    b = torch.from_numpy(S.rhs_for(w)).cuda()
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=(4, 4, 4, 4), sap_cycles=1,
+                          sap_mr_iters=4, outer_restart=4, max_outer=200, inner_iters=30, inner_tol=1e-2,
+                          inner_fp16=1, precision=dd.MIXED, sap_oddeven=1)
+    ctx = dd.Context(p, U)
+    ctx.set_tuning("fp16_rescale", bound)
+    assert ctx.get_tuning("fp16_rescale") == bound
+    x, info, st = ctx.solve(mus, b)
+    s = ctx.stats()
+    say(f"FP16 basis, entry-scale bound {bound}: outer {s['outer_iters']}, inner {s['n_inner_iters']}, "
+        f"restored {s['n_fp16_restores']}")
+    op = O.WilsonTM(U, w.dims, kappa=w.kappa)
+    check_batch(op, [(mus, S.rhs_for(w))], [x], [info])
+    assert st == dd.OK and s["outer_iters"] <= 20
+    if bound == 1:
+        assert s["n_fp16_restores"] >= s["n_inner_iters"] - s["outer_iters"]
+    for bad in (0, 1025):
+        with pytest.raises(dd.DDAMGError) as e:
+            ctx.set_tuning("fp16_rescale", bad)
+        assert e.value.code == dd.EINVAL
+    ctx.close()
+
+
 def test_two_level_solve_with_oddeven_smoother(torch_cuda, dd):
     """The odd-even SAP as the fine smoother of the two-level K-cycle (4^4 SAP
     blocks = aggregates): every column reaches the oracle's FP64 residual."""
