@@ -522,6 +522,35 @@ struct SapLinks {
   }
 };
 
+// The hops in direction MU that leave a SAP block of BS sites, from global
+// memory: where the block is at least 2 sites wide in MU a site lies on at
+// most one face, so the forward and backward cases share one load of the
+// neighbour spinor and one of the link (the lanes of a wave take either;
+// lanes inside the block idle).
+template <int MU, int BS, typename R, int LK>
+__device__ __forceinline__ void leaving_hops(cx<R> (&acc)[12], const int (&e)[8], int s, int blk,
+                                             const R* __restrict__ xt, int V, int t, const GlobalLinks<R, LK>& gl) {
+  const int ef = e[MU], eb = e[4 + MU];
+  const int nf = ef & 0x7fffffff, nbk = eb & 0x7fffffff;
+  const bool fo = nf / BS != blk, bo = nbk / BS != blk;
+  if (!fo && !bo) return;
+  int nb = fo ? nf : nbk;
+  int ls = fo ? s : nbk;
+  asm volatile("" : "+v"(nb), "+v"(ls));
+  cx<R> p[12], u[9];
+  load_cx<R, 12>(xt, V, TT, nb, t, p);
+  gl(MU, ls, u);
+  if (fo) hop_apply<MU, true, GlobalLinks<R, LK>::table_sign>(acc, p, u, ef);
+  else hop_apply<MU, false, GlobalLinks<R, LK>::table_sign>(acc, p, u, eb);
+  if (fo && bo) {   // both faces: a block one site wide in this direction
+    int nb2 = nbk;
+    asm volatile("" : "+v"(nb2));
+    load_cx<R, 12>(xt, V, TT, nb2, t, p);
+    gl(MU, nb2, u);
+    hop_apply<MU, false, GlobalLinks<R, LK>::table_sign>(acc, p, u, eb);
+  }
+}
+
 // One colour half-sweep of red-black SAP (paper section 2): every workgroup
 // owns one block of that colour and K columns of a tile.
 //   1. r = f - D x on the block's sites (full stencil, neighbours in global memory);
@@ -588,7 +617,23 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? (CL ? 3 :
       return true;
     };
     cx<R> acc[12], xs[12], fs[12];
-    all_hops_e<R, LK>(acc, GlobalLinks<R, LK>{U, V}, e8, s, ldg);
+    if (x_zero == 2) {   // x is zero on the block: only the hops that leave it
+      const GlobalLinks<R, LK> gl{U, V};
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
+#pragma unroll 1
+      for (int d = 0; d < 4; ++d) {
+        asm volatile("" ::: "memory");
+        switch (d) {
+          case 0: leaving_hops<0, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          case 1: leaving_hops<1, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          case 2: leaving_hops<2, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          default: leaving_hops<3, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+        }
+      }
+    } else {
+      all_hops_e<R, LK>(acc, GlobalLinks<R, LK>{U, V}, e8, s, ldg);
+    }
     if (x_zero == 2) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) xs[k] = {0, 0};
@@ -679,35 +724,6 @@ __global__ void __launch_bounds__(BS * K, (sizeof(R) == 4 && K == 1) ? (CL ? 3 :
 #pragma unroll
     for (int k = 0; k < 12; ++k) xs[k] = xs[k] + dl[k];
     store_cx<R, 12>(xt, V, TT, s, t, xs);
-  }
-}
-
-// The hops in direction MU that leave a 4^4 block, from global memory: a
-// site is on at most one face per direction, so the forward and backward
-// cases share one load of the neighbour spinor and one of the link (the
-// lanes of a wave take either; lanes inside the block idle).
-template <int MU, typename R, int LK>
-__device__ __forceinline__ void leaving_hops(cx<R> (&acc)[12], const int (&e)[8], int s, int blk,
-                                             const R* __restrict__ xt, int V, int t, const GlobalLinks<R, LK>& gl) {
-  constexpr int BS = 256;
-  const int ef = e[MU], eb = e[4 + MU];
-  const int nf = ef & 0x7fffffff, nbk = eb & 0x7fffffff;
-  const bool fo = nf / BS != blk, bo = nbk / BS != blk;
-  if (!fo && !bo) return;
-  int nb = fo ? nf : nbk;
-  int ls = fo ? s : nbk;
-  asm volatile("" : "+v"(nb), "+v"(ls));
-  cx<R> p[12], u[9];
-  load_cx<R, 12>(xt, V, TT, nb, t, p);
-  gl(MU, ls, u);
-  if (fo) hop_apply<MU, true, GlobalLinks<R, LK>::table_sign>(acc, p, u, ef);
-  else hop_apply<MU, false, GlobalLinks<R, LK>::table_sign>(acc, p, u, eb);
-  if (fo && bo) {   // both faces: blocks narrower than 4 in this direction
-    int nb2 = nbk;
-    asm volatile("" : "+v"(nb2));
-    load_cx<R, 12>(xt, V, TT, nb2, t, p);
-    gl(MU, nb2, u);
-    hop_apply<MU, false, GlobalLinks<R, LK>::table_sign>(acc, p, u, eb);
   }
 }
 
@@ -829,10 +845,10 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
       for (int d = 0; d < 4; ++d) {
         asm volatile("" ::: "memory");
         switch (d) {
-          case 0: leaving_hops<0, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
-          case 1: leaving_hops<1, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
-          case 2: leaving_hops<2, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
-          default: leaving_hops<3, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          case 0: leaving_hops<0, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          case 1: leaving_hops<1, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          case 2: leaving_hops<2, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
+          default: leaving_hops<3, BS, R, LK>(acc, e8, s, blk, xt, V, t, gl); break;
         }
       }
     } else {
