@@ -182,8 +182,9 @@ int ddamg_apply_op(ddamg_ctx* h, int level, int precision, const double* mu, int
  * sap_mr_iters MR steps per block (section 2; fine level, device pointers).
  * precision DDAMG_FP64, DDAMG_FP32, or DDAMG_FP16: the FP32 smoother with
  * each f_c first stored in FP16 as f_c * sqrt(12 V) / 16 (V fine sites), the
- * form the inner Krylov solve uses on its FP16 basis; it needs 4^4 blocks and
- * DDAMG_KNOB_SAP_VARIANT 2 or 3, else DDAMG_EINVAL. */
+ * form the inner Krylov solve uses on its FP16 basis; it needs SAP blocks of
+ * 256 sites and DDAMG_KNOB_SAP_VARIANT 2 or 3 (or sap_oddeven), else
+ * DDAMG_EINVAL. */
 int ddamg_apply_sap(ddamg_ctx* h, int precision, const double* mu, int n_col,
                     const double* f, double* x);
 
@@ -239,8 +240,8 @@ int ddamg_get_stats(ddamg_ctx* h, ddamg_stats* s);
  * 5 = plain device copy of the multivector (reads and writes its size; a
  * kernel of known traffic for calibrating memory counters), 6 = SAP smoother
  * reading its right-hand side from FP16 storage (the form used inside the
- * inner Krylov solve; precision FP32, level 0, 4^4 blocks and SAP variant 2,
- * else DDAMG_EINVAL). */
+ * inner Krylov solve; precision FP32, level 0, SAP blocks of 256 sites and
+ * SAP variant 2 or 3 or sap_oddeven, else DDAMG_EINVAL). */
 int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int n_iter, double* sec);
 
 /* Tile-shape knobs.  DDAMG_KNOB_DSLASH_SITES_FP64: lattice sites per

@@ -250,7 +250,7 @@ int ddamg_apply_sap(ddamg_ctx* c, int precision, const double* mu, int n_col, co
   return guarded([&]() -> int {
     DD_CHECK(c && mu && f && x && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
     DD_CHECK(precision != DDAMG_FP16 || sap_takes_f16(c), DDAMG_EINVAL,
-             "FP16 right-hand sides need 4^4 blocks and SAP variant 2 or 3");
+             "FP16 right-hand sides need 256-site SAP blocks and SAP variant 2 or 3 (or odd-even SAP)");
     const int prec = precision == DDAMG_FP64 ? P64 : P32;
     MV a = mv_alloc(c, 0, prec, n_col), b = mv_alloc(c, 0, prec, n_col);
     double* d_mu = upload_mu(c, mu, n_col, a.ncol());
@@ -538,7 +538,7 @@ int ddamg_time_op(ddamg_ctx* c, int op, int level, int precision, int n_col, int
     DD_CHECK(!(op == 2) || level >= 1, DDAMG_EINVAL, "coarse stencil needs level >= 1");
     DD_CHECK(op >= 0 && op <= 6, DDAMG_EINVAL, "unknown op");
     DD_CHECK(op != 6 || (prec == P32 && level == 0 && sap_takes_f16(c)), DDAMG_EINVAL,
-             "the FP16-input smoother needs FP32, level 0, 4^4 blocks and SAP variant 2");
+             "the FP16-input smoother needs FP32, level 0, 256-site SAP blocks and SAP variant 2 or 3 (or odd-even SAP)");
     MV a64 = mv_alloc(c, lin, P64, n_col);
     random_fill(c, lin, a64, a64.ncol(), 99);
     MV a = (prec == P64) ? a64 : mv_like(c, a64, P32);
