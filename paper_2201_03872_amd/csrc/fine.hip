@@ -399,6 +399,25 @@ __global__ void __launch_bounds__(128) k_clover_build(const double* __restrict__
   }
 }
 
+// Links of the fine stencil: the forward links of the workgroup's site range
+// staged in LDS (2-row FP32), the others (backward hops that leave the
+// range) from global memory.
+template <typename R, int LK, int RS>
+struct RangeLinks {
+  static constexpr bool table_sign = (LK == LK_C);
+  const float4* ulds;
+  const void* U;
+  int V;
+  int base;
+  __device__ __forceinline__ void operator()(int mu, int site, cx<R> (&u)[9]) const {
+    const unsigned l = (unsigned)(site - base);
+    if (l < (unsigned)RS)
+      unpack_2row(ulds[(mu * 3) * RS + l], ulds[(mu * 3 + 1) * RS + l], ulds[(mu * 3 + 2) * RS + l], u);
+    else
+      load_link<R, LK>(U, mu, site, V, u);
+  }
+};
+
 // ------------------------------------------------------------ dslash ---
 // The fine stencil, MODE 0: y = D x ; MODE 1: y = b - D x.
 // With LDS staging: a workgroup owns RS consecutive sites of the
@@ -416,6 +435,7 @@ __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x,
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW, NCH = 24 / RW;
   __shared__ C lds[NCH * RS * TT];
+  __shared__ float4 ulds[LK == LK_C ? 12 * RS : 1];
   const int t = threadIdx.x % TT, sl = threadIdx.x / TT;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = wg / nsb;
@@ -429,6 +449,13 @@ __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x,
   if (active) {
 #pragma unroll
     for (int k = 0; k < NCH; ++k) lds[(k * RS + sl) * TT + t] = xc[((size_t)k * V + s) * TT + t];
+  }
+  if constexpr (LK == LK_C) {   // the range's forward links, each loaded once
+    const float4* Ug = reinterpret_cast<const float4*>(U);
+    for (int i = threadIdx.x; i < 12 * RS; i += RS * TT) {
+      const int q = i / RS, l = i % RS;
+      if (r0 + l < V) ulds[i] = Ug[(size_t)q * V + r0 + l];
+    }
   }
   __syncthreads();
   if (!active) return;
@@ -447,7 +474,8 @@ __global__ void __launch_bounds__(RS * TT) k_dslash_lds(const R* __restrict__ x,
     return true;
   };
   cx<R> acc[12], out[12], xs[12];
-  all_hops<R, LK>(acc, U, nbr, V, s, ld);
+  if constexpr (LK == LK_C) all_hops_ll<R, LK>(acc, RangeLinks<R, LK, RS>{ulds, U, V, r0}, nbr, V, s, ld);
+  else all_hops<R, LK>(acc, U, nbr, V, s, ld);
   from_lds(sl, xs);
   if constexpr (CL) site_diag_cl(out, xs, acc, clov, V, s, (R)mu[tile * TT + t]);
   else site_diag(out, xs, acc, diag, (R)mu[tile * TT + t]);
