@@ -529,7 +529,9 @@ __global__ void __launch_bounds__(256) k_multidot_h(PtrPack Vs, int k, const flo
 #pragma unroll
     for (int j = 0; j < KH; ++j) {
       if (j < kk) {
-        const h4 v = reinterpret_cast<const h4*>(Vs.p[j0 + j])[off];
+        // basis vectors stream through once per step: non-temporal loads
+        // keep them from evicting w, which the other groups read again
+        const h4 v = __builtin_nontemporal_load(reinterpret_cast<const h4*>(Vs.p[j0 + j]) + off);
         const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z, v3 = (float)v.w;
         accr[j] += v0 * wv.x + v1 * wv.y + v2 * wv.z + v3 * wv.w;
         acci[j] += v0 * wv.y - v1 * wv.x + v2 * wv.w - v3 * wv.z;
@@ -785,7 +787,7 @@ __global__ void __launch_bounds__(256) k_multiaxpy_norm_h(PtrPack Vs, int k, con
   for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < tile_units; u += (size_t)gridDim.x * blockDim.x) {
     float acc[4] = {0, 0, 0, 0};
     for (int j = 0; j < k; ++j) {
-      const h4 v = reinterpret_cast<const h4*>(Vs.p[j])[base + u];
+      const h4 v = __builtin_nontemporal_load(reinterpret_cast<const h4*>(Vs.p[j]) + base + u);
       const float cr = cf[j][t][0], ci = cf[j][t][1];
       const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z, v3 = (float)v.w;
       acc[0] += cr * v0 - ci * v1;
