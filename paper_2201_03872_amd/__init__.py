@@ -85,7 +85,8 @@ class Stats(ctypes.Structure):
         ("n_middle_solves", ctypes.c_longlong), ("n_bottom_solves", ctypes.c_longlong),
         ("n_fine_ops", ctypes.c_longlong), ("n_sap_calls", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_int),
         ("col_removals", ctypes.c_int), ("n_inner_iters", ctypes.c_longlong),
-        ("n_fp16_restores", ctypes.c_longlong),
+        ("n_fp16_restores", ctypes.c_longlong), ("sap_kernel_ms", ctypes.c_double),
+        ("n_sap_kernels", ctypes.c_longlong), ("n_sap_kernel_tiles", ctypes.c_longlong),
     ]
 
 
@@ -331,7 +332,7 @@ class Context:
 
     KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2, "coarse_mfma": 3,
              "sap_variant": 4,
-             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7}
+             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7, "time_sap": 8}
 
     # ---- learned smoother ----
     def set_smoother_weights(self, w1, w2):

@@ -199,6 +199,7 @@ void ddamg_destroy(ddamg_ctx* c) {
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   c->pool.clear();
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  for (hipEvent_t e : c->sap_ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -390,6 +391,8 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
   c->st.col_removals = 0;
   c->st.inner_iters = 0;
   c->st.fp16_restores = 0;
+  c->sap_ev_used = 0;
+  c->sap_ev_tiles.clear();
   const int ncol = (int)hmu.size();
   for (double m : hmu) DD_CHECK(std::isfinite(m), DDAMG_EINVAL, "twisted mass is NaN/Inf");
   // NaN guard on the right-hand sides (canonical, one field per distinct rhs)
@@ -427,6 +430,7 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
     }
   }
   c->st.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  sap_timing_collect(c);
   return status;
 }
 
@@ -518,6 +522,9 @@ int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
     s->col_removals = c->st.col_removals;
     s->n_inner_iters = c->st.inner_iters;
     s->n_fp16_restores = c->st.fp16_restores;
+    s->sap_kernel_ms = c->st.sap_kernel_ms;
+    s->n_sap_kernels = c->st.sap_kernel_launches;
+    s->n_sap_kernel_tiles = c->st.sap_kernel_tiles;
     return DDAMG_OK;
   });
 }
@@ -595,6 +602,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_DSLASH_ORDER: return &c->dslash_order;
     case DDAMG_KNOB_WALK_SEGMENTS: return &c->walk_seg;
     case DDAMG_KNOB_FP16_RESCALE: return &c->fp16_rescale;
+    case DDAMG_KNOB_TIME_SAP: return &c->time_sap;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -609,6 +617,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_DSLASH_ORDER: return value >= 0 && value <= 3;
     case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
     case DDAMG_KNOB_FP16_RESCALE: return value >= 1 && value <= 1024;
+    case DDAMG_KNOB_TIME_SAP: return value == 0 || value == 1;
     default: return false;
   }
 }

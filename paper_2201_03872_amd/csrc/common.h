@@ -129,6 +129,8 @@ struct Stats {
   int col_removals = 0;
   long long inner_iters = 0;
   long long fp16_restores = 0;
+  double sap_kernel_ms = 0;          // HIP-event time of the SAP kernels (when timed)
+  long long sap_kernel_launches = 0, sap_kernel_tiles = 0;
 };
 
 }  // namespace ddamg
@@ -169,6 +171,10 @@ struct ddamg_ctx {
   int* d_walk_blk = nullptr;    // [xyz block column][t block] block numbers (4^4 site blocks)
   int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
   int fp16_rescale = 4;         // FP16 Arnoldi basis: bound on the entry scales of the stored vectors
+  int time_sap = 0;             // HIP events around every SAP kernel launch of a solve
+  std::vector<hipEvent_t> sap_ev;   // event pool, (start, stop) pairs, reused by every solve
+  std::vector<int> sap_ev_tiles;    // column tiles of each timed launch
+  size_t sap_ev_used = 0;
   int* d_dslash_order[4] = {nullptr, nullptr, nullptr, nullptr};   // per sites-per-workgroup 16..128
   int sap_variant = 0;          // FP32 SAP on 4^4 blocks: 0 = 2 columns/WG, links in LDS; 1 = 2 columns, links
                                 // through L1/L2; 2 = 1 column/WG, 2-row links through L1/L2; 3 = 1 column/WG,
@@ -280,5 +286,11 @@ double* small_buffer(ddamg_ctx* c, int n_doubles);    // short-lived small devic
 void mv_convert(ddamg_ctx* c, const MV& s, const MV& d);
 void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_norm2);   // x_c /= sqrt(norm2_c)
 void copy_to_host(ddamg_ctx* c, const void* d, void* h, size_t bytes);
+// HIP events around a SAP kernel launch (no-ops unless the time_sap knob is
+// set or the stream is being captured); collect sums them after a
+// synchronisation of the stream
+void sap_timing_begin(ddamg_ctx* c);
+void sap_timing_end(ddamg_ctx* c, int ntiles);
+void sap_timing_collect(ddamg_ctx* c);
 
 }  // namespace ddamg

@@ -264,6 +264,50 @@ void copy_to_host(ddamg_ctx* c, const void* d, void* h, size_t bytes) {
   std::memcpy(h, c->h_pinned, bytes);
 }
 
+static bool sap_timing_on(ddamg_ctx* c) {
+  if (!c->time_sap) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  DD_HIP(hipStreamIsCapturing(c->stream, &cs));
+  return cs == hipStreamCaptureStatusNone;
+}
+
+void sap_timing_begin(ddamg_ctx* c) {
+  if (!sap_timing_on(c)) return;
+  if (c->sap_ev_used + 2 > c->sap_ev.size()) {
+    hipEvent_t a, b;
+    DD_HIP(hipEventCreate(&a));
+    DD_HIP(hipEventCreate(&b));
+    c->sap_ev.push_back(a);
+    c->sap_ev.push_back(b);
+  }
+  DD_HIP(hipEventRecord(c->sap_ev[c->sap_ev_used], c->stream));
+}
+
+void sap_timing_end(ddamg_ctx* c, int ntiles) {
+  if (!sap_timing_on(c)) return;
+  DD_HIP(hipEventRecord(c->sap_ev[c->sap_ev_used + 1], c->stream));
+  c->sap_ev_used += 2;
+  c->sap_ev_tiles.resize(c->sap_ev_used / 2);
+  c->sap_ev_tiles.back() = ntiles;
+}
+
+void sap_timing_collect(ddamg_ctx* c) {
+  double ms = 0;
+  long long tiles = 0;
+  if (c->sap_ev_used) DD_HIP(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i + 1 < c->sap_ev_used; i += 2) {
+    float e = 0;
+    DD_HIP(hipEventElapsedTime(&e, c->sap_ev[i], c->sap_ev[i + 1]));
+    ms += e;
+    tiles += c->sap_ev_tiles[i / 2];
+  }
+  c->st.sap_kernel_ms = ms;
+  c->st.sap_kernel_launches = (long long)(c->sap_ev_used / 2);
+  c->st.sap_kernel_tiles = tiles;
+  c->sap_ev_used = 0;
+  c->sap_ev_tiles.clear();
+}
+
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
   if (level == 0) fine_dslash(c, x, y, d_mu);
   else coarse_apply(c, level, x, y, d_mu);

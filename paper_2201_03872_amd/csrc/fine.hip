@@ -1236,10 +1236,12 @@ static void launch_sap(ddamg_ctx* c, const MV& f, const MV& x, const double* d_m
   const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
   const R* clov = nullptr;
   if constexpr (CL) clov = (const R*)(sizeof(R) == 8 ? (const void*)c->d_clov64 : (const void*)c->d_clov32);
+  sap_timing_begin(c);
   hipLaunchKernelGGL((k_sap_half<R, LK, K, BS, ULDS, FIN, CL>), grid, blk, 0, c->stream, f.as<FIN>(), x.as<R>(), U,
                      c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles, x.tile_reals(),
                      (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale), clov);
   DD_HIP(hipGetLastError());
+  sap_timing_end(c, x.ntiles);
 }
 
 // SAP with a clover term: one column per workgroup on 4^4 blocks (full or
@@ -1278,10 +1280,12 @@ static void launch_sap_oe(ddamg_ctx* c, const MV& f, const MV& x, const double* 
   constexpr int K = sizeof(R) == 4 ? SAP_OE_COLS : 1;   // FP64: the LDS of one column already limits residency
   const int nb = c->n_sap[colour];
   const void* U = LK == LK_C ? (const void*)c->d_U32 : LK == LK_F ? (const void*)c->d_U32f : (const void*)c->d_U64;
+  sap_timing_begin(c);
   hipLaunchKernelGGL((k_sap_oe<R, LK, FIN, K>), dim3(nb * x.ntiles * (TT / K)), dim3(128 * K), 0, c->stream, f.as<FIN>(),
                      x.as<R>(), U, c->geom[0].d_nbr, d_mu, c->d_sap_list[colour], c->geom[0].V, x.ntiles,
                      x.tile_reals(), (R)c->diag, c->p.sap_mr_iters, x_zero, (float)(1.0 / f.hscale));
   DD_HIP(hipGetLastError());
+  sap_timing_end(c, x.ntiles);
 }
 
 // SAP with odd-even reduced block solves (4^4 blocks).  FP32 takes the 2-row

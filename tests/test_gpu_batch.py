@@ -191,6 +191,35 @@ def test_fp16_basis_entry_scale_bound(torch_cuda, dd, bound):
     ctx.close()
 
 
+def test_sap_kernel_timing_stats(torch_cuda, dd):
+    """DDAMG_KNOB_TIME_SAP: HIP events around every SAP kernel launch of a
+    solve, summed into the stats (two half sweeps per one-cycle SAP call);
+    off, the fields stay zero and the solve is unchanged."""
+    torch = torch_cuda
+    w = S.workload("tm_8x8x8x8_3level")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    mus = np.array(w.mus)
+    b = torch.from_numpy(S.rhs_for(w)).cuda()
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=(4, 4, 4, 4), sap_cycles=1,
+                          sap_mr_iters=4, outer_restart=4, max_outer=200, inner_iters=30, inner_tol=1e-2,
+                          inner_fp16=1, precision=dd.MIXED, sap_oddeven=1)
+    ctx = dd.Context(p, U)
+    x0, _, st0 = ctx.solve(mus, b)
+    s0 = ctx.stats()
+    assert s0["n_sap_kernels"] == 0 and s0["sap_kernel_ms"] == 0.0
+    ctx.set_tuning("time_sap", 1)
+    x1, info, st1 = ctx.solve(mus, b)
+    s1 = ctx.stats()
+    say(f"SAP kernel timing: {s1['n_sap_kernels']} launches, {s1['sap_kernel_ms']:.3f} ms, "
+        f"{s1['n_sap_kernel_tiles']} tiles, {s1['n_sap_calls']} SAP calls")
+    assert st0 == st1 == dd.OK
+    assert s1["n_sap_kernels"] == 2 * s1["n_sap_calls"] > 0
+    assert s1["n_sap_kernel_tiles"] >= s1["n_sap_kernels"] and s1["sap_kernel_ms"] > 0
+    assert s1["outer_iters"] == s0["outer_iters"] and s1["n_inner_iters"] == s0["n_inner_iters"]
+    assert torch.equal(x0, x1)
+    ctx.close()
+
+
 def test_two_level_solve_with_oddeven_smoother(torch_cuda, dd):
     """The odd-even SAP as the fine smoother of the two-level K-cycle (4^4 SAP
     blocks = aggregates): every column reaches the oracle's FP64 residual."""
