@@ -121,6 +121,10 @@ typedef struct ddamg_params {
                              /* sigma_{mu nu} F_{mu nu} (clover-leaf F); 0 = no clover term       */
   int    sap_oddeven;        /* 1: SAP block solves run MR on the odd-even reduced block systems */
                              /* (4^4 blocks, c_sw = 0); 0: MR on the full block systems         */
+  int    coarse_gamma5;      /* Krylov solves of the MG cycle on the gamma5-Hermitian form      */
+                             /* gamma5_c D_c(mu) = Q_c + i dmu mu (same solution, same residual */
+                             /* norm; the shifted-Hermitian operator is normal): 0 = off,       */
+                             /* 1 = the coarsest level, 2 = every coarse level                  */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

@@ -53,6 +53,7 @@ class MGParams:
     bottom_maxit: int = 100
     coarse_smooth_iters: int = 2        # MR steps of the middle-level smoother
     coarsest_block: bool = False
+    coarse_gamma5: int = 0              # Krylov on gamma5_c D_c: 0 off, 1 coarsest, 2 every coarse level
 
 
 class OracleMG:
@@ -105,22 +106,28 @@ class OracleMG:
         lev, nxt = self.levels[l], self.levels[l + 1]
         rc = restrict(self.P[l], self.blockings[l], r)
         bottom = (l + 2 == len(self.levels))
+        # gamma5-Hermitian form: gamma5_c D_c(mu) e_c = gamma5_c r_c has the same
+        # solution and residual norm; its operator Q_c + i dmu mu is normal
+        g5 = p.coarse_gamma5 >= (1 if bottom else 2)
+        op = (lambda x, m: nxt.twist(nxt.apply(x, m))) if g5 else nxt.apply
+        rhs = nxt.twist(rc) if g5 else rc
         if bottom:
             if p.coarsest_block:
                 ec = np.zeros_like(rc)
                 for mu in np.unique(mus):
                     idx = np.nonzero(mus == mu)[0]
-                    sol, info = block_gmres(lambda x, m=mu: nxt.apply(x, np.full(x.shape[0], m)),
-                                            rc[idx], p.r_b, p.bottom_maxit)
+                    sol, info = block_gmres(lambda x, m=mu: op(x, np.full(x.shape[0], m)),
+                                            rhs[idx], p.r_b, p.bottom_maxit)
                     ec[idx] = sol
                     self.stats["bottom_iters"].append(info["iters"])
             else:
-                ec, info = gmres(lambda x, act: nxt.apply(x, mus[act]), rc, p.r_b, p.bottom_maxit)
+                ec, info = gmres(lambda x, act: op(x, mus[act]), rhs, p.r_b, p.bottom_maxit)
                 self.stats["bottom_iters"].extend(list(info["iters"]))
         else:
-            ec, info = fgmres(lambda x, act: nxt.apply(x, mus[act]),
-                              lambda x, act: self.cycle(l + 1, x, mus[act]),
-                              rc, p.r_m, p.middle_restart, p.middle_maxit)
+            # a preconditioner of gamma5_c D_c approximates D_c^-1 gamma5_c
+            pre = (lambda x, act: self.cycle(l + 1, nxt.twist(x), mus[act])) if g5 else \
+                  (lambda x, act: self.cycle(l + 1, x, mus[act]))
+            ec, info = fgmres(lambda x, act: op(x, mus[act]), pre, rhs, p.r_m, p.middle_restart, p.middle_maxit)
             self.stats["middle_iters"].extend(list(info["iters"]))
         e = prolong(self.P[l], self.blockings[l], ec)
         res = r - lev.apply(e, mus)

@@ -71,6 +71,7 @@ class Params(ctypes.Structure):
         ("verbose", ctypes.c_int),
         ("csw", ctypes.c_double),
         ("sap_oddeven", ctypes.c_int),
+        ("coarse_gamma5", ctypes.c_int),
     ]
 
 

@@ -99,6 +99,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->verbose = 0;
   p->csw = 0.0;
   p->sap_oddeven = 0;
+  p->coarse_gamma5 = 0;
 }
 
 static void validate(const ddamg_params* p) {
@@ -107,6 +108,7 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->kappa > 0, DDAMG_EINVAL, "kappa must be positive");
   DD_CHECK(std::isfinite(p->csw), DDAMG_EINVAL, "csw must be finite");
   DD_CHECK(p->sap_oddeven == 0 || p->sap_oddeven == 1, DDAMG_EINVAL, "sap_oddeven must be 0 or 1");
+  DD_CHECK(p->coarse_gamma5 >= 0 && p->coarse_gamma5 <= 2, DDAMG_EINVAL, "coarse_gamma5 must be 0, 1 or 2");
   DD_CHECK(!p->sap_oddeven || (p->csw == 0.0 && p->sap_block[0] == 4 && p->sap_block[1] == 4 &&
                                p->sap_block[2] == 4 && p->sap_block[3] == 4),
            DDAMG_EINVAL, "odd-even SAP needs 4^4 blocks and no clover term");
@@ -708,6 +710,11 @@ int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
       }
       c->sap_variant = bv;
     }
+    // the timing runs sized the Krylov and smoother workspaces for n_col
+    // columns at once; a solve that holds fewer columns in flight (large
+    // lattices) sizes its own
+    DD_HIP(hipStreamSynchronize(c->stream));
+    free_work(c);
     if (values)
       for (int k = 0; k < DDAMG_N_KNOBS; ++k) values[k] = *knob_slot(c, k);
     return DDAMG_OK;

@@ -378,6 +378,31 @@ void mv_add(ddamg_ctx* c, const MV& x, const MV& y) {
   DD_HIP(hipGetLastError());
 }
 
+// x <- gamma5 x on any level: the complex components of chirality -1 (the
+// second half of the dof of a site: spins 2, 3 on the fine level, the last N
+// of the 2N coarse dof) change sign.
+template <typename R>
+__global__ void k_gamma5(R* __restrict__ x, size_t n, size_t plane, int RW, int dof) {
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    const size_t in_tile = q % ((size_t)plane * (size_t)(2 * dof / RW));
+    const int k = (int)(in_tile / plane);                  // chunk
+    const int ci = k * (RW / 2) + (int)(q % RW) / 2;       // complex component
+    if (ci >= dof / 2) x[q] = -x[q];
+  }
+}
+
+void mv_gamma5(ddamg_ctx* c, const MV& x) {
+  DD_CHECK(x.prec == P64 || x.prec == P32, DDAMG_EINVAL, "mv_gamma5: FP64 or FP32 only");
+  const size_t n = x.reals();
+  const int RW = reals_per_chunk(x.prec);
+  const size_t plane = (size_t)x.nsites * x.T * RW;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_gamma5<double>, grid_for(n), dim3(256), 0, c->stream, x.as<double>(), n, plane, RW, x.dof);
+  else
+    hipLaunchKernelGGL(k_gamma5<float>, grid_for(n), dim3(256), 0, c->stream, x.as<float>(), n, plane, RW, x.dof);
+  DD_HIP(hipGetLastError());
+}
+
 static inline size_t npairs_of(const MV& a) { return a.reals() / 2; }
 static inline size_t tile_pairs_of(const MV& a) { return a.tile_reals() / 2; }
 

@@ -34,11 +34,13 @@ __device__ __forceinline__ void store_one(R* __restrict__ tile, int nsites, int 
 // ------------------------------------------------------- coarse stencil ---
 // MODE 0: full operator with twist; MODE 1: self block + hops internal to the
 // grouping of this level (no twist); MODE 2: single hop `hopi` if it leaves
-// the group of the site.
+// the group of the site.  g5o = 1 (MODE 0 only) applies gamma5_c to the
+// result: y = gamma5_c D_c(mu) x = gamma5_c D_c(0) x + i dmu mu x, the
+// Hermitian form of the coarse operator shifted by i dmu mu.
 template <typename R, int MODE>
 __global__ void k_coarse(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ blk,
                          const int* __restrict__ nbr, const double* __restrict__ mu, double muf, int V, int d,
-                         size_t tile_reals, int gsize, int hopi) {
+                         size_t tile_reals, int gsize, int hopi, int g5o) {
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int s = wg % V;
   const int tile = wg / V;
@@ -59,7 +61,9 @@ __global__ void k_coarse(const R* __restrict__ x, R* __restrict__ y, const R* __
   }
   if constexpr (MODE == 0) {
     const cx<R> xs = load_one(xt, V, TC, s, t, i);
-    const R m = (R)(muf * mu[tile * TC + t]) * (i < d / 2 ? (R)1 : (R)-1);
+    const R g5 = i < d / 2 ? (R)1 : (R)-1;
+    if (g5o) acc = g5 * acc;
+    const R m = (R)(muf * mu[tile * TC + t]) * (g5o ? (R)1 : g5);
     acc.re -= m * xs.im;
     acc.im += m * xs.re;
   }
@@ -113,7 +117,7 @@ template <int MFMA_GPW>
 __global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x, float* __restrict__ y,
                                                      const bf16x8* __restrict__ A, const int* __restrict__ nbr,
                                                      const double* __restrict__ mu, double muf, int V, int d,
-                                                     size_t tile_reals, int ntiles) {
+                                                     size_t tile_reals, int ntiles, int g5o) {
   const int ngrp = (ntiles + 1) / 2;
   const int nwgc = (ngrp + MFMA_GPW - 1) / MFMA_GPW;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -163,7 +167,9 @@ __global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x
       }
     }
   }
-  // twist i dmu mu gamma5_c on the site's own x (FP32), then store
+  // twist i dmu mu gamma5_c on the site's own x (FP32), then store; with
+  // g5o the rows of chirality -1 change sign and the twist becomes i dmu mu
+  // on every row (the Hermitian form gamma5_c D_c)
 #pragma unroll
   for (int g = 0; g < MFMA_GPW; ++g) {
     if (g >= ng) break;
@@ -177,9 +183,10 @@ __global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * w + 4 * kb + r;
       const size_t o = (((size_t)(i / 2) * V + s) * TC + t) * 4 + (i % 2) * 2;
-      const float gm = i < d / 2 ? m : -m;
-      yt[o] = accr[g][r] - gm * xt[o + 1];
-      yt[o + 1] = acci[g][r] + gm * xt[o];
+      const float sg = (g5o && i >= d / 2) ? -1.f : 1.f;
+      const float gm = (g5o || i < d / 2) ? m : -m;
+      yt[o] = sg * accr[g][r] - gm * xt[o + 1];
+      yt[o + 1] = sg * acci[g][r] + gm * xt[o];
     }
   }
   (void)nwgc;
@@ -199,11 +206,11 @@ void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const doubl
       const int nwgc = (ngrp + 3) / 4;
       hipLaunchKernelGGL(k_coarse_mfma<4>, dim3(g.V * nwgc), dim3(64 * (d / 16)), 0, c->stream, x.as<float>(),
                          y.as<float>(), (const bf16x8*)c->coarse[level].d_blk16, g.d_nbr, d_mu,
-                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles);
+                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles, c->coarse[level].g5out);
     } else {
       hipLaunchKernelGGL(k_coarse_mfma<1>, dim3(g.V * ngrp), dim3(64 * (d / 16)), 0, c->stream, x.as<float>(),
                          y.as<float>(), (const bf16x8*)c->coarse[level].d_blk16, g.d_nbr, d_mu,
-                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles);
+                         c->coarse[level].mu_factor, g.V, d, x.tile_reals(), x.ntiles, c->coarse[level].g5out);
     }
     DD_HIP(hipGetLastError());
     return;
@@ -212,11 +219,11 @@ void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const doubl
   if (x.prec == P64)
     hipLaunchKernelGGL((k_coarse<double, 0>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
                        c->coarse[level].d_blk64, g.d_nbr, d_mu, c->coarse[level].mu_factor, g.V, d, x.tile_reals(),
-                       g.gsize, 0);
+                       g.gsize, 0, c->coarse[level].g5out);
   else
     hipLaunchKernelGGL((k_coarse<float, 0>), grid, blk, 0, c->stream, x.as<float>(), y.as<float>(),
                        c->coarse[level].d_blk32, g.d_nbr, d_mu, c->coarse[level].mu_factor, g.V, d, x.tile_reals(),
-                       g.gsize, 0);
+                       g.gsize, 0, c->coarse[level].g5out);
   DD_HIP(hipGetLastError());
 }
 
@@ -227,10 +234,10 @@ void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, 
   dim3 grid(g.V * x.ntiles), blk(d * TC);
   if (mode == 0)
     hipLaunchKernelGGL((k_coarse<double, 1>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
-                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, 0);
+                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, 0, 0);
   else
     hipLaunchKernelGGL((k_coarse<double, 2>), grid, blk, 0, c->stream, x.as<double>(), y.as<double>(),
-                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, hopi);
+                       c->coarse[level].d_blk64, g.d_nbr, nullptr, 0.0, g.V, d, x.tile_reals(), g.gsize, hopi, 0);
   DD_HIP(hipGetLastError());
 }
 

@@ -110,6 +110,7 @@ struct Coarse {
   float* d_blk32 = nullptr;
   void* d_blk16 = nullptr;    // BF16 blocks in the MFMA operand layout (d % 16 == 0)
   double mu_factor = 1.0;
+  int g5out = 0;              // 1: the stencil applies gamma5_c D_c(mu) (Hermitian form + i dmu mu)
 };
 
 // Simple device allocation pool: every buffer is released at context destruction.
@@ -194,6 +195,7 @@ void mv_xpay(ddamg_ctx* c, const MV& x, const double* d_alpha, const MV& y);  //
 void mv_scale(ddamg_ctx* c, const double* d_alpha, const MV& x);  // x *= alpha_c (complex)
 void mv_sub(ddamg_ctx* c, const MV& a, const MV& b, const MV& out);   // out = a - b
 void mv_add(ddamg_ctx* c, const MV& x, const MV& y);                  // y += x
+void mv_gamma5(ddamg_ctx* c, const MV& x);                            // x <- gamma5 x (in place)
 void mv_copy_kernel(ddamg_ctx* c, const MV& s, const MV& d);          // plain copy kernel
 void mv_gather_cols(ddamg_ctx* c, const MV& full, const MV& comp, const int* d_map, int dir);
 // per-column complex dots <V_j, w> for j < k, written to d_out[j*ncol + c] (complex)

@@ -121,7 +121,7 @@ struct LW {
 // by the workspace, so the recorded pointers stay valid until the workspace
 // is reallocated (which destroys the graphs).
 struct GraphState {
-  int nt = -1, m = 0, ncol = 0;
+  int nt = -1, m = 0, ncol = 0, g5 = 0;
   int knobs[6] = {0, 0, 0, 0, 0, 0};
   double *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr, *d_tol = nullptr, *d_est = nullptr;
   double *d_n2 = nullptr, *d_cbuf = nullptr, *d_part = nullptr, *d_mu = nullptr, *d_coef = nullptr;
@@ -587,13 +587,15 @@ static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {
   int k[6];
   knob_state(c, k);
   GraphState* g = w.gs;
-  const bool same = g && g->nt == nt && g->m == m && std::equal(k, k + 6, g->knobs);
+  const int g5 = level > 0 ? c->coarse[level].g5out : 0;
+  const bool same = g && g->nt == nt && g->m == m && g->g5 == g5 && std::equal(k, k + 6, g->knobs);
   if (same) return *g;
   destroy_graphs(c, g);
   g = new GraphState();
   w.gs = g;
   g->nt = nt;
   g->m = m;
+  g->g5 = g5;
   g->ncol = nt * c->T;
   std::copy(k, k + 6, g->knobs);
   const size_t n = g->ncol;
@@ -1013,7 +1015,21 @@ static void mr_smooth(ddamg_ctx* c, int level, const double* d_mu, const MV& f, 
   }
 }
 
+// Sets the gamma5-output flag of a coarse level for the lifetime of the
+// object (restored on every exit path).
+struct G5Scope {
+  ddamg_ctx* c;
+  int level, saved;
+  G5Scope(ddamg_ctx* c_, int l, int on) : c(c_), level(l), saved(c_->coarse[l].g5out) { c->coarse[l].g5out = on; }
+  ~G5Scope() { c->coarse[level].g5out = saved; }
+};
+
 // e = MG_l(r): restrict, solve the next level, prolong, post-smooth.
+// With coarse_gamma5 the Krylov solves of the next level run on
+// gamma5_c D_c(mu) e_c = gamma5_c r_c, whose operator Q_c + i dmu mu (Q_c the
+// Hermitian gamma5_c D_c(0)) is normal: same solution and residual norm,
+// but GMRES is not slowed by the non-normality of D_c.  A middle-level
+// preconditioner then approximates (gamma5_c D_c)^-1 = D_c^-1 gamma5_c.
 void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e) {
   const int nt = r.ntiles, prec = r.prec;
   LW& w = lw(c, l, prec, nt);
@@ -1022,19 +1038,35 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
   restrict_mv(c, l, r, rc);
   KrylovOut ko;
   const bool bottom = (l + 2 == c->nlev);
+  const bool g5 = c->p.coarse_gamma5 >= (bottom ? 1 : 2);
+  if (g5) mv_gamma5(c, rc);
   if (bottom && c->p.coarsest_block) {
+    G5Scope gs(c, l + 1, g5);
     int total = 0;
     block_gmres(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
                 nullptr, nullptr, &total);
     c->st.bottom_calls++;
     c->st.bottom_iters += total;
   } else if (bottom) {
+    G5Scope gs(c, l + 1, g5);
     krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
            nullptr, prec, false, &ko);
     c->st.bottom_calls++;
     c->st.bottom_iters += ko.total;
   } else {
-    Precond pc = [&](const MV& v, const MV& z, const double* dm) { mg_cycle(c, l + 1, dm, v, z); };
+    G5Scope gs(c, l + 1, g5);
+    Precond pc = [&](const MV& v, const MV& z, const double* dm) {
+      if (!g5) {
+        mg_cycle(c, l + 1, dm, v, z);
+        return;
+      }
+      // z = MG_{l+1}(gamma5 v): the cycle sees the plain operator D_{l+1};
+      // v is flipped in place and restored (the cycle only reads it)
+      G5Scope plain(c, l + 1, 0);
+      mv_gamma5(c, v);
+      mg_cycle(c, l + 1, dm, v, z);
+      mv_gamma5(c, v);
+    };
     krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_m, std::min(c->p.middle_restart, KMAX - 1), c->p.middle_maxit, &pc,
            prec, false, &ko);
     c->st.middle_calls++;
@@ -1199,6 +1231,16 @@ void bootstrap(ddamg_ctx* c) {
 void build_hierarchy(ddamg_ctx* c, const double* const* tv_init) {
   for (int l = 0; l + 1 < c->nlev; ++l) setup_transition(c, l, tv_init ? tv_init[l] : nullptr);
   if (c->nlev > 1 && c->p.setup_boot > 0) bootstrap(c);
+  // the setup smooths all N test vectors at once in FP64: its Krylov and
+  // cycle workspaces are sized for N columns, far more than a solve of a
+  // large lattice can afford next to its own; drop them (the solve sizes
+  // its workspaces for its own column tiles)
+  DD_HIP(hipStreamSynchronize(c->stream));
+  free_work(c);
+  free_block_work(c);
+  // the smoothed test vectors served the bootstrap only (P holds their
+  // orthonormalised form)
+  for (int l = 0; l < 2; ++l) mv_free(c, c->tvk[l]);
 }
 
 // Rebuild from host test vectors (canonical layout) of transition l.

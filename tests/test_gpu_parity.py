@@ -387,6 +387,43 @@ def test_solve_three_level(torch_cuda, dd, precision, block):
     assert np.all(rel <= 1e-10 * (1 + 1e-6))
 
 
+@pytest.mark.parametrize("precision,g5,block", [(0, 1, 0), (1, 1, 0), (1, 2, 0), (1, 2, 1)])
+def test_solve_three_level_gamma5_coarse(torch_cuda, dd, precision, g5, block):
+    """Coarse Krylov solves on the gamma5-Hermitian form gamma5_c D_c(mu)
+    (coarsest level, or every coarse level): every column reaches the true
+    FP64 residual 1e-10 by the oracle's operator."""
+    w = S.workload("tm_8x8x8x8_3level")
+    say("solve", w.name, "precision", precision, "coarse_gamma5", g5, "block", block)
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision, coarse_gamma5=g5, coarsest_block=block)
+    assert st == dd.OK
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+
+
+def test_gamma5_middle_level_equivalence(torch_cuda, dd):
+    """On the middle level the gamma5 form (FGMRES on gamma5_c D_c with the
+    right preconditioner MG(gamma5_c v)) is the plain middle iteration times
+    the unitary gamma5_c: with the gamma5 form on the coarsest level in both
+    runs the iteration counts are identical and the solutions agree to FP64
+    rounding (the oracle pins the same identity)."""
+    torch = torch_cuda
+    w = S.workload("tm_8x8x8x8_3level")
+    say("gamma5 middle-level equivalence", w.name)
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    b = torch.from_numpy(S.rhs_for(w)).cuda()
+    out = []
+    for g5 in (1, 2):
+        ctx = dd.Context(dd.params_for_workload(w, precision=dd.PLAIN_FP64, coarse_gamma5=g5),
+                         U, tv_init=S.setup_start_vectors(w))
+        x, info, st = ctx.solve(np.array(w.mus), b)
+        out.append((x.cpu().numpy(), [i["outer_iters"] for i in info], ctx.stats()))
+        ctx.close()
+    (xa, ia, sa), (xb, ib, sb) = out
+    assert ia == ib
+    assert sa["n_middle_solves"] == sb["n_middle_solves"] and sa["avg_middle_iters"] == sb["avg_middle_iters"]
+    assert sa["avg_bottom_iters"] == sb["avg_bottom_iters"]
+    assert np.max(relerr_cols(xb, xa)) < 1e-9
+
+
 def test_error_paths(torch_cuda, dd):
     torch = torch_cuda
     say("error paths")

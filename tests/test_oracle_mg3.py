@@ -10,7 +10,12 @@
   e = P D_c^-1 R r + S(r - D P D_c^-1 R r) with S the level's smoother, on
   the middle level (S = MR steps) and on the fine level (S = SAP);
 * the three-level solve reaches the 1e-10 true residual and agrees with dense
-  LU within cond * 1e-10, with per-column and with block GMRES at the bottom.
+  LU within cond * 1e-10, with per-column and with block GMRES at the bottom;
+* the gamma5-Hermitian form of the coarse solves: gamma5_c D_c(mu) - i mu is
+  Hermitian (so the Krylov operator is normal); with exact coarse solves the
+  cycle is unchanged; on the middle level the form is an exact equivalence
+  (right preconditioner MG(gamma5 v)), so the middle iterations and the cycle
+  output equal those of the plain middle level step for step.
 """
 import numpy as np
 import pytest
@@ -89,22 +94,24 @@ def test_mr_smoother_coarse_level_is_least_squares():
         assert all(n1 <= n0 * (1 + 1e-14) for n0, n1 in zip(norms, norms[1:]))
 
 
-def _three_level(block=False, r_m=7e-2, r_b=1e-1, kappa=0.14, seed=51):
+def _three_level(block=False, r_m=7e-2, r_b=1e-1, kappa=0.14, seed=51, g5=0):
     dims = (4, 4, 4, 4)
     U = S.gauge_field(dims, 0.3, seed)
     p = O.MGParams(agg=((2, 2, 2, 2), (2, 2, 2, 2)), n_tv=(8, 8), sap_block=(2, 2, 2, 2),
                    sap_cycles=2, sap_mr=4, mu_setup=0.01, r_m=r_m, r_b=r_b,
                    middle_maxit=200, middle_restart=200, bottom_maxit=200,
-                   coarse_smooth_iters=2, coarsest_block=block)
+                   coarse_smooth_iters=2, coarsest_block=block, coarse_gamma5=g5)
     start = [S.gaussian_spinors(8, 256, seed + 1).reshape(8, 256, 12),
              S.gaussian_coarse(8, 16, 16, seed + 2)]
     return O.OracleMG(U, dims, kappa, p).setup(start)
 
 
-def test_three_level_cycle_equals_dense_formula():
+@pytest.mark.parametrize("g5", [0, 2])
+def test_three_level_cycle_equals_dense_formula(g5):
     """With the middle and bottom solves driven to rounding level the cycle's
-    output is fixed by dense linear algebra on every level."""
-    mg = _three_level(r_m=1e-13, r_b=1e-13)
+    output is fixed by dense linear algebra on every level, whichever form
+    (plain or gamma5-Hermitian) the coarse Krylov solves take."""
+    mg = _three_level(r_m=1e-13, r_b=1e-13, g5=g5)
     assert [lv.V for lv in mg.levels] == [256, 16, 1]
     mus = np.array([0.01, 0.3])
     lev0, lev1, lev2 = mg.levels
@@ -154,3 +161,27 @@ def test_three_level_solve_matches_dense_lu(block):
     cond = np.linalg.cond(D)
     for c in range(2):
         assert np.linalg.norm(x[c].reshape(-1) - xs[c]) <= cond * 1e-10 * np.linalg.norm(xs[c])
+
+
+def test_gamma5_coarse_operator_is_shifted_hermitian():
+    mg = _three_level()
+    for lev in mg.levels[1:]:
+        n = lev.V * lev.d
+        for mu in (0.0, 0.05):
+            Q = dense_of(lambda E: lev.twist(lev.apply(E, np.full(E.shape[0], mu))), n, (lev.V, lev.d))
+            H = Q - 1j * mu * np.eye(n)
+            assert np.max(np.abs(H - H.conj().T)) < 1e-14 * np.max(np.abs(H))
+
+
+def test_gamma5_middle_level_is_an_exact_equivalence():
+    """FGMRES on gamma5 D_1 with the right preconditioner MG_2(gamma5 v) runs
+    the plain middle iteration multiplied by gamma5 (a unitary map), so with
+    the same bottom solver (gamma5 form in both) the iterations and the cycle
+    output are the same."""
+    a, b = _three_level(g5=1), _three_level(g5=2)
+    mus = np.array([0.01, 0.2])
+    r = S.gaussian_spinors(2, 256, 55).reshape(2, 256, 12)
+    ea, eb = a.cycle(0, r, mus), b.cycle(0, r, mus)
+    assert a.stats["middle_iters"] == b.stats["middle_iters"]
+    assert a.stats["bottom_iters"] == b.stats["bottom_iters"]
+    assert np.max(np.abs(ea - eb)) < 1e-9 * np.max(np.abs(ea))
