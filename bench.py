@@ -1,24 +1,33 @@
 """Benchmark: simultaneous multi-rhs x multi-shift twisted-mass solves on one MI355X.
 
-Workload: 16^3x32 lattice, seeded links exp(i 0.3 H), kappa = 0.150, 12 Z2-noise
-right-hand sides x 4 twisted masses {0.002, 0.01, 0.03, 0.1} = 48 columns.
-One step = one ddamg_solve of all 48 columns to a true FP64 relative residual
-<= 1e-10 per column (flexible GMRES in FP64, FP32 preconditioner).  The
-right-hand sides are resident in HBM before the timed region; the context
-(gauge field in the internal layouts, autotuned tile shapes) is built once
-before it, as it is shared by every solve on this gauge field.
+Headline workload: the 40^3x80 lattice (one GPU's share of an 80^3x160 run),
+seeded links exp(i 0.35 H), kappa = 0.152, 4 Gaussian right-hand sides x 8
+twisted masses log-spaced in [7e-4, 0.5] = 32 columns.  One step = one
+ddamg_solve of all 32 columns to a true FP64 relative residual <= 1e-10 per
+column.  The right-hand sides are resident in HBM before the timed region;
+the context (gauge field in the internal layouts, the multigrid hierarchy,
+autotuned tile shapes) is built once before it and shared by every solve on
+this gauge field.
+
+Solver (paper sections 2 and 4): FP64 flexible GMRES preconditioned by the
+aggregation multigrid cycle with red-black SAP; the coarse solves run GMRES on
+the gamma5-Hermitian form of the coarse operator.  The tuned form runs the
+cycle in FP32 with the coarse stencil on BF16 MFMA; the plain form runs the
+same method in FP64.  Columns are solved 8 at a time (memory), converged
+columns leave the batch.
 
 Printed JSON: value = converged rhs x shift solves per second of the tuned
-form; the plain FP64 GPU form of the same method; the roofline of the
+form; the plain FP64 form of the same method; the three-level hierarchy; the
+16^3x32 workload in its one-, two- and three-level forms; the roofline of the
 dominant kernel measured live with HIP events on the library's stream; the
-same workload with a clover term (c_sw = 1.0); and the FP64 oracle timed on
-the host on a bounded sample.
+fine stencil's bandwidth; and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,184 +35,252 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "tm_16x16x16x32_12rhs_4shift"
+BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+WORKLOAD = "tm_40x40x40x80_4rhs_8shift"
+SMALL = "tm_16x16x16x32_12rhs_4shift"
 
-# Solver of the plain FP64 form: FP64 FGMRES(40) preconditioned by FP64 SAP.
-# At kappa = 0.150 these seeded fields are past the critical hopping
-# parameter; the measured study (see the design notes) found that SAP with one
-# red-black cycle and 12 block-MR steps preconditions best, and that the
-# aggregation hierarchy does not reduce the outer iteration count there.
-SOLVER = dict(n_levels=1, sap_cycles=1, sap_mr_iters=12, outer_restart=40, max_outer=3000)
-# The tuned form: FP64 FGMRES(4) whose every step is an FP32 inner FGMRES of
-# up to 40 steps (to 1e-2, Arnoldi basis stored in FP16) around FP32 SAP whose
-# block solves take 4 MR steps on the odd-even reduced block systems (the
-# measured optimum: as few FGMRES steps as 10 MR steps on the full blocks);
-# the outer FP64 iteration wins the accuracy back, and its restart every 4
-# steps lets converged columns leave the batch.
-TUNED = dict(SOLVER, outer_restart=4, inner_iters=40, inner_tol=1e-2, inner_fp16=1, sap_mr_iters=4, sap_oddeven=1)
-# the clover form: odd-even block solves are for the clover-free operator, so
-# its SAP takes 10 MR steps on the full blocks
-CLOVER_SOLVER = dict(TUNED, sap_oddeven=0, sap_mr_iters=10)
+# Two-level aggregation multigrid (4^4 aggregates, 24 test vectors, one
+# bootstrap round), one red-black SAP cycle with 4 MR steps on the odd-even
+# reduced 4^4 blocks, coarse GMRES on the gamma5-Hermitian form to 0.1.
+MG2 = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds=3, setup_boot=1,
+           coarse_gamma5=1, bottom_maxit=100, inner_iters=0)
+# 40^3x80: FP64 FGMRES(4) over the cycle, 8 columns in flight (HBM budget)
+TUNED = dict(MG2, outer_restart=4, max_outer=300, max_active_cols=8)
+# the three-level hierarchy of the workload definition (4^4 then 2^4
+# aggregates, 24 / 32 test vectors): middle FGMRES to 7e-2, coarsest GMRES to 0.1
+THREE = dict(TUNED, n_levels=3, middle_restart=25, middle_maxit=50)
+# 16^3x32 forms: one-level (FP64 FGMRES(4) over an FP32 FGMRES(40) with an FP16
+# basis around SAP), two- and three-level (FP64 FGMRES(40) over the cycle)
+SMALL_ONE = dict(n_levels=1, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, outer_restart=4, inner_iters=40,
+                 inner_tol=1e-2, inner_fp16=1, max_outer=3000)
+SMALL_TWO = dict(MG2, outer_restart=40, max_outer=400)
+SMALL_THREE = dict(SMALL_TWO, n_levels=3, middle_restart=25, middle_maxit=50)
+
+# the kernel classes the library can time live (ddamg.h, DDAMG_KNOB_TIME_SAP)
+TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
+# roofline kernel of the tuned solve: the level-1 coarse stencil (BF16 MFMA),
+# the largest share of the solve's kernel time in the committed trace
+ROOFLINE_CLASS = "coarse1"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sap_oe_fp32_16x16x16x32_48col.md")
-# the FP32 SAP half-sweep kernel of each autotuner variant (4^4 blocks) as it
-# runs inside the inner Krylov solve, and the time_op form that launches it:
-# variants 2 (2-row links) and 3 (full links) read their right-hand side
-# straight from the FP16 Arnoldi basis (op 6; the profiler lists those
-# instantiations by their mangled names); with odd-even block solves one
-# kernel (2-row links) serves every variant
-SAP_KERNELS = {0: ("k_sap_half<float, 2, 2, 256, true, float, false>", 1),
-               1: ("k_sap_half<float, 2, 2, 256, false, float, false>", 1),
-               2: ("_ZN5ddamg10k_sap_halfIfLi2ELi1ELi256ELb0EDF16_Lb0EEE", 6),
-               3: ("_ZN5ddamg10k_sap_halfIfLi1ELi1ELi256ELb0EDF16_Lb0EEE", 6)}
-SAP_OE_KERNEL = ("_ZN5ddamg8k_sap_oeIfLi2EDF16_Li2EEE", 6)
+def coarse1_bytes_flops(Vc, d, ncol_tiles):
+    """Algorithmic bytes and flops of one launch of the level-1 coarse stencil
+    on BF16 MFMA: the 9 blocks of each coarse site once in the MFMA operand
+    form [Re A | Im A] (d x 2d BF16, 4 d^2 bytes per block), the FP32 input
+    and output vectors (8 bytes per complex, 8 columns per tile); flops 8 per
+    complex multiply-add, 9 d^2 per site and column."""
+    ncol = 8 * ncol_tiles
+    bytes_ = Vc * (9 * 4 * d * d + 2 * 8 * d * ncol)
+    flops = Vc * 9 * d * d * 8 * ncol
+    return bytes_, flops
 
 
-def sap_kernel(solver, variant):
-    """(kernel name, time_op form) of the SAP half sweep a solver runs."""
-    if solver.get("sap_oddeven"):
-        return SAP_OE_KERNEL
-    return SAP_KERNELS[variant]
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2201_03872_amd", "csrc", "fine.hip")
-# SAP calls timed for the roofline (after one untimed call)
-SAP_TIMED_CALLS = 10
-# clover coefficient of the twisted-mass clover form measured beside the headline
-CLOVER_CSW = 1.0
+def run_form(dd, torch, w, U, b, mus, precision, solver, steps, warmup_rhs, tune_cols, timed_class=None,
+             label=""):
+    """Context + autotune, one untimed solve of `warmup_rhs` right-hand sides
+    (allocates the workspaces a wave of columns needs), then `steps` timed
+    solves of all columns."""
+    p = dd.params_for_workload(w, precision=precision, **solver)
+    t0 = time.time()
+    ctx = dd.Context(p, U)
+    t_h = time.time() - t0
+    tuned = ctx.autotune(tune_cols)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log(f"  {label}: hierarchy {t_h:.1f}s, context + autotune {setup_s:.1f}s")
+    if warmup_rhs:
+        ctx.solve(mus, b[:warmup_rhs].contiguous())
+        log(f"  {label}: warm-up solve done")
+    if timed_class:
+        ctx.set_tuning("time_kernel", TIMED[timed_class])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    allconv, worst, iters = True, 0.0, []
+    for i in range(steps):
+        x, info, st = ctx.solve(mus, b)
+        allconv &= all(c["converged"] for c in info)
+        worst = max(worst, max(c["true_rel_res"] for c in info))
+        iters = [c["outer_iters"] for c in info]
+        log(f"  {label}: step {i} done ({time.time() - t0:.2f}s)")
+    torch.cuda.synchronize()
+    el = time.time() - t0
+    stats = ctx.stats()
+    if timed_class:
+        ctx.set_tuning("time_kernel", 0)
+    ncol = len(iters)
+    return ctx, dict(setup_s=setup_s, hierarchy_s=t_h, elapsed=el, allconv=allconv, worst=worst, stats=stats,
+                     tuned=tuned, outer_iters_max=max(iters), outer_iters_mean=sum(iters) / ncol,
+                     solves_per_s=(ncol * steps / el) if allconv else 0.0, x=x)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the SAP half sweep from the committed counter
-    summary, valid only for the same kernel variant while its source is
-    unchanged (else None)."""
-    import hashlib
-    try:
-        note = open(TRAFFIC_NOTE).read()
-    except OSError:
-        return None
-    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    keys = ("kernel_source_sha256", "traffic_bytes_per_launch", "kernel:")
-    fields = dict(line.split(":", 1) for line in note.splitlines() if line.startswith(keys))
-    if fields.get("kernel_source_sha256", "").strip() != digest or fields.get("kernel", "").strip() != kernel:
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def summary(r, precision_note):
+    s = r["stats"]
+    return {"solves_per_s": r["solves_per_s"], "seconds_per_solve_call": r["elapsed"], "all_converged": r["allconv"],
+            "worst_true_rel_res": r["worst"], "outer_iters_max": r["outer_iters_max"],
+            "outer_iters_mean": r["outer_iters_mean"], "avg_bottom_iters": s["avg_bottom_iters"],
+            "n_bottom_solves": s["n_bottom_solves"], "avg_middle_iters": s["avg_middle_iters"],
+            "n_middle_solves": s["n_middle_solves"], "inner_iters": s["n_inner_iters"],
+            "setup_s": r["setup_s"], "hierarchy_s": r["hierarchy_s"], "precision": precision_note}
 
 
-def sap_oe_flops_per_half_sweep(V, ncol, mr):
-    """Algorithmic flops of one half sweep of SAP with odd-even reduced block
-    solves, averaged over the two half sweeps of a one-cycle call, counted per
-    pair of an even and an odd site of the active blocks (V / 4 pairs):
-
-    * each MR step applies the Schur complement: the in-block hops of the even
-      site (6 on average, 165 flop each), D_ee^-1 (72), the in-block hops of
-      the odd site, D_oo (72) and the hop sum (48); then the inner products
-      (144) and the two axpys (192) on the odd site: 2508;
-    * once: the right-hand side r_o - D_oe D_ee^-1 r_e and the back
-      substitution of x_e (6 hops, 48 and 72 each: 2220), and the block
-      residual (none in the first half sweep; the 2 block-leaving hops of each
-      of the two sites in the second: 660, counted once although the kernel
-      evaluates the even one twice)."""
-    hop = 1320 / 8
-    step = 12 * hop + 72 + 72 + 48 + 144 + 192
-    per_pair = mr * step + 2 * (6 * hop + 48 + 72) + 0.5 * (2 * 2 * hop)
-    return V / 4 * ncol * per_pair
-
-
-def sap_flops_per_half_sweep(V, ncol, mr, clover=False):
-    """Algorithmic flops of one red-black SAP half sweep (half the sites),
-    averaged over the two half sweeps of a one-cycle SAP call.
-
-    Each MR step applies the block operator D_BB, whose hops stay inside the
-    4^4 block: 6 of a site's 8 on average (each direction loses the quarter
-    of the sites on the block face), 165 flop per hop (1320 / 8), plus the
-    diagonal (4 flop per real, 96), the two inner products <q, rho> and
-    |q|^2 (12 flop per complex, 144) and the two complex axpys (8 flop per
-    complex each, 192).  The block residual costs nothing in the first half
-    sweep (x = 0, residual = right-hand side); in the second, x is still zero
-    inside its own blocks, so only the 2 block-leaving hops per site count.
-    With a clover term the site term is two Hermitian 6x6 blocks (6 real
-    diagonal entries, 15 complex pairs: 504 flop) plus the twist and the
-    hop sum (72) in place of the 96 of the scalar diagonal; the second half
-    sweep's residual applies it to x = 0 and is not counted."""
-    hop = 1320 / 8
-    site = 504 + 72 if clover else 96
-    per_site = 0.5 * (2 * hop) + mr * (6 * hop + site + 144 + 192)
-    return V / 2 * ncol * per_site
-
-
-def cpu_baseline(w, U, outer_iters, sap_mr, oddeven=False):
-    """The FP64 oracle on a bounded sample of the same workload: one column of
-    the 16^3x32 problem, one oracle application of each operation of an outer
-    iteration (fine operator, one-cycle SAP, 20-vector Gram-Schmidt step),
-    scaled by the FGMRES iteration count (outer + inner) of the GPU solve.  The SAP
-    cost is affine in the MR step count; it is timed at 1 and 2 steps and
-    extrapolated to the solver's count.  numpy runs on one thread."""
-    import numpy as np
+# --------------------------------------------------------------- CPU baseline ---
+def _cpu_c1_column(args):
+    """One column of the 4^4 workload solved by the FP64 oracle's two-level
+    multigrid (one process, one thread)."""
+    c, = args
     from threadpoolctl import threadpool_limits
+    import numpy as np
     import oracle as O
     import synthetic as S
-    from oracle.multigrid import Blocking, FineLevel
     with threadpool_limits(limits=1):
-        return _cpu_baseline(w, U, outer_iters, sap_mr, oddeven, np, O, S, Blocking, FineLevel)
-
-
-def _cpu_baseline(w, U, outer_iters, sap_mr, oddeven, np, O, S, Blocking, FineLevel):
-    t_all = time.time()
-    lev = FineLevel(O.WilsonTM(U, w.dims, kappa=w.kappa))
-    V = w.volume
-    x = S.gaussian_spinors(1, V, 1).reshape(1, V, 12)
-    mus = np.array([w.mus[0]])
-
-    def timed(f, n=1):
+        w = S.workload("tm_4x4x4x4_2rhs_3shift")
+        U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+        p = O.MGParams(agg=w.agg, n_tv=w.n_tv, sap_block=w.sap_block, mu_setup=min(w.mus))
         t = time.time()
-        for _ in range(n):
-            f()
-        return (time.time() - t) / n
-
-    t_fine = timed(lambda: lev.apply(x, mus))
-    sb = Blocking(w.dims, w.sap_block)
-    t_s1 = timed(lambda: O.sap(lev, sb, x, mus, 1, 1, oddeven=oddeven))
-    t_s2 = timed(lambda: O.sap(lev, sb, x, mus, 1, 2, oddeven=oddeven))
-    t_sap = t_s1 + (sap_mr - 1) * max(t_s2 - t_s1, 0.0)
-    basis = [x * (k + 1) for k in range(20)]
-
-    def gram():
-        h = [O.col_dot(b, x) for b in basis]
-        y = x.copy()
-        for hb, b in zip(h, basis):
-            y = y - hb[:, None, None] * b
-        return O.col_norm(y)
-
-    t_gram = timed(gram)
-    per_col = outer_iters * (t_fine + t_sap + t_gram)
-    return dict(value=1.0 / per_col, unit="rhs*shift solves/s", cores=1, kind="oracle",
-                sample=(f"one column of {w.name}: one numpy-FP64 oracle application each of the fine operator "
-                        f"({t_fine:.2f}s), one-cycle SAP with {sap_mr} MR steps{' (odd-even)' if oddeven else ''} "
-                        f"({t_sap:.2f}s, from 1- and 2-step "
-                        f"timings {t_s1:.2f}s/{t_s2:.2f}s) and a 20-vector "
-                        f"Gram-Schmidt step ({t_gram:.2f}s), times the {outer_iters} FGMRES iterations (outer + "
-                        f"inner) the GPU solve needed; sampling took {time.time() - t_all:.0f}s"))
+        mg = O.OracleMG(U, w.dims, w.kappa, p).setup(S.setup_start_vectors(w))
+        b = S.rhs_for(w)[c // len(w.mus)][None]
+        mu = np.array([w.mus[c % len(w.mus)]])
+        x, info = mg.solve(b, mu)
+        ok = bool(mg.true_relres(b, x, mu)[0] <= 1e-10)
+        return time.time() - t, ok
 
 
-# Learned-smoother study: 16^3x32 fields drawn like the benchmark's (eps 0.3,
-# kappa 0.150), 8 training and 4 held-out gauge seeds; 8 x 160 Adam steps of
-# 16 residual -> error pairs (20480 pairs), errors from 0..2 SAP sweeps; the
-# trained net (4 minimal-residual steps per call, SAP fallback) replaces SAP in
-# FGMRES(40) on 3 rhs x 4 shifts per held-out field.
+def _cpu_c5_sample(args):
+    """Per-operation FP64 oracle timings of the two-level method on a 8^3x16
+    sub-lattice drawn with the 40^3x80 recipe (one process, one thread):
+    fine operator, one-cycle odd-even SAP, restriction, prolongation, one
+    coarse operator application and a 5-vector Gram-Schmidt step on each
+    level.  Every cost is per site and scales with the volume."""
+    seed, = args
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    import oracle as O
+    import synthetic as S
+    from oracle.multigrid import Blocking, FineLevel, build_prolongator, restrict, prolong, galerkin
+    with threadpool_limits(limits=1):
+        w = S.workload(WORKLOAD)
+        dims = (8, 8, 8, 16)
+        U = S.gauge_field(dims, w.eps, w.seed_gauge + seed)
+        lev = FineLevel(O.WilsonTM(U, dims, kappa=w.kappa))
+        V = lev.V
+        x = S.gaussian_spinors(1, V, 1 + seed).reshape(1, V, 12)
+        mus = np.array([w.mus[0]])
+        sb = Blocking(dims, (4, 4, 4, 4))
+        tv = S.gaussian_spinors(24, V, 2 + seed).reshape(24, V, 12)
+        P = build_prolongator(tv, sb)
+        coarse = galerkin(lev, P, sb)
+        xc = restrict(P, sb, x)
+
+        def timed(f, n=3):
+            t = time.time()
+            for _ in range(n):
+                f()
+            return (time.time() - t) / n
+
+        def gram(v, k):
+            basis = [v * (j + 1) for j in range(k)]
+            h = [O.col_dot(bb, v) for bb in basis]
+            y = v.copy()
+            for hb, bb in zip(h, basis):
+                y = y - hb[:, None, None] * bb
+            return O.col_norm(y)
+
+        return dict(V=V, Vc=coarse.V,
+                    fine_op=timed(lambda: lev.apply(x, mus)),
+                    sap=timed(lambda: O.sap(lev, sb, x, mus, 1, 4, oddeven=True), 1),
+                    restrict=timed(lambda: restrict(P, sb, x)),
+                    prolong=timed(lambda: prolong(P, sb, xc)),
+                    coarse_op=timed(lambda: coarse.apply(xc, mus), 10),
+                    gram_fine=timed(lambda: gram(x, 5)),
+                    gram_coarse=timed(lambda: gram(xc, 17), 10))
+
+
+def cpu_measure():
+    """The FP64 oracle on the host cores, one column per process (all cores
+    busy at once), run before the process touches the GPU: (1) the 4^4
+    workload's 6 columns solved in full by the oracle's two-level multigrid;
+    (2) per-operation oracle timings of the two-level method on 8^3x16
+    sub-lattices drawn with the 40^3x80 recipe."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, 16)
+    cpu_model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ctx = mp.get_context("fork")
+    t0 = time.time()
+    with ctx.Pool(min(cores, 6)) as pool:
+        c1 = pool.map(_cpu_c1_column, [(c,) for c in range(6)])
+    c1_wall = time.time() - t0
+    t0 = time.time()
+    with ctx.Pool(cores) as pool:
+        samples = pool.map(_cpu_c5_sample, [(k,) for k in range(cores)])
+    return dict(cores=cores, cpu_model=cpu_model, c1=c1, c1_wall=c1_wall, samples=samples,
+                c5_wall=time.time() - t0)
+
+
+def cpu_baseline(raw, tuned_stats, outer_per_col, ncol, V_fine, Vc):
+    """Combines the oracle timings with the operation counts of the GPU's
+    tuned solve: the headline workload's per-column oracle time is the
+    per-site operation costs scaled to 40^3x80 times the counts."""
+    import numpy as np
+    samples, cores = raw["samples"], raw["cores"]
+    m = {k: float(np.mean([s[k] for s in samples])) for k in samples[0] if k not in ("V", "Vc")}
+    fs = V_fine / samples[0]["V"]
+    cs = Vc / samples[0]["Vc"]
+    st = tuned_stats
+    outer = outer_per_col
+    waves = ncol // 8
+    n_cycles = st["n_bottom_solves"] / waves
+    bottom = st["avg_bottom_iters"]
+    # per column: every outer step = fine operator (FGMRES) + cycle (restrict,
+    # bottom GMRES, prolong, fine residual, SAP) + an outer Gram-Schmidt step;
+    # every bottom step = coarse operator + Gram-Schmidt step
+    per_cycle = (m["restrict"] + m["prolong"] + m["fine_op"] + m["sap"]) * fs + bottom * (
+        m["coarse_op"] + m["gram_coarse"]) * cs
+    per_outer = m["fine_op"] * fs + m["gram_fine"] * fs
+    per_col = n_cycles * per_cycle + outer * per_outer
+    c1 = raw["c1"]
+    return dict(value=cores / per_col, unit="rhs*shift solves/s", cores=cores, kind="oracle",
+                cpu_model=raw["cpu_model"], nproc=os.cpu_count(),
+                sample=(f"FP64 numpy oracle, one column per process on {cores} processes at once (one thread "
+                        f"each): per-operation timings of the two-level method on 8x8x8x16 sub-lattices drawn "
+                        f"with the 40^3x80 recipe ({raw['c5_wall']:.0f}s wall), scaled per site to 40x40x40x80 "
+                        f"and multiplied by the GPU tuned solve's counts per column ({n_cycles:.0f} cycles of "
+                        f"{bottom:.1f} coarse GMRES steps, {outer:.1f} outer steps): {per_col:.0f}s per column; "
+                        f"extrapolated, not a full solve"),
+                c1_full_solves={"columns": 6, "wall_s": raw["c1_wall"], "solves_per_s": 6 / raw["c1_wall"],
+                                "processes": min(cores, 6), "all_converged": all(ok for _, ok in c1),
+                                "seconds_per_column": [round(t, 2) for t, _ in c1],
+                                "workload": "tm_4x4x4x4_2rhs_3shift (4^4, kappa 0.14, two-level MG), full "
+                                            "oracle solves to 1e-10"},
+                per_op_seconds_per_site={k: v / (samples[0]["Vc"] if k in ("coarse_op", "gram_coarse")
+                                                 else samples[0]["V"]) for k, v in m.items()})
+
+
+# --------------------------------------------------------------- learned study ---
+# Learned-smoother study: 16^3x32 fields drawn like the 16^3x32 workload's
+# (eps 0.3, kappa 0.150), 8 training and 4 held-out gauge seeds; 8 x 160 Adam
+# steps of 16 residual -> error pairs (20480 pairs), errors from 0..2 SAP
+# sweeps; the trained net (4 minimal-residual steps per call, SAP fallback)
+# replaces SAP in FGMRES(40) on 3 rhs x 4 shifts per held-out field.
 LEARNED_TRAIN_SEEDS = tuple(range(4101, 4109))
 LEARNED_HELDOUT_SEEDS = tuple(range(4201, 4205))
 LEARNED = dict(steps=160, batch=16, lr=2e-3, sap_sweeps=2, cycles=4, n_rhs=3)
+LEARNED_SOLVER = dict(n_levels=1, sap_cycles=1, sap_mr_iters=12, outer_restart=40, max_outer=3000)
 
 
 def learned_study(dd, S, np, torch):
-    w = S.workload(WORKLOAD)
+    w = S.workload(SMALL)
     mus = np.array(w.mus)
     b = torch.from_numpy(S.rhs_for(w)[:LEARNED["n_rhs"]].copy()).cuda()
     ncol = b.shape[0] * len(mus)
@@ -216,7 +293,7 @@ def learned_study(dd, S, np, torch):
 
     def ctx_for(seed, **kw):
         U = S.gauge_field(w.dims, w.eps, seed)
-        c = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, **{**SOLVER, **kw}), U)
+        c = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, **{**LEARNED_SOLVER, **kw}), U)
         c.autotune(ncol)
         return c
 
@@ -280,14 +357,17 @@ def learned_study(dd, S, np, torch):
     print(json.dumps(out), flush=True)
 
 
+# --------------------------------------------------------------- main ---
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed solves of one right-hand side (8 columns, one wave) before the timed steps")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-three", action="store_true", help="skip the three-level hierarchy on 40^3x80")
+    ap.add_argument("--no-small", action="store_true", help="skip the 16^3x32 forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-clover", action="store_true", help="skip the twisted-mass clover measurement")
     ap.add_argument("--learned", action="store_true",
                     help="instead of the solve benchmark, train the learned smoother on 8 gauge fields and "
                          "compare it with SAP on 4 held-out fields")
@@ -296,6 +376,11 @@ def main():
         print("bench.py measures one GPU: this library has no multi-GPU path (how it would shard is "
               "described in the design notes); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    raw_cpu = None
+    if not args.no_cpu_baseline and not args.learned:
+        log("cpu baseline: oracle on the host cores (before the GPU is touched)")
+        raw_cpu = cpu_measure()
 
     import numpy as np
     import torch
@@ -313,122 +398,80 @@ def main():
     b = torch.from_numpy(S.rhs_for(w)).cuda()
     mus = np.array(w.mus)
     ncol = w.n_col
+    wu = 1 if args.warmup else 0
 
-    def run_form(precision, steps, warmup, solver, time_sap=False):
-        p = dd.params_for_workload(w, precision=precision, **solver)
-        t0 = time.time()
-        ctx = dd.Context(p, U)
-        tuned = ctx.autotune(ncol)
-        torch.cuda.synchronize()
-        setup_s = time.time() - t0
-        log(f"  precision={precision}: context + autotune {setup_s:.2f}s {tuned}")
-        for i in range(warmup):
-            ctx.solve(mus, b)
-            log(f"  warmup solve {i} done")
-        if time_sap:   # HIP events around every SAP kernel launch of the timed solves
-            ctx.set_tuning("time_sap", 1)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        allconv, worst = True, 0.0
-        for i in range(steps):
-            x, info, st = ctx.solve(mus, b)
-            allconv &= all(c["converged"] for c in info)
-            worst = max(worst, max(c["true_rel_res"] for c in info))
-            log(f"  step {i} done ({time.time() - t0:.2f}s)")
-        torch.cuda.synchronize()
-        el = time.time() - t0
-        stats = ctx.stats()
-        if time_sap:
-            ctx.set_tuning("time_sap", 0)
-        return ctx, dict(setup_s=setup_s, elapsed=el, allconv=allconv, worst=worst, stats=stats, tuned=tuned)
-
-    ctx, tuned = run_form(dd.MIXED, args.steps, args.warmup, TUNED, time_sap=True)
-    value = ncol * args.steps / tuned["elapsed"]
-    log("tuned form", tuned)
-
-    # roofline of the dominant kernel of the tuned solve (the FP32 SAP half
-    # sweep) and of the fine stencil, timed with HIP events on the context stream
-    n_iter = 10
+    # tuned form, with live HIP-event timing of the roofline kernel class
+    ctx, tuned = run_form(dd, torch, w, U, b, mus, dd.MIXED, TUNED, args.steps, wu, 8, ROOFLINE_CLASS, "tuned")
+    value = tuned["solves_per_s"]
+    st = tuned["stats"]
+    # fine stencil bandwidth on this lattice (one wave of 8 columns, HIP events)
     V = w.volume
-    sap_name, sap_op = sap_kernel(TUNED, tuned["tuned"]["sap_variant"])
-    t_sap = ctx.time_op(sap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0   # one call = two half sweeps
-    sap_flops = (sap_oe_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"]) if TUNED.get("sap_oddeven")
-                 else sap_flops_per_half_sweep(V, ncol, TUNED["sap_mr_iters"]))
-    sap_tf_standalone = sap_flops / t_sap / 1e12
-    # the same kernel inside the last timed solve: HIP events around each of its
-    # launches on the context stream; the flops scale with the column tiles of
-    # each launch (converged tiles leave the batch)
-    st_t = tuned["stats"]
-    ntile = (ncol + 7) // 8
-    sap_ms, sap_n, sap_tiles = st_t["sap_kernel_ms"], st_t["n_sap_kernels"], st_t["n_sap_kernel_tiles"]
-    sap_us_solve = sap_ms * 1e3 / sap_n if sap_n else None
-    sap_tf_solve = (sap_flops / ntile * sap_tiles) / (sap_ms * 1e-3) / 1e12 if sap_n else None
-    t_copy = ctx.time_op(5, 0, dd.FP64, ncol, 5)              # plain copy of one FP64 48-column vector
-    copy_bytes = 2 * V * 12 * 16 * ncol
-    t32 = ctx.time_op(0, 0, dd.FP32, ncol, n_iter)
-    t64 = ctx.time_op(0, 0, dd.FP64, ncol, n_iter)
+    n_iter = 10
+    t32 = ctx.time_op(0, 0, dd.FP32, 8, n_iter)
+    t64 = ctx.time_op(0, 0, dd.FP64, 8, n_iter)
     links32 = 288 if tuned["tuned"]["fp32_links"] == 0 else 192
-    bytes32 = V * (links32 + ncol * 48 * 4)
-    bytes64 = V * (576 + ncol * 48 * 8)
+    bytes32 = V * (links32 + 8 * 48 * 4)
+    bytes64 = V * (576 + 8 * 48 * 8)
+    Vc, dc, _ = ctx.level_info(1)
+    tuned.pop("x")
     ctx.close()
+    torch.cuda.empty_cache()
 
-    # the coarse stencil on the hierarchy of this workload (4^4 then 2^4
-    # aggregates, 24 / 32 test vectors): BF16 MFMA against the FP32 vector
-    # kernel and FP64, HIP events on the context stream
-    cctx = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, setup_rounds=1), U)
-    coarse = {}
-    for level in (1, 2):
-        Vc, dof, cdims = cctx.level_info(level)
-        flops = Vc * 9 * dof * dof * 8 * ncol
-        row = {"sites": Vc, "dof": dof, "flop_per_launch": flops}
-        for name, prec, knob in (("bf16_mfma", dd.FP32, 1), ("fp32_vector", dd.FP32, 0), ("fp64", dd.FP64, 0)):
-            cctx.set_tuning("coarse_mfma", knob)
-            sec = cctx.time_op(2, level, prec, ncol, 50)
-            row[name] = {"us": sec * 1e6, "TFLOPs": flops / sec / 1e12}
-        row["bf16_mfma"]["frac_of_bf16_peak"] = row["bf16_mfma"]["TFLOPs"] / 2500.0
-        coarse[f"level{level}"] = row
-    cctx.close()
-    log("coarse stencil", coarse)
-
-    # the twisted-mass clover operator on the same workload and solver
-    # (c_sw = CLOVER_CSW): one warm-up and one timed solve, the clover forms
-    # of the fine stencil and of the FP16-input SAP half sweep (HIP events)
-    clover = None
-    if not args.no_clover:
-        cctx, cl = run_form(dd.MIXED, 1, 1, dict(CLOVER_SOLVER, csw=CLOVER_CSW))
-        log("clover form", cl)
-        t32c = cctx.time_op(0, 0, dd.FP32, ncol, n_iter)
-        t64c = cctx.time_op(0, 0, dd.FP64, ncol, n_iter)
-        _, csap_op = sap_kernel(CLOVER_SOLVER, cl["tuned"]["sap_variant"])
-        tsc = cctx.time_op(csap_op, 0, dd.FP32, ncol, SAP_TIMED_CALLS) / 2.0
-        cctx.close()
-        links32c = 288 if cl["tuned"]["fp32_links"] == 0 else 192
-        bytes32c = V * (links32c + 288 + ncol * 48 * 4)      # + the FP32 clover blocks
-        bytes64c = V * (576 + 576 + ncol * 48 * 8)
-        csap_flops = sap_flops_per_half_sweep(V, ncol, CLOVER_SOLVER["sap_mr_iters"], clover=True)
-        clover = {"csw": CLOVER_CSW, "solves_per_s": ncol / cl["elapsed"] if cl["allconv"] else 0.0,
-                  "all_converged": cl["allconv"], "worst_true_rel_res": cl["worst"],
-                  "outer_iters": cl["stats"]["outer_iters"], "inner_iters": cl["stats"]["n_inner_iters"],
-                  "dslash_fp32_us": t32c * 1e6, "dslash_fp32_GBs": bytes32c / t32c / 1e9,
-                  "dslash_fp64_us": t64c * 1e6, "dslash_fp64_GBs": bytes64c / t64c / 1e9,
-                  "sap_half_sweep_us": tsc * 1e6, "sap_TFLOPs": csap_flops / tsc / 1e12}
+    # roofline of the dominant kernel: the level-1 coarse stencil on BF16
+    # MFMA, HBM bound (its blocks, 1.7 GB, stream from HBM at every launch)
+    n_l, ms_l, tiles_l = st["n_sap_kernels"], st["sap_kernel_ms"], st["n_sap_kernel_tiles"]
+    bytes_tile, flops_tile = coarse1_bytes_flops(Vc, dc, 1)
+    blocks_bytes = Vc * 9 * 4 * dc * dc
+    # bytes per launch: the blocks once, the vectors per column tile
+    alg_bytes = n_l * blocks_bytes + tiles_l * (bytes_tile - blocks_bytes)
+    us_launch = ms_l * 1e3 / n_l if n_l else None
+    achieved = alg_bytes / (ms_l * 1e-3) / 1e9 if n_l else None
+    roofline = {"kernel": "k_coarse_mfma<4> (level-1 coarse stencil, BF16 MFMA, FP32 accumulation)",
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "us_per_launch": us_launch, "launches_timed": n_l, "timed_in": "the timed solves",
+                "algorithmic_bytes_per_launch": alg_bytes / n_l if n_l else None,
+                "mfma_TFLOPs": (n_l and tiles_l * flops_tile / (ms_l * 1e-3) / 1e12),
+                "mfma_frac_of_bf16_peak": (n_l and tiles_l * flops_tile / (ms_l * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)}
 
     plain = None
     if not args.no_plain:
-        pctx, plain = run_form(dd.PLAIN_FP64, 1, 0, SOLVER)
+        pctx, plain = run_form(dd, torch, w, U, b, mus, dd.PLAIN_FP64, TUNED, args.steps, wu, 8, None, "plain")
+        plain.pop("x")
         pctx.close()
-        log("plain FP64 form", plain)
+        torch.cuda.empty_cache()
+    three = None
+    if not args.no_three:
+        tctx, three = run_form(dd, torch, w, U, b[:1].contiguous(), mus, dd.MIXED, THREE, 1, 1, 8, None,
+                               "three-level")
+        three.pop("x")
+        tctx.close()
+        torch.cuda.empty_cache()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle sample")
-        cpu = cpu_baseline(w, U, tuned["stats"]["outer_iters"] + tuned["stats"]["n_inner_iters"],
-                           TUNED["sap_mr_iters"], bool(TUNED.get("sap_oddeven")))
+    small = None
+    if not args.no_small:
+        ws = S.workload(SMALL)
+        Us = S.gauge_field(ws.dims, ws.eps, ws.seed_gauge)
+        bs = torch.from_numpy(S.rhs_for(ws)).cuda()
+        ms = np.array(ws.mus)
+        small = {}
+        for name, prec, solver in (("one_level", dd.MIXED, SMALL_ONE), ("two_level", dd.MIXED, SMALL_TWO),
+                                   ("three_level", dd.MIXED, SMALL_THREE),
+                                   ("two_level_plain_fp64", dd.PLAIN_FP64, SMALL_TWO)):
+            c, r = run_form(dd, torch, ws, Us, bs, ms, prec, solver, 1, 12, ws.n_col, None, "16^3x32 " + name)
+            r.pop("x")
+            c.close()
+            small[name] = summary(r, "f64" if prec == dd.PLAIN_FP64 else "f64 outer / f32 cycle")
+        small["config"] = {"workload": ws.name, "lattice": "16x16x16x32", "kappa": ws.kappa, "columns": ws.n_col,
+                           "one_level": "FP64 FGMRES(4) over FP32 FGMRES(40, FP16 basis) over SAP",
+                           "two_level": "FP64 FGMRES(40) over the two-level cycle (4^4 aggregates, N = 24)",
+                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)"}
 
-    sap_tf = sap_tf_solve if sap_tf_solve is not None else sap_tf_standalone
+    cpu = cpu_baseline(raw_cpu, st, tuned["outer_iters_mean"], ncol, V, Vc) if raw_cpu else None
+
     out = {
         "metric": "rhs*shift solves/s at true FP64 relative residual 1e-10 (tuned form); dslash HBM GB/s",
-        "value": value if tuned["allconv"] else 0.0,
+        "value": value,
         "unit": "rhs*shift solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -437,37 +480,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 outer / f32 inner (f16 basis storage) / f32 preconditioner",
+        "dtype": "f64 outer / f32 cycle / bf16 coarse blocks",
         "data": "synthetic",
-        "config": {"workload": w.name, "lattice": "16x16x16x32", "kappa": w.kappa, "n_rhs": w.n_rhs,
-                   "shifts": list(w.mus), "columns": ncol, "tol": 1e-10,
-                   "solver": "FP64 FGMRES(4) over FP32 FGMRES(40, to 1e-2, FP16 basis) over FP32 red-black "
-                             "SAP (4^4 blocks, 1 cycle, 4 MR steps on the odd-even reduced blocks)",
-                   "plain_solver": "FP64 FGMRES(40) over FP64 red-black SAP (4^4 blocks, 1 cycle, 12 MR steps)"},
+        "config": {"workload": w.name, "lattice": "40x40x40x80", "kappa": w.kappa, "eps": w.eps, "n_rhs": w.n_rhs,
+                   "shifts": list(w.mus), "columns": ncol, "tol": 1e-10, "columns_in_flight": 8,
+                   "solver": "FP64 FGMRES(4) over the two-level aggregation MG cycle in FP32 (4^4 aggregates, "
+                             "N = 24, one bootstrap round; red-black SAP 1 cycle of 4 MR steps on the odd-even "
+                             "reduced 4^4 blocks; coarse GMRES on gamma5_c D_c to 0.1, BF16 MFMA stencil)"},
         "all_converged": tuned["allconv"],
         "worst_true_rel_res": tuned["worst"],
-        "outer_iters": tuned["stats"]["outer_iters"],
-        "inner_iters": tuned["stats"]["n_inner_iters"],
-        "plain_outer_iters": plain["stats"]["outer_iters"] if plain else None,
-        "context_setup_s": tuned["setup_s"],
+        "tuned": summary(tuned, "f64 outer / f32 cycle / bf16 coarse blocks"),
+        "plain_fp64": summary(plain, "f64") if plain else None,
+        "tuned_over_plain": (value / plain["solves_per_s"]) if plain and plain["solves_per_s"] else None,
+        "three_level_one_wave": summary(three, "f64 outer / f32 cycle") if three else None,
         "autotuned": tuned["tuned"],
-        "plain_fp64_solves_per_s": (ncol / plain["elapsed"]) if plain and plain["allconv"] else None,
-        "tuned_over_plain": (value / (ncol / plain["elapsed"])) if plain and plain["allconv"] else None,
-        "dslash": {"fp32_us": t32 * 1e6, "fp32_GBs": bytes32 / t32 / 1e9,
-                   "fp32_GFLOPs": 1320 * V * ncol / t32 / 1e9,
-                   "fp64_us": t64 * 1e6, "fp64_GBs": bytes64 / t64 / 1e9,
-                   "fp64_GFLOPs": 1320 * V * ncol / t64 / 1e9,
-                   "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": sap_name + " (FP32 red-black SAP half sweep, 48 columns)",
-                     "bound": "alu", "achieved": sap_tf, "peak": 157.3, "unit": "TFLOP/s",
-                     "frac": sap_tf / 157.3, "traffic": measured_traffic(sap_name),
-                     "us_per_launch": sap_us_solve if sap_us_solve is not None else t_sap * 1e6,
-                     "launches_timed": sap_n, "timed_in": "the last timed solve" if sap_n else "standalone calls",
-                     "standalone": {"us_per_launch": t_sap * 1e6, "achieved": sap_tf_standalone,
-                                    "launches": 2 * SAP_TIMED_CALLS}},
-        "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
-        "coarse_stencil_48col": coarse,
-        "clover": clover,
+        "dslash_40x40x40x80_8col": {"fp32_us": t32 * 1e6, "fp32_GBs": bytes32 / t32 / 1e9,
+                                    "fp32_GFLOPs": 1320 * V * 8 / t32 / 1e9,
+                                    "fp64_us": t64 * 1e6, "fp64_GBs": bytes64 / t64 / 1e9,
+                                    "fp64_GFLOPs": 1320 * V * 8 / t64 / 1e9,
+                                    "fp32_hbm_frac": bytes32 / t32 / 1e9 / HBM_PEAK_GBS,
+                                    "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
+        "roofline": roofline,
+        "small_16x16x16x32": small,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

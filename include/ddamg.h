@@ -148,7 +148,7 @@ typedef struct ddamg_stats {
   long long n_inner_iters;   /* FP32 inner FGMRES steps over all outer steps (last solve)       */
   long long n_fp16_restores; /* inner steps whose FP16 basis vector was stored again at its exact
                                 norm (entry scale outside the DDAMG_KNOB_FP16_RESCALE bound)     */
-  double sap_kernel_ms;      /* with DDAMG_KNOB_TIME_SAP: summed HIP-event time of the SAP kernel  */
+  double sap_kernel_ms;      /* with DDAMG_KNOB_TIME_SAP: summed HIP-event time of the timed kernel */
                              /* launches of the last solve (else 0)                               */
   long long n_sap_kernels;   /* ... the number of those launches                                  */
   long long n_sap_kernel_tiles; /* ... and the sum of their column tiles (8 columns each)         */
@@ -282,8 +282,13 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             c of the true norm to the prediction leaves [1/B, B]
                                             the vector is stored again at its exact norm.  B: 1 to
                                             1024 (default 4; 1 stores every vector at its norm) */
-#define DDAMG_KNOB_TIME_SAP          8   /* 1: HIP events around every SAP kernel launch of a solve,
-                                            summed into ddamg_stats (sap_kernel_ms); 0 (default) off */
+#define DDAMG_KNOB_TIME_SAP          8   /* kernel class timed with HIP events around every launch of
+                                            a solve, summed into ddamg_stats (sap_kernel_ms,
+                                            n_sap_kernels, n_sap_kernel_tiles): 0 (default) off,
+                                            1 the fine SAP half sweep, 2 the coarse stencil of level 1,
+                                            3 the restriction 0 -> 1, 4 the prolongation 1 -> 0,
+                                            5 the fine stencil */
+#define DDAMG_KNOB_TIME_KERNEL       DDAMG_KNOB_TIME_SAP
 #define DDAMG_N_KNOBS 9
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);

@@ -333,7 +333,7 @@ class Context:
 
     KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2, "coarse_mfma": 3,
              "sap_variant": 4,
-             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7, "time_sap": 8}
+             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7, "time_sap": 8, "time_kernel": 8}
 
     # ---- learned smoother ----
     def set_smoother_weights(self, w1, w2):

@@ -619,7 +619,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_DSLASH_ORDER: return value >= 0 && value <= 3;
     case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
     case DDAMG_KNOB_FP16_RESCALE: return value >= 1 && value <= 1024;
-    case DDAMG_KNOB_TIME_SAP: return value == 0 || value == 1;
+    case DDAMG_KNOB_TIME_SAP: return value >= 0 && value <= 5;
     default: return false;
   }
 }

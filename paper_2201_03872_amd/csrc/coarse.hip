@@ -197,7 +197,15 @@ static bool use_mfma(ddamg_ctx* c, int level, const MV& x) {
   return x.prec == P32 && c->coarse_mfma && d % 16 == 0 && d <= 64 && c->coarse[level].d_blk16 != nullptr;
 }
 
+static void coarse_apply_launch(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);
+
 void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
+  if (level == 1) kernel_timing_begin(c, TIMED_COARSE1);
+  coarse_apply_launch(c, level, x, y, d_mu);
+  if (level == 1) kernel_timing_end(c, TIMED_COARSE1, x.ntiles);
+}
+
+static void coarse_apply_launch(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
   const LevelGeom& g = c->geom[level];
   const int d = g.dof;
   if (use_mfma(c, level, x)) {
@@ -274,6 +282,7 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
   DD_CHECK(x.prec == y.prec && x.ntiles == y.ntiles && x.nsites == gf.V && y.nsites == gc.V, DDAMG_EINVAL,
            "restrict: shape");
   dim3 grid(gc.V * x.ntiles), blk(2 * N * TC);
+  if (level == 0) kernel_timing_begin(c, TIMED_RESTRICT0);
   if (x.prec == P64)
     hipLaunchKernelGGL(k_restrict<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
                        gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
@@ -281,6 +290,7 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
     hipLaunchKernelGGL(k_restrict<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
                        gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
   DD_HIP(hipGetLastError());
+  if (level == 0) kernel_timing_end(c, TIMED_RESTRICT0, x.ntiles);
 }
 
 // ------------------------------------------------------------- prolong ---
@@ -318,6 +328,7 @@ void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulat
            "prolong: shape");
   const int nsb = (gf.V + 256 / TC - 1) / (256 / TC);
   dim3 grid(nsb * x.ntiles), blk(256);
+  if (level == 0) kernel_timing_begin(c, TIMED_PROLONG0);
   if (x.prec == P64)
     hipLaunchKernelGGL(k_prolong<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
                        gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
@@ -325,6 +336,7 @@ void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulat
     hipLaunchKernelGGL(k_prolong<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
                        gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
   DD_HIP(hipGetLastError());
+  if (level == 0) kernel_timing_end(c, TIMED_PROLONG0, x.ntiles);
 }
 
 // ------------------------------------------------------------- setup ---

@@ -172,7 +172,7 @@ struct ddamg_ctx {
   int* d_walk_blk = nullptr;    // [xyz block column][t block] block numbers (4^4 site blocks)
   int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
   int fp16_rescale = 4;         // FP16 Arnoldi basis: bound on the entry scales of the stored vectors
-  int time_sap = 0;             // HIP events around every SAP kernel launch of a solve
+  int time_sap = 0;             // kernel class timed with HIP events at every launch of a solve (0 off)
   std::vector<hipEvent_t> sap_ev;   // event pool, (start, stop) pairs, reused by every solve
   std::vector<int> sap_ev_tiles;    // column tiles of each timed launch
   size_t sap_ev_used = 0;
@@ -294,5 +294,10 @@ void copy_to_host(ddamg_ctx* c, const void* d, void* h, size_t bytes);
 void sap_timing_begin(ddamg_ctx* c);
 void sap_timing_end(ddamg_ctx* c, int ntiles);
 void sap_timing_collect(ddamg_ctx* c);
+// the same for one kernel class (the value of the time_sap knob): HIP events
+// around every launch of that class
+enum { TIMED_SAP = 1, TIMED_COARSE1 = 2, TIMED_RESTRICT0 = 3, TIMED_PROLONG0 = 4, TIMED_DSLASH = 5 };
+void kernel_timing_begin(ddamg_ctx* c, int cls);
+void kernel_timing_end(ddamg_ctx* c, int cls, int ntiles);
 
 }  // namespace ddamg

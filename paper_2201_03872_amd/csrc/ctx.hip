@@ -264,15 +264,15 @@ void copy_to_host(ddamg_ctx* c, const void* d, void* h, size_t bytes) {
   std::memcpy(h, c->h_pinned, bytes);
 }
 
-static bool sap_timing_on(ddamg_ctx* c) {
-  if (!c->time_sap) return false;
+static bool timing_on(ddamg_ctx* c, int cls) {
+  if (c->time_sap != cls) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   DD_HIP(hipStreamIsCapturing(c->stream, &cs));
   return cs == hipStreamCaptureStatusNone;
 }
 
-void sap_timing_begin(ddamg_ctx* c) {
-  if (!sap_timing_on(c)) return;
+void kernel_timing_begin(ddamg_ctx* c, int cls) {
+  if (!timing_on(c, cls)) return;
   if (c->sap_ev_used + 2 > c->sap_ev.size()) {
     hipEvent_t a, b;
     DD_HIP(hipEventCreate(&a));
@@ -283,13 +283,16 @@ void sap_timing_begin(ddamg_ctx* c) {
   DD_HIP(hipEventRecord(c->sap_ev[c->sap_ev_used], c->stream));
 }
 
-void sap_timing_end(ddamg_ctx* c, int ntiles) {
-  if (!sap_timing_on(c)) return;
+void kernel_timing_end(ddamg_ctx* c, int cls, int ntiles) {
+  if (!timing_on(c, cls)) return;
   DD_HIP(hipEventRecord(c->sap_ev[c->sap_ev_used + 1], c->stream));
   c->sap_ev_used += 2;
   c->sap_ev_tiles.resize(c->sap_ev_used / 2);
   c->sap_ev_tiles.back() = ntiles;
 }
+
+void sap_timing_begin(ddamg_ctx* c) { kernel_timing_begin(c, TIMED_SAP); }
+void sap_timing_end(ddamg_ctx* c, int ntiles) { kernel_timing_end(c, TIMED_SAP, ntiles); }
 
 void sap_timing_collect(ddamg_ctx* c) {
   double ms = 0;

@@ -1211,7 +1211,9 @@ static void launch_dslash(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, c
 }
 
 void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu) {
+  kernel_timing_begin(c, TIMED_DSLASH);
   launch_dslash<0>(c, x, y, nullptr, d_mu);
+  kernel_timing_end(c, TIMED_DSLASH, x.ntiles);
 }
 
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu) {

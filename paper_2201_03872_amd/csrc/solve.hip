@@ -746,7 +746,10 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
             int maxit, const Precond* pc, int zprec, bool fixed, KrylovOut* out, int role = 0) {
   const int nt = b.ntiles, ncol = b.ncol();
   DD_CHECK(m >= 1 && m < KMAX, DDAMG_EINVAL, "Krylov restart length must be in [1, 63]");
-  if (!pc && !fixed && role == 0 && c->p.use_graphs) {
+  // captured graphs record no timing events: a level whose stencil is being
+  // timed live runs the host-driven steps (identical iterates)
+  const bool timed = level == 1 && c->time_sap == TIMED_COARSE1;
+  if (!pc && !fixed && role == 0 && c->p.use_graphs && !timed) {
     krylov_graph(c, level, d_mu, b, x, x_zero, tol, m, maxit, out);
     return;
   }
