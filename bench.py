@@ -413,6 +413,10 @@ def main():
     bytes32 = V * (links32 + 8 * 48 * 4)
     bytes64 = V * (576 + 8 * 48 * 8)
     Vc, dc, _ = ctx.level_info(1)
+    # plain copy kernel of one FP64 8-column vector (read + write), the
+    # reference for the bandwidth and for calibrating the traffic counters
+    t_copy = ctx.time_op(5, 0, dd.FP64, 8, 5)
+    copy_bytes = 2 * V * 12 * 16 * 8
     tuned.pop("x")
     ctx.close()
     torch.cuda.empty_cache()
@@ -426,7 +430,7 @@ def main():
     alg_bytes = n_l * blocks_bytes + tiles_l * (bytes_tile - blocks_bytes)
     us_launch = ms_l * 1e3 / n_l if n_l else None
     achieved = alg_bytes / (ms_l * 1e-3) / 1e9 if n_l else None
-    roofline = {"kernel": "k_coarse_mfma<4> (level-1 coarse stencil, BF16 MFMA, FP32 accumulation)",
+    roofline = {"kernel": "k_coarse_mfma_t1<48> (level-1 coarse stencil, BF16 MFMA, FP32 accumulation)",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
                 "us_per_launch": us_launch, "launches_timed": n_l, "timed_in": "the timed solves",
@@ -501,6 +505,7 @@ def main():
                                     "fp32_hbm_frac": bytes32 / t32 / 1e9 / HBM_PEAK_GBS,
                                     "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
         "roofline": roofline,
+        "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
         "small_16x16x16x32": small,
         "cpu_baseline": cpu,
     }

@@ -278,35 +278,40 @@ void mv_copy(ddamg_ctx* c, const MV& s, const MV& d) {
   mv_convert(c, s, d);
 }
 
-template <typename RS, typename RD>
-__global__ void k_convert(const RS* __restrict__ a, RD* __restrict__ b, int ntiles, int nsites, int dof, int T) {
-  constexpr int RWS = Chunk<RS>::RW, RWD = Chunk<RD>::RW;
-  const int ncs = 2 * dof / RWS, ncd = 2 * dof / RWD;
-  const size_t total = (size_t)ntiles * nsites * dof * T;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int t = (int)(i % T);
-    size_t r = i / T;
-    const int s = (int)(r % nsites);
-    r /= nsites;
-    const int k = (int)(r % dof);
-    const int tile = (int)(r / dof);
-    const RS* p = a + (size_t)tile * ncs * nsites * T * RWS + (((size_t)(k / (RWS / 2)) * nsites + s) * T + t) * RWS +
-                  (k % (RWS / 2)) * 2;
-    RD* q = b + (size_t)tile * ncd * nsites * T * RWD + (((size_t)(k / (RWD / 2)) * nsites + s) * T + t) * RWD +
-            (k % (RWD / 2)) * 2;
-    q[0] = (RD)p[0];
-    q[1] = (RD)p[1];
+// FP64 <-> FP32 in the tiled layout.  An FP32 chunk holds two complexes,
+// an FP64 chunk one, so FP32 chunk c of a (site, column) holds FP64 chunks 2c
+// and 2c+1; one lane per FP32 chunk moves 16 bytes on the FP32 side and two
+// 16-byte chunks on the FP64 side.
+__global__ void k_convert_64_32(const double2* __restrict__ a, float4* __restrict__ b, size_t nunits, size_t nsT) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = u / nsT, st = u - q * nsT;          // q = tile * ncd + c
+    const size_t src = (2 * q) * nsT + st;               // tile * 2 ncd + 2c  (ncs = 2 ncd)
+    const double2 v0 = a[src], v1 = a[src + nsT];
+    b[u] = make_float4((float)v0.x, (float)v0.y, (float)v1.x, (float)v1.y);
+  }
+}
+
+__global__ void k_convert_32_64(const float4* __restrict__ a, double2* __restrict__ b, size_t nunits, size_t nsT) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = u / nsT, st = u - q * nsT;
+    const float4 v = a[u];
+    const size_t dst = (2 * q) * nsT + st;
+    b[dst] = make_double2(v.x, v.y);
+    b[dst + nsT] = make_double2(v.z, v.w);
   }
 }
 
 void mv_convert(ddamg_ctx* c, const MV& s, const MV& d) {
-  const size_t n = (size_t)s.ntiles * s.nsites * s.dof * s.T;
+  DD_CHECK(s.dof == d.dof && s.nsites == d.nsites && s.ntiles <= d.ntiles && s.T == d.T && s.dof % 2 == 0,
+           DDAMG_EINVAL, "mv_convert: shape");
+  const size_t nsT = (size_t)s.nsites * s.T;
+  const size_t n32 = (size_t)s.ntiles * (s.dof / 2) * nsT;   // FP32 chunks
   if (s.prec == P64 && d.prec == P32)
-    hipLaunchKernelGGL((k_convert<double, float>), grid_for(n), dim3(256), 0, c->stream, s.as<double>(),
-                       d.as<float>(), s.ntiles, s.nsites, s.dof, s.T);
+    hipLaunchKernelGGL(k_convert_64_32, grid_for(n32), dim3(256), 0, c->stream, (const double2*)s.p, (float4*)d.p,
+                       n32, nsT);
   else if (s.prec == P32 && d.prec == P64)
-    hipLaunchKernelGGL((k_convert<float, double>), grid_for(n), dim3(256), 0, c->stream, s.as<float>(),
-                       d.as<double>(), s.ntiles, s.nsites, s.dof, s.T);
+    hipLaunchKernelGGL(k_convert_32_64, grid_for(n32), dim3(256), 0, c->stream, (const float4*)s.p, (double2*)d.p,
+                       n32, nsT);
   else
     throw Error{DDAMG_EINVAL, "mv_convert: precisions"};
   DD_HIP(hipGetLastError());
@@ -368,13 +373,31 @@ __global__ void k_add(const R* __restrict__ a, R* __restrict__ b, size_t n) {
     b[i] += a[i];
 }
 
+__global__ void k_add4(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float4 u = a[i];
+    float4 v = b[i];
+    v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+    b[i] = v;
+  }
+}
+
+__global__ void k_add2(const double2* __restrict__ a, double2* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 u = a[i];
+    double2 v = b[i];
+    v.x += u.x; v.y += u.y;
+    b[i] = v;
+  }
+}
+
 void mv_add(ddamg_ctx* c, const MV& x, const MV& y) {
   DD_CHECK(x.prec == y.prec && x.reals() == y.reals(), DDAMG_EINVAL, "mv_add: shape");
-  const size_t n = x.reals();
+  const size_t n = x.bytes() / 16;   // whole 16-byte chunks
   if (x.prec == P64)
-    hipLaunchKernelGGL(k_add<double>, grid_for(n), dim3(256), 0, c->stream, x.as<double>(), y.as<double>(), n);
+    hipLaunchKernelGGL(k_add2, grid_for(n), dim3(256), 0, c->stream, (const double2*)x.p, (double2*)y.p, n);
   else
-    hipLaunchKernelGGL(k_add<float>, grid_for(n), dim3(256), 0, c->stream, x.as<float>(), y.as<float>(), n);
+    hipLaunchKernelGGL(k_add4, grid_for(n), dim3(256), 0, c->stream, (const float4*)x.p, (float4*)y.p, n);
   DD_HIP(hipGetLastError());
 }
 

@@ -192,6 +192,85 @@ __global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x
   (void)nwgc;
 }
 
+// One tile (T = 8 columns) per workgroup, for coarse lattices where the
+// batch in flight is a single tile: the real and imaginary halves of the 8
+// columns share one 16-wide B operand, B = [[Re X, Im X]; [-Im X, Re X]]
+// (rows 0..d-1 against Re A, d..2d-1 against Im A), so one MFMA per k step
+// yields [Re Y | Im Y] and no lane computes a padded column.  The x of the
+// site and its 8 neighbours (9 d complexes per column) is staged in LDS once
+// by coalesced 16-byte loads and shared by the d/16 waves (each owns 16
+// rows); the A operand streams from memory once per workgroup.
+template <int D>
+__global__ void __launch_bounds__(64 * (D / 16)) k_coarse_mfma_t1(const float* __restrict__ x, float* __restrict__ y,
+                                                                 const bf16x8* __restrict__ A,
+                                                                 const int* __restrict__ nbr,
+                                                                 const double* __restrict__ mu, double muf, int V,
+                                                                 int g5o) {
+  constexpr int MT = D / 16, KS = D / 16, NCH = D / 2;   // row tiles, k steps, 2-complex chunks per site
+  constexpr int NT = 64 * MT;
+  __shared__ float4 xs[9][NCH][TC];
+  const int s = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  int nb[9];
+  nb[0] = s;
+#pragma unroll
+  for (int p = 1; p < 9; ++p) nb[p] = nbr[(size_t)(p - 1) * V + s];
+  const float4* xg = reinterpret_cast<const float4*>(x);
+  for (int q = threadIdx.x; q < 9 * NCH * TC; q += NT) {
+    const int t = q % TC, c = (q / TC) % NCH, p = q / (TC * NCH);
+    xs[p][c][t] = xg[((size_t)c * V + nb[p]) * TC + t];
+  }
+  __syncthreads();
+  const int n = lane % 16, kb = lane / 16;
+  const int t = n % 8;
+  const bool imh = n >= 8;
+  f32x4 acc = f32x4{0, 0, 0, 0};
+  const bf16x8* Aw = A + ((size_t)s * 9 * MT + w) * KS * 64 + lane;
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    bf16x8 a[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a[ks] = Aw[((size_t)p * MT * KS + ks) * 64];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = 32 * ks + 8 * kb;          // 8 consecutive k of one half
+      const bool re_part = k0 < D;
+      const int c0 = re_part ? k0 : k0 - D;
+      bf16x8 b;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = xs[p][c0 / 2 + q][t];   // (re, im) of complexes c0+2q, c0+2q+1
+        float e0, e1;
+        if (!imh) {   // real half of the output: [Re X; -Im X]
+          e0 = re_part ? v.x : -v.y;
+          e1 = re_part ? v.z : -v.w;
+        } else {      // imaginary half: [Im X; Re X]
+          e0 = re_part ? v.y : v.x;
+          e1 = re_part ? v.w : v.z;
+        }
+        b[2 * q] = (__bf16)e0;
+        b[2 * q + 1] = (__bf16)e1;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b, acc, 0, 0, 0);
+    }
+  }
+  // lane (n, kb) holds rows 16w + 4kb + r of column t: the real part (n < 8)
+  // or the imaginary part (n >= 8); twist i dmu mu gamma5_c on the site's own
+  // x (with g5o: gamma5_c on the stencil part, i dmu mu on every row)
+  const float m = (float)(muf * mu[t]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * w + 4 * kb + r;
+    const float sg = (g5o && i >= D / 2) ? -1.f : 1.f;
+    const float gm = (g5o || i < D / 2) ? m : -m;
+    const float4 v = xs[0][i / 2][t];
+    const float xr = (i % 2) ? v.z : v.x, xi = (i % 2) ? v.w : v.y;
+    const size_t o = (((size_t)(i / 2) * V + s) * TC + t) * 4 + (i % 2) * 2;
+    if (!imh) y[o] = sg * acc[r] - gm * xi;
+    else y[o + 1] = sg * acc[r] + gm * xr;
+  }
+}
+
 static bool use_mfma(ddamg_ctx* c, int level, const MV& x) {
   const int d = c->geom[level].dof;
   return x.prec == P32 && c->coarse_mfma && d % 16 == 0 && d <= 64 && c->coarse[level].d_blk16 != nullptr;
@@ -208,6 +287,23 @@ void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const doubl
 static void coarse_apply_launch(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
   const LevelGeom& g = c->geom[level];
   const int d = g.dof;
+  if (use_mfma(c, level, x) && x.ntiles == 1) {
+    const bf16x8* A = (const bf16x8*)c->coarse[level].d_blk16;
+    const double muf = c->coarse[level].mu_factor;
+    const int g5o = c->coarse[level].g5out;
+    switch (d) {
+      case 16: hipLaunchKernelGGL(k_coarse_mfma_t1<16>, dim3(g.V), dim3(64), 0, c->stream, x.as<float>(), y.as<float>(),
+                                  A, g.d_nbr, d_mu, muf, g.V, g5o); break;
+      case 32: hipLaunchKernelGGL(k_coarse_mfma_t1<32>, dim3(g.V), dim3(128), 0, c->stream, x.as<float>(),
+                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
+      case 48: hipLaunchKernelGGL(k_coarse_mfma_t1<48>, dim3(g.V), dim3(192), 0, c->stream, x.as<float>(),
+                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
+      default: hipLaunchKernelGGL(k_coarse_mfma_t1<64>, dim3(g.V), dim3(256), 0, c->stream, x.as<float>(),
+                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
+    }
+    DD_HIP(hipGetLastError());
+    return;
+  }
   if (use_mfma(c, level, x)) {
     const int ngrp = (x.ntiles + 1) / 2;
     if ((size_t)g.V * ngrp >= 8192) {
@@ -251,28 +347,69 @@ void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, 
 
 // ------------------------------------------------------------ restrict ---
 // y(a)[s*N + j] = sum_{x in A_a} sum_{k of chirality s} conj(P[x][k][j]) x(x)[k]
-// One workgroup per (coarse site, tile); lane = (row, column).
+// A dense contraction per aggregate, Y (2N x T) = P_a^dag X_a, streaming P
+// once: one workgroup of four waves per (aggregate, tile); lane (s, j) of a
+// wave owns row s*N + j for all T columns of the tile, the waves take every
+// fourth site and their partial sums meet in LDS.  Per site and 16-byte
+// chunk of the vector (CPC components of one chirality) the lanes read their
+// P entries (consecutive j: coalesced) and the chunk of every column (the
+// same addresses on every lane of a chirality: one broadcast line), then do
+// CPC * T multiply-adds.
 template <typename R>
-__global__ void k_restrict(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ P,
-                           const int* __restrict__ blk_of_coarse, int Vf, int dof, int N, int gs, int Vc,
-                           size_t tile_f, size_t tile_c) {
+__global__ void __launch_bounds__(256) k_restrict(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ P,
+                                                  const int* __restrict__ blk_of_coarse, int Vf, int dof, int N, int gs,
+                                                  int Vc, size_t tile_f, size_t tile_c) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW;
+  constexpr int CPC = RW / 2;
+  constexpr int NWR = 4;   // waves per aggregate, each over every NWR-th site; partial sums meet in LDS
+  __shared__ cx<R> part[NWR - 1][TC][64];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int a = wg % Vc, tile = wg / Vc;
-  const int r = threadIdx.x / TC, t = threadIdx.x % TC;
-  const int sig = r / N, j = r % N;
+  const int r = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const bool live = r < 2 * N;
+  const int sig = live ? r / N : 0, j = live ? r % N : 0;
   const int h = dof / 2;
   const int b = blk_of_coarse[a];
-  const R* xt = x + (size_t)tile * tile_f;
+  const C* xt = reinterpret_cast<const C*>(x + (size_t)tile * tile_f);
   const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
-  cx<R> acc = {0, 0};
-  for (int q = 0; q < gs; ++q) {
+  cx<R> acc[TC];
+#pragma unroll
+  for (int t = 0; t < TC; ++t) acc[t] = {0, 0};
+  const int c0 = sig * h / CPC, nch = h / CPC;
+  for (int q = wv; q < gs; q += NWR) {
     const int s = b * gs + q;
-    for (int kk = 0; kk < h; ++kk) {
-      const int k = sig * h + kk;
-      cmac_conj(acc, Pc[((size_t)s * dof + k) * N + j], load_one(xt, Vf, TC, s, t, k));
+    for (int cc = 0; cc < nch; ++cc) {
+      const int ch = c0 + cc;
+      cx<R> pv[CPC];
+#pragma unroll
+      for (int e = 0; e < CPC; ++e) pv[e] = Pc[((size_t)s * dof + ch * CPC + e) * N + j];
+      const C* xc = xt + ((size_t)ch * Vf + s) * TC;
+#pragma unroll
+      for (int t = 0; t < TC; ++t) {
+        const C v = xc[t];
+        if constexpr (CPC == 1) {
+          cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
+        } else {
+          cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
+          cmac_conj(acc[t], pv[1], cx<R>{v.z, v.w});
+        }
+      }
     }
   }
-  store_one(y + (size_t)tile * tile_c, Vc, TC, a, t, r, acc);
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < TC; ++t) part[wv - 1][t][r] = acc[t];
+  }
+  __syncthreads();
+  if (wv > 0 || !live) return;
+#pragma unroll
+  for (int t = 0; t < TC; ++t)
+#pragma unroll
+    for (int w = 0; w < NWR - 1; ++w) acc[t] = acc[t] + part[w][t][r];
+  R* yt = y + (size_t)tile * tile_c;
+#pragma unroll
+  for (int t = 0; t < TC; ++t) store_one(yt, Vc, TC, a, t, r, acc[t]);
 }
 
 void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
@@ -281,7 +418,9 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
   const int N = c->tr[level].N;
   DD_CHECK(x.prec == y.prec && x.ntiles == y.ntiles && x.nsites == gf.V && y.nsites == gc.V, DDAMG_EINVAL,
            "restrict: shape");
-  dim3 grid(gc.V * x.ntiles), blk(2 * N * TC);
+  DD_CHECK(2 * N <= 64 && gf.dof % (2 * reals_per_chunk(x.prec) / 2) == 0, DDAMG_EINVAL,
+           "restrict: at most 32 test vectors, chirality halves of whole chunks");
+  dim3 grid(gc.V * x.ntiles), blk(256);
   if (level == 0) kernel_timing_begin(c, TIMED_RESTRICT0);
   if (x.prec == P64)
     hipLaunchKernelGGL(k_restrict<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
@@ -294,30 +433,109 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
 }
 
 // ------------------------------------------------------------- prolong ---
-// y(x)[k] (+)= sum_j P[x][k][j] xc(a(x))[s(k)*N + j];  lane = (fine site, column)
-template <typename R>
+// y(x)[k] (+)= sum_j P[x][k][j] xc(a(x))[s(k)*N + j]
+// One lane per (fine site, column of the tile) computing every component of
+// its site.  The lane first holds its column of the coarse vector (2N
+// complexes; the T lanes of a site read one line per chunk), then walks its
+// P rows in storage order, each row (N complexes) loaded as consecutive
+// 16-byte chunks (the same for the T lanes of a site), so every P line is used
+// up at once instead of being revisited from the caches; its output chunks of
+// consecutive columns form one line per chunk.  DOF is the fine dof (12 on the
+// fine level, 2N' on a coarse one), NN the number N of test vectors.
+template <typename R, int DOF, int NN>
 __global__ void __launch_bounds__(256) k_prolong(const R* __restrict__ xc, R* __restrict__ y, const R* __restrict__ P,
-                                                 const int* __restrict__ coarse_of_blk, int Vf, int dof, int N, int gs,
-                                                 int Vc, size_t tile_f, size_t tile_c, int accumulate, int nsb) {
-  constexpr int SP = 256 / TC;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = wg / nsb;
-  const int s = (wg % nsb) * SP + threadIdx.x / TC;
-  const int t = threadIdx.x % TC;
-  if (s >= Vf) return;
+                                                 const int* __restrict__ coarse_of_blk, int Vf, int gs, int Vc,
+                                                 size_t tile_f, size_t tile_c, int accumulate, int ntiles) {
+  using C = typename Chunk<R>::type;
+  constexpr int RW = Chunk<R>::RW;
+  constexpr int CPC = RW / 2;
+  constexpr int H = DOF / 2;
+  constexpr int NCH = NN / CPC;    // chunks of a P row and of one chirality of the coarse vector
+  const size_t lane_id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int t = (int)(lane_id % TC);
+  const size_t st = lane_id / TC;
+  const int s = (int)(st % Vf), tile = (int)(st / Vf);
+  if (tile >= ntiles) return;
   const int a = coarse_of_blk[s / gs];
-  const R* ct = xc + (size_t)tile * tile_c;
-  R* yt = y + (size_t)tile * tile_f;
-  const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
-  const int h = dof / 2;
-  for (int k = 0; k < dof; ++k) {
-    const int sig = k / h;
-    cx<R> acc = {0, 0};
-    const cx<R>* Pr = Pc + ((size_t)s * dof + k) * N;
-    for (int j = 0; j < N; ++j) cmac(acc, Pr[j], load_one(ct, Vc, TC, a, t, sig * N + j));
-    if (accumulate) acc = acc + load_one(yt, Vf, TC, s, t, k);
-    store_one(yt, Vf, TC, s, t, k, acc);
+  const C* ct = reinterpret_cast<const C*>(xc + (size_t)tile * tile_c);
+  C* yt = reinterpret_cast<C*>(y + (size_t)tile * tile_f);
+  const C* Ps = reinterpret_cast<const C*>(P + (size_t)s * DOF * NN * 2);
+  C xv[2][NCH];
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) xv[sg][q] = ct[((size_t)(sg * NCH + q) * Vc + a) * TC + t];
+  cx<R> acc[CPC];
+#pragma unroll
+  for (int k = 0; k < DOF; ++k) {
+    const int sg = k / H;
+    cx<R> v = {0, 0};
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+      const C pv = Ps[(size_t)k * NCH + q];
+      const C x = xv[sg][q];
+      if constexpr (CPC == 1) {
+        cmac(v, cx<R>{pv.x, pv.y}, cx<R>{x.x, x.y});
+      } else {
+        cmac(v, cx<R>{pv.x, pv.y}, cx<R>{x.x, x.y});
+        cmac(v, cx<R>{pv.z, pv.w}, cx<R>{x.z, x.w});
+      }
+    }
+    acc[k % CPC] = v;
+    if (k % CPC == CPC - 1) {
+      C* out = yt + ((size_t)(k / CPC) * Vf + s) * TC + t;
+      if constexpr (CPC == 1) {
+        if (accumulate) { const C o = *out; acc[0].re += o.x; acc[0].im += o.y; }
+        *out = C{acc[0].re, acc[0].im};
+      } else {
+        if (accumulate) {
+          const C o = *out;
+          acc[0].re += o.x; acc[0].im += o.y; acc[1].re += o.z; acc[1].im += o.w;
+        }
+        *out = C{acc[0].re, acc[0].im, acc[1].re, acc[1].im};
+      }
+    }
   }
+}
+
+template <typename R, int DOF, int NN>
+static void launch_prolong(ddamg_ctx* c, const R* xc, R* y, const R* P, const LevelGeom& gf, const LevelGeom& gc,
+                           size_t tile_f, size_t tile_c, int accumulate, int ntiles) {
+  const size_t lanes = (size_t)gf.V * TC * ntiles;
+  hipLaunchKernelGGL((k_prolong<R, DOF, NN>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, c->stream, xc, y,
+                     P, gf.d_coarse_of_blk, gf.V, gf.gsize, gc.V, tile_f, tile_c, accumulate, ntiles);
+}
+
+// the fine dof and N of every level transition the library builds: the
+// fine level (12) to N = 4..32, and coarse levels (2N') to N = 4..32
+template <typename R>
+static void prolong_dispatch(ddamg_ctx* c, const R* xc, R* y, const R* P, const LevelGeom& gf, const LevelGeom& gc,
+                             int N, size_t tile_f, size_t tile_c, int accumulate, int ntiles) {
+#define DD_PROLONG_N(D)                                                                                   \
+  switch (N) {                                                                                           \
+    case 2: launch_prolong<R, D, 2>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return;   \
+    case 4: launch_prolong<R, D, 4>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return;   \
+    case 6: launch_prolong<R, D, 6>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return;   \
+    case 8: launch_prolong<R, D, 8>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return;   \
+    case 12: launch_prolong<R, D, 12>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return; \
+    case 16: launch_prolong<R, D, 16>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return; \
+    case 24: launch_prolong<R, D, 24>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return; \
+    case 32: launch_prolong<R, D, 32>(c, xc, y, P, gf, gc, tile_f, tile_c, accumulate, ntiles); return; \
+    default: break;                                                                                      \
+  }
+  switch (gf.dof) {
+    case 12: DD_PROLONG_N(12) break;
+    case 8: DD_PROLONG_N(8) break;
+    case 16: DD_PROLONG_N(16) break;
+    case 24: DD_PROLONG_N(24) break;
+    case 32: DD_PROLONG_N(32) break;
+    case 48: DD_PROLONG_N(48) break;
+    case 64: DD_PROLONG_N(64) break;
+    default: break;
+  }
+#undef DD_PROLONG_N
+  throw Error{DDAMG_EINVAL, "prolong: unsupported (dof, N): dof in {8, 12, 16, 24, 32, 48, 64}, N in {2, 4, 6, 8, "
+                            "12, 16, 24, 32}"};
 }
 
 void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulate) {
@@ -326,15 +544,15 @@ void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulat
   const int N = c->tr[level].N;
   DD_CHECK(x.prec == y.prec && x.ntiles == y.ntiles && y.nsites == gf.V && x.nsites == gc.V, DDAMG_EINVAL,
            "prolong: shape");
-  const int nsb = (gf.V + 256 / TC - 1) / (256 / TC);
-  dim3 grid(nsb * x.ntiles), blk(256);
+  const int cpc = reals_per_chunk(x.prec) / 2;
+  DD_CHECK(N % cpc == 0, DDAMG_EINVAL, "prolong: N must be whole chunks");
   if (level == 0) kernel_timing_begin(c, TIMED_PROLONG0);
   if (x.prec == P64)
-    hipLaunchKernelGGL(k_prolong<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
-                       gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+    prolong_dispatch<double>(c, x.as<double>(), y.as<double>(), c->tr[level].d_P64, gf, gc, N, y.tile_reals(),
+                             x.tile_reals(), accumulate, x.ntiles);
   else
-    hipLaunchKernelGGL(k_prolong<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
-                       gf.d_coarse_of_blk, gf.V, gf.dof, N, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate, nsb);
+    prolong_dispatch<float>(c, x.as<float>(), y.as<float>(), c->tr[level].d_P32, gf, gc, N, y.tile_reals(),
+                            x.tile_reals(), accumulate, x.ntiles);
   DD_HIP(hipGetLastError());
   if (level == 0) kernel_timing_end(c, TIMED_PROLONG0, x.ntiles);
 }

@@ -32,31 +32,36 @@ using Precond = std::function<void(const MV& v, const MV& z, const double* d_mu)
 constexpr int KMAX = 64;
 
 // ------------------------------------------------------------ kernels ---
-__global__ void k_normalize(double* __restrict__ dummy, const double* __restrict__ n2, void* x, int prec, size_t npairs,
-                            int T, int RWp, size_t tile_pairs) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < npairs; i += (size_t)gridDim.x * blockDim.x) {
-    const int tile = (int)(i / tile_pairs);
-    const int t = (int)((i / RWp) % T);
-    const double v = n2[tile * T + t];
-    const double s = v > 0 ? 1.0 / sqrt(v) : 0.0;
-    if (prec == 0) {
-      double* p = (double*)x;
-      p[2 * i] *= s;
-      p[2 * i + 1] *= s;
+// x_col /= sqrt(n2_col): one lane per 16-byte chunk (column t = unit mod T)
+template <typename C>
+__global__ void k_normalize(C* __restrict__ x, const double* __restrict__ n2, size_t nunits, int T,
+                            size_t tile_units) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = (u / tile_units) * T + u % T;
+    const double v = n2[col];
+    C a = x[u];
+    if constexpr (sizeof(a.x) == 8) {
+      const double sc = v > 0 ? 1.0 / sqrt(v) : 0.0;
+      a.x *= sc; a.y *= sc;
     } else {
-      float* p = (float*)x;
-      p[2 * i] = (float)(p[2 * i] * s);
-      p[2 * i + 1] = (float)(p[2 * i + 1] * s);
+      const float sc = (float)(v > 0 ? 1.0 / sqrt(v) : 0.0);
+      a.x *= sc; a.y *= sc; a.z *= sc; a.w *= sc;
     }
+    x[u] = a;
   }
 }
 
 void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2) {
-  const size_t np = x.reals() / 2;
-  size_t g = (np + 255) / 256;
+  DD_CHECK(x.prec == P64 || x.prec == P32, DDAMG_EINVAL, "mv_normalize: FP64 or FP32");
+  const size_t tile_units = (size_t)x.nchunk * x.nsites * x.T, nunits = tile_units * x.ntiles;
+  size_t g = (nunits + 255) / 256;
   if (g > 65536) g = 65536;
-  hipLaunchKernelGGL(k_normalize, dim3((unsigned)g), dim3(256), 0, c->stream, nullptr, d_n2, x.p, x.prec, np, x.T,
-                     reals_per_chunk(x.prec) / 2, x.tile_reals() / 2);
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_normalize<double2>, dim3((unsigned)g), dim3(256), 0, c->stream, (double2*)x.p, d_n2, nunits,
+                       x.T, tile_units);
+  else
+    hipLaunchKernelGGL(k_normalize<float4>, dim3((unsigned)g), dim3(256), 0, c->stream, (float4*)x.p, d_n2, nunits,
+                       x.T, tile_units);
   DD_HIP(hipGetLastError());
 }
 

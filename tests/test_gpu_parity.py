@@ -266,6 +266,36 @@ def test_transfer_and_coarse_operator_parity(torch_cuda, dd):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims,agg,N", [((8, 4, 4, 8), (2, 2, 2, 2), 8), ((8, 8, 8, 8), (4, 4, 4, 4), 24)])
+def test_transfer_fp32_parity(torch_cuda, dd, dims, agg, N):
+    """FP32 restriction and prolongation (the forms the mixed-precision cycle
+    runs) against the oracle's FP64 R and P with the same test vectors.  Bar:
+    each output sums K = 6 |A| (R) or N (P) products of FP32-rounded inputs
+    with FP32 accumulation, so the relative error per column is bounded by
+    about K u with u = 2^-24; the bar is K u (the measured error is printed)."""
+    torch = torch_cuda
+    say("transfer FP32", dims, agg, N)
+    ctx, U, V = _two_level_case(dd, dims, agg, N)
+    tv = S.gaussian_spinors(N, V, 67).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv)
+    blk = Blocking(dims, agg)
+    P = build_prolongator(tv, blk)
+    u = 2.0 ** -24
+    for ncol in (10, 3):
+        x = S.gaussian_spinors(ncol, V, 68 + ncol)
+        rc_ref = restrict(P, blk, x.reshape(ncol, V, 12))
+        rc = ctx.restrict(0, dd.FP32, torch.from_numpy(x).cuda()).cpu().numpy()
+        e_r = np.max(relerr_cols(rc, rc_ref))
+        xc = S.gaussian_coarse(ncol, blk.nblocks, 2 * N, 80 + ncol)
+        pr_ref = prolong(P, blk, xc).reshape(ncol, V, 4, 3)
+        pr = ctx.prolong(0, dd.FP32, torch.from_numpy(xc).cuda()).cpu().numpy()
+        e_p = np.max(relerr_cols(pr, pr_ref))
+        say(f"  ncol {ncol}: R rel err {e_r:.2e} (bar {6 * blk.bsize * u:.1e}), P rel err {e_p:.2e} (bar {N * u:.1e})")
+        assert e_r < 6 * blk.bsize * u
+        assert e_p < N * u
+    ctx.close()
+
+
 @pytest.mark.parametrize("N,N2", [(8, 8), (24, 32)])
 def test_coarse_mfma_parity(torch_cuda, dd, N, N2):
     """The FP32 coarse stencil on BF16 MFMA (FP32 accumulation) against the
