@@ -186,6 +186,21 @@ int ddamg_get_test_vectors(ddamg_ctx* h, int level, double* tv);
 int ddamg_apply_op(ddamg_ctx* h, int level, int precision, const double* mu, int n_col,
                    const double* x, double* y);
 
+/* ddamg_apply_op for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layouts and result (the same kernels), but it calls no
+ * hipMalloc, hipFree or other allocating routine.  The internal-layout input
+ * and output and the per-column shifts live in a device array of 64 MiB that
+ * the library holds on every GPU it runs on until the process ends (its
+ * address is resolved per device at the first ddamg_setup there).  A batch
+ * that needs more (two internal vectors of n_col columns rounded up to whole
+ * tiles of 8, plus the shifts) returns DDAMG_EINVAL with the size in
+ * ddamg_last_error.  Every call on one GPU shares that array, whose contents
+ * are those of the last call: calls that overlap on one GPU (several host
+ * threads, or several streams) race and must be serialised by the caller. */
+int ddamg_apply_op_noalloc(ddamg_ctx* h, int level, int precision, const double* mu, int n_col,
+                           const double* x, double* y);
+
 /* x_c = M_SAP(mu_c) f_c: sap_cycles red-black Schwarz cycles from x = 0 with
  * sap_mr_iters MR steps per block (section 2; fine level, device pointers).
  * precision DDAMG_FP64, DDAMG_FP32, or DDAMG_FP16: the FP32 smoother with

@@ -117,6 +117,7 @@ def load():
         "ddamg_set_test_vectors": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "ddamg_get_test_vectors": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "ddamg_apply_op": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
+        "ddamg_apply_op_noalloc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
         "ddamg_apply_sap": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
         "ddamg_restrict": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
         "ddamg_prolong": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
@@ -240,6 +241,13 @@ class Context:
         m, mp = _mu(mu)
         y = self._vec(level, x.shape[0])
         _check(load().ddamg_apply_op(self.h, level, precision, mp, x.shape[0], _dptr(x), _dptr(y)))
+        return y
+
+    def apply_op_noalloc(self, level, precision, mu, x, y):
+        """The no-allocation form of apply_op: the caller provides y (same
+        shape as x); the library allocates nothing."""
+        m, mp = _mu(mu)
+        _check(load().ddamg_apply_op_noalloc(self.h, level, precision, mp, x.shape[0], _dptr(x), _dptr(y)))
         return y
 
     def apply_sap(self, precision, mu, f):

@@ -3,8 +3,10 @@
 // and keeps a thread-local message for ddamg_last_error().
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 
 #include "common.h"
 
@@ -149,6 +151,28 @@ static void validate(const ddamg_params* p) {
            "inner_iters / inner_tol");
 }
 
+// ------------------------------------------------ no-allocation scratch ---
+// Device memory of ddamg_apply_op_noalloc: a file-scope device array (each
+// GPU holds its own copy while the library is loaded).  Host code never uses
+// its name as an address: the address is resolved once per device, with that
+// device current, at the first setup on it, and kept per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[64] = {};
+
+static void* noalloc_scratch_address(int dev) {
+  DD_CHECK(dev >= 0 && dev < 64, DDAMG_EDEVICE, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    DD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch)));
+    DD_CHECK(ptr != nullptr, DDAMG_EDEVICE, "no device address for the scratch array");
+    g_scratch_addr[dev] = ptr;
+  }
+  return g_scratch_addr[dev];
+}
+
 int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device, const double* const* tv_init,
                 void* hip_stream, ddamg_ctx** out) {
   return guarded([&]() -> int {
@@ -158,6 +182,8 @@ int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
     auto t0 = std::chrono::steady_clock::now();
     ddamg_ctx* c = new ddamg_ctx();
     try {
+      DD_HIP(hipGetDevice(&c->device));
+      c->noalloc_scratch = noalloc_scratch_address(c->device);
       c->p = *p;
       if (c->p.col_tile == 0) c->p.col_tile = 8;
       c->T = 8;
@@ -245,6 +271,60 @@ int ddamg_apply_op(ddamg_ctx* c, int level, int precision, const double* mu, int
     mv_free(c, a);
     mv_free(c, b);
     c->pool.release(d_mu);
+    return DDAMG_OK;
+  });
+}
+
+// ddamg_apply_op without any allocation: the internal-layout input and
+// output and the per-column shifts live in the device's scratch array.
+int ddamg_apply_op_noalloc(ddamg_ctx* c, int level, int precision, const double* mu, int n_col, const double* x,
+                           double* y) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mu && x && y && n_col >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    DD_CHECK(level >= 0 && level < c->nlev, DDAMG_ESTATE, "level not built");
+    DD_CHECK(precision == DDAMG_FP64 || precision == DDAMG_FP32, DDAMG_EINVAL, "precision");
+    DD_CHECK(c->noalloc_scratch, DDAMG_ESTATE, "scratch array not resolved for this device");
+    for (int i = 0; i < n_col; ++i) DD_CHECK(std::isfinite(mu[i]), DDAMG_EINVAL, "mu contains NaN/Inf");
+    const LevelGeom& g = c->geom[level];
+    MV a;
+    a.prec = precision == DDAMG_FP64 ? P64 : P32;
+    a.T = c->T;
+    a.ntiles = (n_col + a.T - 1) / a.T;
+    a.dof = g.dof;
+    a.nsites = g.V;
+    a.nchunk = 2 * a.dof / reals_per_chunk(a.prec);
+    a.owned = false;
+    auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t vb = up256(a.bytes()), mb = up256((size_t)a.ncol() * sizeof(double));
+    const size_t need = 2 * vb + mb;
+    if (need > NOALLOC_SCRATCH_BYTES) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "batch needs %zu bytes of scratch, more than the %zu of the no-allocation entry",
+                    need, NOALLOC_SCRATCH_BYTES);
+      throw Error{DDAMG_EINVAL, msg};
+    }
+    char* base = static_cast<char*>(c->noalloc_scratch);
+    MV b = a;
+    a.p = base;
+    b.p = base + vb;
+    double* d_mu = reinterpret_cast<double*>(base + 2 * vb);
+    // the padded columns of the last tile start at zero, with zero shift;
+    // the array keeps the previous call's contents, so clear it (fill kernel)
+    mv_zero(c, a);
+    MV mupad = a;
+    mupad.p = d_mu;
+    mupad.prec = P64;
+    mupad.nchunk = 1;
+    mupad.nsites = 1;
+    mupad.dof = 1;
+    mupad.T = 1;
+    mupad.ntiles = (int)(mb / 16);   // mb / 16 chunks of 16 bytes
+    mv_zero(c, mupad);
+    DD_HIP(hipMemcpyAsync(d_mu, mu, (size_t)n_col * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    to_internal(c, level, x, n_col, a);
+    operator_apply(c, level, a, b, d_mu);
+    from_internal(c, level, b, n_col, y);
+    DD_HIP(hipStreamSynchronize(c->stream));
     return DDAMG_OK;
   });
 }

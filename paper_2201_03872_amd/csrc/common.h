@@ -139,6 +139,8 @@ struct Stats {
 struct ddamg_ctx {
   ddamg_params p;
   hipStream_t stream = nullptr;
+  int device = 0;                     // device current at setup
+  void* noalloc_scratch = nullptr;    // that device's address of the no-allocation scratch array
   hipStream_t cap_stream = nullptr;   // private stream for graph capture (default priority)
   int T = 8;
   int nlev = 1;
