@@ -130,7 +130,14 @@ typedef struct ddamg_params {
 typedef struct ddamg_col_info {
   int    outer_iters;        /* outer FGMRES iterations this column took                        */
   int    converged;          /* 1 if the FP64 true residual met tol                             */
-  double true_rel_res;       /* ||b - D(mu) x|| / ||b|| in FP64 on the GPU                      */
+  double true_rel_res;       /* ||b - D(mu) x|| / ||b|| in FP64 on the GPU when the column left */
+  double err_vs_fp64;        /* the same in an independent FP64 pass after the solve: the       */
+                             /* caller's x and b read back from the canonical arrays, r = b -  */
+                             /* D(mu) x with the FP64 stencil and links, ||r|| / ||b||; the     */
+                             /* result's error against the FP64 operator whatever the precision */
+                             /* the preconditioner ran in                                       */
+  int    fallbacks;          /* learned-smoother calls that fell back to SAP while the column  */
+                             /* was in flight                                                   */
 } ddamg_col_info;
 
 typedef struct ddamg_stats {
@@ -170,7 +177,10 @@ int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
 
 /* Replace the test vectors of level transition `level` (host, canonical
  * layout as for tv_init) and rebuild P, R and every coarser operator from
- * them (the test vectors are orthonormalised per aggregate and chirality). */
+ * them (the test vectors are orthonormalised per aggregate and chirality).
+ * Paper section 2: the interpolation is built from a few approximate low
+ * modes (test vectors), the coarse operator is the Galerkin product.  The
+ * hook lets a caller (the parity tests) impose the oracle's vectors. */
 int ddamg_set_test_vectors(ddamg_ctx* h, int level, const double* tv);
 
 /* Copy out the orthonormalised test vectors (P) of a level transition, host,
@@ -178,7 +188,10 @@ int ddamg_set_test_vectors(ddamg_ctx* h, int level, const double* tv);
 int ddamg_get_test_vectors(ddamg_ctx* h, int level, double* tv);
 
 /* y_c = D_level(mu_c) x_c for n_col columns (device pointers, canonical
- * layout of that level).  level 0 = fine operator (the paper's batched
+ * layout of that level).  Paper section 3 and Fig. 2: the operator is
+ * applied to a bundle of vectors at once, each matrix entry loaded once for
+ * all of them; Fig. 6 caption: D_TM = D_W + i (dmu) mu gamma5.
+ * level 0 = fine operator (the paper's batched
  * operator application, each link loaded once for a tile of columns);
  * level > 0 = Galerkin coarse operator D_c(0) + i (dmu) mu_c gamma5_c.
  * precision DDAMG_FP64 or DDAMG_FP32 (FP32 uses 2-row compressed links on the
@@ -330,6 +343,13 @@ int ddamg_autotune(ddamg_ctx* h, int n_col, int* values);
  * call instead (counted in ddamg_stats.learned_fallbacks). */
 int ddamg_smoother_set_weights(ddamg_ctx* h, const double* w1, const double* w2);
 int ddamg_smoother_get_weights(ddamg_ctx* h, double* w1, double* w2);
+/* Load / store the network weights from / to a file (host path): the 8 bytes
+ * "DDAMGPTC", a little-endian int32 format version (1), then layer 1 and
+ * layer 2 as little-endian double complex in the shapes above (288 + 288
+ * complexes).  A missing, short, or foreign file returns DDAMG_EINVAL with
+ * the reason in ddamg_last_error, and leaves the current weights unchanged. */
+int ddamg_load_smoother(ddamg_ctx* h, const char* path);
+int ddamg_save_smoother(ddamg_ctx* h, const char* path);
 /* y = f(x), one network pass, for n_col fine vectors (device, canonical layout). */
 int ddamg_smoother_apply(ddamg_ctx* h, int n_col, const double* x, double* y);
 /* One layer (1 or 2), or its adjoint when adjoint != 0, on FP32 internal data:

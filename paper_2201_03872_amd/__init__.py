@@ -76,7 +76,13 @@ class Params(ctypes.Structure):
 
 
 class ColInfo(ctypes.Structure):
-    _fields_ = [("outer_iters", ctypes.c_int), ("converged", ctypes.c_int), ("true_rel_res", ctypes.c_double)]
+    _fields_ = [("outer_iters", ctypes.c_int), ("converged", ctypes.c_int), ("true_rel_res", ctypes.c_double),
+                ("err_vs_fp64", ctypes.c_double), ("fallbacks", ctypes.c_int)]
+
+
+def _info(i):
+    return dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res,
+                err_vs_fp64=i.err_vs_fp64, fallbacks=i.fallbacks)
 
 
 class Stats(ctypes.Structure):
@@ -136,6 +142,8 @@ def load():
         "ddamg_smoother_set_weights": (ctypes.c_int, [vp, vp, vp]),
         "ddamg_smoother_get_weights": (ctypes.c_int, [vp, vp, vp]),
         "ddamg_smoother_apply": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),
+        "ddamg_load_smoother": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "ddamg_save_smoother": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "ddamg_ptc_layer": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
         "ddamg_ptc_weight_grad": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "ddamg_train_smoother": (ctypes.c_int, [vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -295,8 +303,7 @@ class Context:
         info = (ColInfo * ncol)()
         st = _check(load().ddamg_solve(self.h, mp, len(m), _dptr(b), n_rhs, _dptr(x), int(x0 is not None), info),
                     allow=(OK, NOT_CONVERGED))
-        return x, [dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res)
-                   for i in info], st
+        return x, [_info(i) for i in info], st
 
     def solve_batch(self, systems, x0=None):
         """systems: list of (mus, b) with b a [n_rhs][V][4][3] complex128 CUDA
@@ -318,8 +325,7 @@ class Context:
         xs, infos, o = [], [], 0
         for r, k in zip(n_rhs, n_shift):
             xs.append(x[o:o + r * k])
-            infos.append([dict(outer_iters=i.outer_iters, converged=bool(i.converged), true_rel_res=i.true_rel_res)
-                          for i in info[o:o + r * k]])
+            infos.append([_info(i) for i in info[o:o + r * k]])
             o += r * k
         return xs, infos, st
 
@@ -354,6 +360,12 @@ class Context:
         b = np.empty((9, 1, 2, 4, 4), dtype=np.complex128)
         _check(load().ddamg_smoother_get_weights(self.h, a.ctypes.data, b.ctypes.data))
         return a, b
+
+    def load_smoother(self, path):
+        _check(load().ddamg_load_smoother(self.h, os.fsencode(path)))
+
+    def save_smoother(self, path):
+        _check(load().ddamg_save_smoother(self.h, os.fsencode(path)))
 
     def smoother_apply(self, x):
         y = self._vec(0, x.shape[0])

@@ -509,6 +509,8 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
       info[i].outer_iters = job.iters[i];
       info[i].converged = job.converged[i];
       info[i].true_rel_res = job.relres[i];
+      info[i].err_vs_fp64 = job.err[i];
+      info[i].fallbacks = job.fallbacks[i];
     }
   }
   c->st.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -814,6 +816,52 @@ int ddamg_smoother_get_weights(ddamg_ctx* c, double* w1, double* w2) {
   return guarded([&]() -> int {
     DD_CHECK(c && w1 && w2, DDAMG_EINVAL, "null pointer");
     ptc_get_weights(c, w1, w2);
+    return DDAMG_OK;
+  });
+}
+
+static const char kPtcMagic[8] = {'D', 'D', 'A', 'M', 'G', 'P', 'T', 'C'};
+constexpr int kPtcVersion = 1;
+constexpr size_t kPtcW = 9 * 2 * 1 * 4 * 4 * 2;   // reals per layer
+
+int ddamg_load_smoother(ddamg_ctx* c, const char* path) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && path, DDAMG_EINVAL, "null pointer");
+    FILE* f = std::fopen(path, "rb");
+    DD_CHECK(f, DDAMG_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    int32_t version = 0;
+    std::vector<double> w1(kPtcW), w2(kPtcW);
+    const bool ok = std::fread(magic, 1, 8, f) == 8 && std::fread(&version, sizeof version, 1, f) == 1 &&
+                    std::fread(w1.data(), sizeof(double), kPtcW, f) == kPtcW &&
+                    std::fread(w2.data(), sizeof(double), kPtcW, f) == kPtcW;
+    const bool extra = ok && std::fgetc(f) != EOF;
+    std::fclose(f);
+    DD_CHECK(ok, DDAMG_EINVAL, std::string("short smoother file ") + path);
+    DD_CHECK(std::memcmp(magic, kPtcMagic, 8) == 0, DDAMG_EINVAL, std::string("not a smoother file: ") + path);
+    DD_CHECK(version == kPtcVersion, DDAMG_EINVAL, "unsupported smoother file version");
+    DD_CHECK(!extra, DDAMG_EINVAL, std::string("trailing bytes in smoother file ") + path);
+    for (double v : w1) DD_CHECK(std::isfinite(v), DDAMG_EINVAL, "smoother weights contain NaN/Inf");
+    for (double v : w2) DD_CHECK(std::isfinite(v), DDAMG_EINVAL, "smoother weights contain NaN/Inf");
+    ptc_set_weights(c, w1.data(), w2.data());
+    return DDAMG_OK;
+  });
+}
+
+int ddamg_save_smoother(ddamg_ctx* c, const char* path) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && path, DDAMG_EINVAL, "null pointer");
+    DD_CHECK(ptc_ready(c), DDAMG_ESTATE, "smoother weights not set");
+    std::vector<double> w1(kPtcW), w2(kPtcW);
+    ptc_get_weights(c, w1.data(), w2.data());
+    FILE* f = std::fopen(path, "wb");
+    DD_CHECK(f, DDAMG_EINVAL, std::string("cannot create ") + path);
+    const int32_t version = kPtcVersion;
+    const bool ok = std::fwrite(kPtcMagic, 1, 8, f) == 8 && std::fwrite(&version, sizeof version, 1, f) == 1 &&
+                    std::fwrite(w1.data(), sizeof(double), kPtcW, f) == kPtcW &&
+                    std::fwrite(w2.data(), sizeof(double), kPtcW, f) == kPtcW;
+    const bool closed = std::fclose(f) == 0;
+    DD_CHECK(ok && closed, DDAMG_EINVAL, std::string("cannot write ") + path);
     return DDAMG_OK;
   });
 }

@@ -273,6 +273,8 @@ struct OuterJob {
   std::vector<int> iters;
   std::vector<double> relres;   // true FP64 relative residual when the column left
   std::vector<char> converged;
+  std::vector<double> err;      // FP64 relative residual of the caller's x, recomputed after the solve
+  std::vector<int> fallbacks;   // learned-smoother fallbacks while the column was in flight
   int total = 0;                // outer iterations (cycles x steps) of the whole batch
 };
 void outer_solve(ddamg_ctx* c, OuterJob& job);

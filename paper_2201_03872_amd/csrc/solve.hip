@@ -826,6 +826,45 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
 // waiting columns take their place.  When the membership changes, the active
 // columns are gathered into dense tiles (ping-pong buffers), so converged
 // columns cost nothing afterwards (section 3: shrinking the vector bundle).
+// An independent FP64 check of every column as the caller receives it: x
+// and b are read back from the canonical arrays into the outer solve's FP64
+// buffers, wmax columns at a time, r = b - D(mu) x with the FP64 stencil,
+// and err = ||r|| / ||b||.
+static void final_check(ddamg_ctx* c, OuterJob& job, LW& w, int wmax) {
+  const int T = c->T, ncol = job.ncol;
+  const int cap = w.cap;
+  for (int c0 = 0; c0 < ncol; c0 += wmax) {
+    const int n = std::min(wmax, ncol - c0);
+    const int ntn = (n + T - 1) / T, nc = ntn * T;
+    std::vector<int> xm(nc, -1), bm(nc, -1);
+    std::vector<double> mu(nc, 0.0);
+    for (int i = 0; i < n; ++i) {
+      xm[i] = c0 + i;
+      bm[i] = job.rhs_of[c0 + i];
+      mu[i] = job.mu[c0 + i];
+    }
+    const MV b = get(c, w.cb, 0, P64, cap, ntn), x = get(c, w.cx, 0, P64, cap, ntn);
+    const MV r = get(c, w.cb2, 0, P64, cap, ntn);
+    int* d_xm = w.d_map;
+    int* d_bm = w.d_map + cap * T;
+    DD_HIP(hipMemcpyAsync(d_xm, xm.data(), nc * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    DD_HIP(hipMemcpyAsync(d_bm, bm.data(), nc * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    DD_HIP(hipMemcpyAsync(w.d_muc, mu.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    mv_zero(c, b);
+    mv_zero(c, x);
+    canon_cols(c, 0, b, d_bm, const_cast<double*>(job.b), 0);
+    canon_cols(c, 0, x, d_xm, job.x, 0);
+    fine_residual(c, b, x, r, w.d_muc);
+    double* d_n2 = w.d_h + (size_t)KMAX * cap * T * 2;
+    std::vector<double> rn(nc), bn(nc);
+    mv_norm2(c, r, d_n2);
+    copy_to_host(c, d_n2, rn.data(), nc * sizeof(double));
+    mv_norm2(c, b, d_n2);
+    copy_to_host(c, d_n2, bn.data(), nc * sizeof(double));
+    for (int i = 0; i < n; ++i) job.err[c0 + i] = bn[i] > 0 ? std::sqrt(rn[i] / bn[i]) : 0.0;
+  }
+}
+
 void outer_solve(ddamg_ctx* c, OuterJob& job) {
   const int T = c->T, ncol = job.ncol;
   const int m = std::min(c->p.outer_restart, KMAX - 1);
@@ -865,6 +904,8 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
   job.iters.assign(ncol, 0);
   job.relres.assign(ncol, 0.0);
   job.converged.assign(ncol, 0);
+  job.err.assign(ncol, 0.0);
+  job.fallbacks.assign(ncol, 0);
   std::vector<double> bnorm(ncol, -1.0);
   std::vector<int> act;            // slot -> column (-1: empty)
   int next = 0, cur = 0, nt = 0, total = 0;
@@ -994,11 +1035,17 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
         act[i] = -1;
         leave[i] = 0;
       }
+    const int fb0 = c->st.learned_fallbacks;
     gmres_cycle(c, 0, w, nt, x, w.d_muc, &pc, prec, m, false, beta, done, tol_abs, est, bn, cy, d_n2, total);
+    const int dfb = c->st.learned_fallbacks - fb0;
     for (int i = 0; i < nc; ++i)
-      if (act[i] >= 0) job.iters[act[i]] += cy.kc[i];
+      if (act[i] >= 0) {
+        job.iters[act[i]] += cy.kc[i];
+        if (!done[i]) job.fallbacks[act[i]] += dfb;
+      }
   }
   job.total = total;
+  final_check(c, job, w, wmax);
 }
 
 // --------------------------------------------------------------- MG ---

@@ -392,6 +392,9 @@ def _solve_and_check(torch, dd, w, precision, **over):
     mm = np.tile(mus, w.n_rhs)
     rel = O.col_norm(bb - op.apply(xs, mm)) / O.col_norm(bb)
     say("  true residuals (oracle operator)", rel.max(), "iters", [i["outer_iters"] for i in info], ctx.stats())
+    # the library's own after-the-solve FP64 check of every column agrees with the oracle's
+    err = np.array([i["err_vs_fp64"] for i in info])
+    assert np.max(np.abs(err - rel)) < 1e-13, (err, rel)
     ctx.close()
     return rel, info, st
 

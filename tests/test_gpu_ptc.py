@@ -165,6 +165,8 @@ def test_fallback_to_sap_when_the_network_fails(torch_cuda, dd):
     x, info, st = ctx.solve(np.array(w.mus), b)
     assert st == dd.OK
     assert ctx.stats()["learned_fallbacks"] > 0
+    # every column was in flight while the net failed: each records fallbacks
+    assert all(i["fallbacks"] > 0 for i in info)
     op = O.WilsonTM(U, w.dims, kappa=w.kappa)
     bb = np.repeat(S.rhs_for(w), 3, axis=0)
     rel = O.col_norm(bb - op.apply(x.cpu().numpy(), np.tile(np.array(w.mus), 2))) / O.col_norm(bb)
@@ -182,3 +184,36 @@ def test_learned_smoother_requires_weights(dd, torch_cuda):
         ctx.solve(np.array(w.mus), torch.from_numpy(S.rhs_for(w)).cuda())
     assert e.value.code == dd.ESTATE
     ctx.close()
+
+
+def test_smoother_file_round_trip_and_rejection(torch_cuda, dd, tmp_path):
+    """ddamg_save_smoother / ddamg_load_smoother: a saved net loads back into
+    another context bit for bit (the file holds the FP64 master weights); a
+    foreign, short or missing file is rejected and leaves the weights alone."""
+    w = S.workload("tm_4x4x4x4_2rhs_3shift")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    p = dd.default_params(dims=w.dims, kappa=w.kappa, n_levels=1, sap_block=w.sap_block)
+    a, b = dd.Context(p, U), dd.Context(p, U)
+    rng = np.random.default_rng(5)
+    W1 = rng.standard_normal((9, 2, 1, 4, 4)) + 1j * rng.standard_normal((9, 2, 1, 4, 4))
+    W2 = rng.standard_normal((9, 1, 2, 4, 4)) + 1j * rng.standard_normal((9, 1, 2, 4, 4))
+    a.set_smoother_weights(W1, W2)
+    f = tmp_path / "net.ddamg"
+    a.save_smoother(str(f))
+    assert f.stat().st_size == 8 + 4 + 2 * 288 * 16
+    b.load_smoother(str(f))
+    V1, V2 = b.smoother_weights()
+    assert np.array_equal(V1, a.smoother_weights()[0]) and np.array_equal(V2, a.smoother_weights()[1])
+    raw = f.read_bytes()
+    for bad, why in ((b"XXXXXXXX" + raw[8:], "not a smoother file"), (raw[:100], "short"),
+                     (raw + b"\0", "trailing")):
+        g = tmp_path / "bad.ddamg"
+        g.write_bytes(bad)
+        with pytest.raises(dd.DDAMGError) as e:
+            b.load_smoother(str(g))
+        assert e.value.code == dd.EINVAL and why in str(e.value)
+    with pytest.raises(dd.DDAMGError):
+        b.load_smoother(str(tmp_path / "missing.ddamg"))
+    assert np.array_equal(b.smoother_weights()[0], V1)
+    a.close()
+    b.close()
