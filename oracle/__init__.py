@@ -13,6 +13,7 @@ Plain, slow, obviously-correct numpy in complex128:
 * ``krylov``    - GMRES / FGMRES / block GMRES (section 4)
 * ``solver``    - the MG-preconditioned simultaneous multi-rhs multi-shift solve
 * ``ptc``       - gauge-covariant parallel-transport convolution smoother
+* ``nondegenerate`` - the non-degenerate twisted-mass doublet operator
 """
 from .dirac import WilsonTM, gammas, gamma5
 from .multigrid import (Blocking, FineLevel, CoarseOp, build_prolongator, restrict, prolong,
@@ -20,3 +21,4 @@ from .multigrid import (Blocking, FineLevel, CoarseOp, build_prolongator, restri
 from .krylov import gmres, fgmres, block_gmres, col_norm, col_dot
 from .solver import MGParams, OracleMG
 from . import ptc
+from .nondegenerate import nd_apply, nd_mus
