@@ -199,6 +199,17 @@ int ddamg_get_test_vectors(ddamg_ctx* h, int level, double* tv);
 int ddamg_apply_op(ddamg_ctx* h, int level, int precision, const double* mu, int n_col,
                    const double* x, double* y);
 
+/* Non-degenerate twisted mass (paper section 1: the method generalised to the
+ * non-degenerate doublet).  Doublet operator on psi = (psi_u, psi_d):
+ *   D_ND psi = ( D(+mubar) psi_u - epsbar psi_d ,  D(-mubar) psi_d - epsbar psi_u )
+ * i.e. D_W (x) 1 + i mubar gamma5 (x) tau3 - epsbar (x) tau1, with D(mu) the
+ * operator above (clover term included when c_sw != 0).  n_pair doublets,
+ * each with its own (mubar, epsbar) (host arrays); x, y device pointers in the
+ * fine canonical layout with the two flavours of doublet i as columns 2i (u)
+ * and 2i+1 (d): [pair][flavour][V][4][3]. */
+int ddamg_apply_op_nd(ddamg_ctx* h, int precision, const double* mubar, const double* epsbar, int n_pair,
+                      const double* x, double* y);
+
 /* ddamg_apply_op for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * same arguments, layouts and result (the same kernels), but it calls no
@@ -254,6 +265,18 @@ int ddamg_solve(ddamg_ctx* h, const double* mu, int n_shift, const double* b, in
  * and leave the solve as they converge.  Returns as ddamg_solve. */
 int ddamg_solve_batch(ddamg_ctx* h, int n_sys, const int* n_rhs, const int* n_shift, const double* mu,
                       const double* b, double* x, int use_x0, ddamg_col_info* info);
+
+/* Solve D_ND x_i = b_i for n_pair doublets (layout as ddamg_apply_op_nd; b
+ * and x device pointers, x the initial guess if use_x0) to the relative
+ * residual tol of each doublet (both flavours together), with FP64 flexible
+ * GMRES whose Krylov vectors are the doublets (dots and norms summed over the
+ * two flavour columns) and whose preconditioner is the multigrid cycle of
+ * this context applied flavour by flavour with shifts +mubar and -mubar
+ * (flavour diagonal; the epsbar coupling is left to the outer iteration).
+ * info: 2 n_pair entries, equal within a doublet; the residuals are the
+ * doublet's. */
+int ddamg_solve_nd(ddamg_ctx* h, const double* mubar, const double* epsbar, int n_pair, const double* b, double* x,
+                   int use_x0, ddamg_col_info* info);
 
 /* Solve D_level(mu_c) x_c = b_c on a coarse level (level >= 1) with
  * restarted GMRES (block = 0, per column) or block GMRES (block != 0: columns

@@ -124,6 +124,8 @@ def load():
         "ddamg_get_test_vectors": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "ddamg_apply_op": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
         "ddamg_apply_op_noalloc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
+        "ddamg_apply_op_nd": (ctypes.c_int, [vp, ctypes.c_int, dp, dp, ctypes.c_int, vp, vp]),
+        "ddamg_solve_nd": (ctypes.c_int, [vp, dp, dp, ctypes.c_int, vp, vp, ctypes.c_int, vp]),
         "ddamg_apply_sap": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.c_int, vp, vp]),
         "ddamg_restrict": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
         "ddamg_prolong": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]),
@@ -257,6 +259,26 @@ class Context:
         m, mp = _mu(mu)
         _check(load().ddamg_apply_op_noalloc(self.h, level, precision, mp, x.shape[0], _dptr(x), _dptr(y)))
         return y
+
+    def apply_op_nd(self, precision, mubar, epsbar, x):
+        """Doublet operator on x: [n_pair][2][V][4][3] (or [2 n_pair][V][4][3])
+        complex128 CUDA tensor."""
+        m, mp = _mu(mubar)
+        e, ep = _mu(epsbar)
+        y = torch_empty_like(x)
+        _check(load().ddamg_apply_op_nd(self.h, precision, mp, ep, len(m), _dptr(x), _dptr(y)))
+        return y
+
+    def solve_nd(self, mubar, epsbar, b, x0=None):
+        """Doublet solves: b [n_pair][2][V][4][3] complex128 CUDA tensor.
+        Returns (x, info per column, status)."""
+        m, mp = _mu(mubar)
+        e, ep = _mu(epsbar)
+        x = x0.clone() if x0 is not None else torch_zeros_like(b)
+        info = (ColInfo * (2 * len(m)))()
+        st = _check(load().ddamg_solve_nd(self.h, mp, ep, len(m), _dptr(b), _dptr(x), int(x0 is not None),
+                                          ctypes.cast(info, ctypes.c_void_p)), allow=(OK, NOT_CONVERGED))
+        return x, [_info(i) for i in info], st
 
     def apply_sap(self, precision, mu, f):
         m, mp = _mu(mu)
@@ -411,6 +433,16 @@ class Context:
         sec = ctypes.c_double()
         _check(load().ddamg_time_op(self.h, op, level, precision, n_col, n_iter, ctypes.byref(sec)))
         return sec.value
+
+
+def torch_empty_like(t):
+    import torch
+    return torch.empty_like(t)
+
+
+def torch_zeros_like(t):
+    import torch
+    return torch.zeros_like(t)
 
 
 def params_for_workload(w, **overrides) -> Params:

@@ -275,6 +275,44 @@ int ddamg_apply_op(ddamg_ctx* c, int level, int precision, const double* mu, int
   });
 }
 
+int ddamg_apply_op_nd(ddamg_ctx* c, int precision, const double* mubar, const double* epsbar, int n_pair,
+                      const double* x, double* y) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mubar && epsbar && x && y && n_pair >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    DD_CHECK(precision == DDAMG_FP64 || precision == DDAMG_FP32, DDAMG_EINVAL, "precision");
+    const int prec = precision == DDAMG_FP64 ? P64 : P32;
+    const int ncol = 2 * n_pair;
+    std::vector<double> hmu(ncol), eps;
+    for (int i = 0; i < n_pair; ++i) {
+      DD_CHECK(std::isfinite(mubar[i]) && std::isfinite(epsbar[i]), DDAMG_EINVAL, "mubar / epsbar contain NaN/Inf");
+      hmu[2 * i] = mubar[i];
+      hmu[2 * i + 1] = -mubar[i];
+    }
+    MV a = mv_alloc(c, 0, prec, ncol), b = mv_alloc(c, 0, prec, ncol);
+    eps.assign(a.ncol(), 0.0);
+    for (int i = 0; i < n_pair; ++i) eps[2 * i] = eps[2 * i + 1] = epsbar[i];
+    double* d_mu = upload_mu(c, hmu.data(), ncol, a.ncol());
+    double* d_eps = upload_mu(c, eps.data(), a.ncol(), a.ncol());
+    to_internal(c, 0, x, ncol, a);
+    const double* saved = c->nd_eps;
+    c->nd_eps = d_eps;
+    try {
+      operator_apply(c, 0, a, b, d_mu);
+    } catch (...) {
+      c->nd_eps = saved;
+      throw;
+    }
+    c->nd_eps = saved;
+    from_internal(c, 0, b, ncol, y);
+    DD_HIP(hipStreamSynchronize(c->stream));
+    mv_free(c, a);
+    mv_free(c, b);
+    c->pool.release(d_mu);
+    c->pool.release(d_eps);
+    return DDAMG_OK;
+  });
+}
+
 // ddamg_apply_op without any allocation: the internal-layout input and
 // output and the per-column shifts live in the device's scratch array.
 int ddamg_apply_op_noalloc(ddamg_ctx* c, int level, int precision, const double* mu, int n_col, const double* x,
@@ -465,7 +503,8 @@ static int active_columns(ddamg_ctx* c, int ncol) {
 
 // Solve the columns (shift hmu[i], right-hand side b[rhs_of[i]]) together.
 static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std::vector<int>& rhs_of,
-                         const double* b, double* x, int use_x0, ddamg_col_info* info) {
+                         const double* b, double* x, int use_x0, ddamg_col_info* info,
+                         const std::vector<double>* eps = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   c->st.middle_calls = c->st.middle_iters = c->st.bottom_calls = c->st.bottom_iters = 0;
   c->st.fine_ops = c->st.sap_calls = 0;
@@ -498,6 +537,7 @@ static int solve_columns(ddamg_ctx* c, const std::vector<double>& hmu, const std
   job.b = b;
   job.x = x;
   job.use_x0 = use_x0 != 0;
+  if (eps) job.eps = *eps;
   job.max_active = active_columns(c, ncol);
   outer_solve(c, job);
   DD_HIP(hipStreamSynchronize(c->stream));
@@ -552,6 +592,25 @@ int ddamg_solve_batch(ddamg_ctx* c, int n_sys, const int* n_rhs, const int* n_sh
       k0 += n_shift[s];
     }
     return solve_columns(c, hmu, rhs_of, b, x, use_x0, info);
+  });
+}
+
+int ddamg_solve_nd(ddamg_ctx* c, const double* mubar, const double* epsbar, int n_pair, const double* b, double* x,
+                   int use_x0, ddamg_col_info* info) {
+  return guarded([&]() -> int {
+    DD_CHECK(c && mubar && epsbar && b && x && n_pair >= 1, DDAMG_EINVAL, "null pointer or empty batch");
+    const int ncol = 2 * n_pair;
+    std::vector<double> hmu(ncol), eps(ncol);
+    std::vector<int> rhs_of(ncol);
+    for (int i = 0; i < n_pair; ++i) {
+      DD_CHECK(std::isfinite(mubar[i]) && std::isfinite(epsbar[i]), DDAMG_EINVAL, "mubar / epsbar contain NaN/Inf");
+      hmu[2 * i] = mubar[i];
+      hmu[2 * i + 1] = -mubar[i];
+      eps[2 * i] = eps[2 * i + 1] = epsbar[i];
+      rhs_of[2 * i] = 2 * i;
+      rhs_of[2 * i + 1] = 2 * i + 1;
+    }
+    return solve_columns(c, hmu, rhs_of, b, x, use_x0, info, &eps);
   });
 }
 

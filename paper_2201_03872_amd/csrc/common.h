@@ -140,6 +140,7 @@ struct ddamg_ctx {
   ddamg_params p;
   hipStream_t stream = nullptr;
   int device = 0;                     // device current at setup
+  const double* nd_eps = nullptr;     // set while the fine operator is the doublet operator: epsbar per column
   void* noalloc_scratch = nullptr;    // that device's address of the no-allocation scratch array
   hipStream_t cap_stream = nullptr;   // private stream for graph capture (default priority)
   int T = 8;
@@ -273,6 +274,7 @@ struct OuterJob {
   std::vector<int> iters;
   std::vector<double> relres;   // true FP64 relative residual when the column left
   std::vector<char> converged;
+  std::vector<double> eps;      // doublet solves: epsbar per column (pairs of columns), empty otherwise
   std::vector<double> err;      // FP64 relative residual of the caller's x, recomputed after the solve
   std::vector<int> fallbacks;   // learned-smoother fallbacks while the column was in flight
   int total = 0;                // outer iterations (cycles x steps) of the whole batch

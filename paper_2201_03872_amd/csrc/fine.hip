@@ -1210,14 +1210,56 @@ static void launch_dslash(ddamg_ctx* c, const MV& x, const MV& y, const MV* b, c
   c->st.fine_ops++;
 }
 
+// Flavour coupling of the non-degenerate doublet operator: the two flavours
+// of a doublet are the columns t and t^1 of one tile, so the partner of a
+// 16-byte unit is the unit next to it (u ^ 1): y += sign * epsbar_col * x(partner).
+template <typename C>
+__global__ void k_flavour_mix(const C* __restrict__ x, C* __restrict__ y, const double* __restrict__ eps,
+                              size_t nunits, int T, size_t tile_units, double sign) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = (u / tile_units) * T + u % T;
+    const C p = x[u ^ 1];
+    C v = y[u];
+    if constexpr (sizeof(v.x) == 8) {
+      const double e = sign * eps[col];
+      v.x += e * p.x; v.y += e * p.y;
+    } else {
+      const float e = (float)(sign * eps[col]);
+      v.x += e * p.x; v.y += e * p.y; v.z += e * p.z; v.w += e * p.w;
+    }
+    y[u] = v;
+  }
+}
+
+static void flavour_mix(ddamg_ctx* c, const MV& x, const MV& y, double sign) {
+  DD_CHECK(x.prec == y.prec && x.reals() == y.reals() && x.T % 2 == 0, DDAMG_EINVAL, "flavour mix: shape");
+  const size_t tile_units = (size_t)x.nchunk * x.nsites * x.T, nunits = tile_units * x.ntiles;
+  size_t g = (nunits + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_flavour_mix<double2>, dim3((unsigned)g), dim3(256), 0, c->stream, (const double2*)x.p,
+                       (double2*)y.p, c->nd_eps, nunits, x.T, tile_units, sign);
+  else if (x.prec == P32)
+    hipLaunchKernelGGL(k_flavour_mix<float4>, dim3((unsigned)g), dim3(256), 0, c->stream, (const float4*)x.p,
+                       (float4*)y.p, c->nd_eps, nunits, x.T, tile_units, sign);
+  else
+    throw Error{DDAMG_EINVAL, "flavour mix: FP64 or FP32"};
+  DD_HIP(hipGetLastError());
+}
+
+// With c->nd_eps set (the outer solve of doublets, ddamg_apply_op_nd) the
+// fine operator is the doublet operator: D(+-mubar) per column (the shifts
+// carry the signs) and - epsbar tau1.
 void fine_dslash(ddamg_ctx* c, const MV& x, const MV& y, const double* d_mu) {
   kernel_timing_begin(c, TIMED_DSLASH);
   launch_dslash<0>(c, x, y, nullptr, d_mu);
   kernel_timing_end(c, TIMED_DSLASH, x.ntiles);
+  if (c->nd_eps) flavour_mix(c, x, y, -1.0);
 }
 
 void fine_residual(ddamg_ctx* c, const MV& b, const MV& x, const MV& r, const double* d_mu) {
   launch_dslash<1>(c, x, r, &b, d_mu);
+  if (c->nd_eps) flavour_mix(c, x, r, +1.0);
 }
 
 void fine_masked(ddamg_ctx* c, const MV& x, const MV& y, int mode, int hopi) {

@@ -65,6 +65,46 @@ void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2) {
   DD_HIP(hipGetLastError());
 }
 
+// Doublets: the two columns of a pair form one vector, so their dots and
+// squared norms are summed and the sum given to both.  h: [nq][ncol] complex.
+__global__ void k_pair_sum_c(double* __restrict__ h, int nq, int ncol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = ncol / 2;
+  if (i >= nq * np) return;
+  const int q = i / np, pr = i % np;
+  double* a = h + ((size_t)q * ncol + 2 * pr) * 2;
+  const double re = a[0] + a[2], im = a[1] + a[3];
+  a[0] = a[2] = re;
+  a[1] = a[3] = im;
+}
+
+__global__ void k_pair_sum_r(double* __restrict__ n2, int ncol) {
+  const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pr >= ncol / 2) return;
+  const double v = n2[2 * pr] + n2[2 * pr + 1];
+  n2[2 * pr] = n2[2 * pr + 1] = v;
+}
+
+static void pair_sum_c(ddamg_ctx* c, double* h, int nq, int ncol) {
+  const int n = nq * (ncol / 2);
+  hipLaunchKernelGGL(k_pair_sum_c, dim3((n + 255) / 256), dim3(256), 0, c->stream, h, nq, ncol);
+  DD_HIP(hipGetLastError());
+}
+
+static void pair_sum_r(ddamg_ctx* c, double* n2, int ncol) {
+  hipLaunchKernelGGL(k_pair_sum_r, dim3((ncol / 2 + 255) / 256), dim3(256), 0, c->stream, n2, ncol);
+  DD_HIP(hipGetLastError());
+}
+
+// While alive, the fine operator is the doublet operator with epsbar per
+// column at `eps` (or the flavour-diagonal one with eps = nullptr).
+struct NDScope {
+  ddamg_ctx* c;
+  const double* saved;
+  NDScope(ddamg_ctx* c_, const double* eps) : c(c_), saved(c_->nd_eps) { c->nd_eps = eps; }
+  ~NDScope() { c->nd_eps = saved; }
+};
+
 // dst (FP16 basis, same layout) = src (FP32) / sqrt(n2_col) * hscale: the
 // normalisation and the store of a new basis vector in one pass
 __global__ void k_normalize_f16(const float* __restrict__ src, _Float16* __restrict__ dst,
@@ -117,6 +157,7 @@ struct LW {
   double* d_vsc = nullptr;       // FP16 basis: [KMAX+1][ncol] 1/c_j^2 of the stored vectors + [ncol] store scale
   int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
   double* d_muc = nullptr;       // [ncol] shifts of the active columns
+  double* d_epsc = nullptr;      // [ncol] doublet coupling epsbar of the active columns
   struct GraphState* gs = nullptr;   // captured GMRES steps (unpreconditioned solves)
 };
 
@@ -184,8 +225,10 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     if (w.d_vsc) c->pool.release(w.d_vsc);
     if (w.d_map) c->pool.release(w.d_map);
     if (w.d_muc) c->pool.release(w.d_muc);
+    if (w.d_epsc) c->pool.release(w.d_epsc);
     w.d_map = nullptr;
     w.d_muc = nullptr;
+    w.d_epsc = nullptr;
     destroy_graphs(c, w.gs);
     w.gs = nullptr;
     w.cap = ntiles;
@@ -227,6 +270,7 @@ struct Cycle {
   // FP16 basis stored unnormalised: entry scale c_j of each stored vector,
   // 1/c_j^2 and the store scale of the next vector (uploaded each step)
   std::vector<double> cj, vsc, nstore, osc_exact;
+  bool pairs = false;           // doublets: columns 2i, 2i+1 form one Krylov vector
   Cycle(int ncol, int m_) : m(m_), H((size_t)ncol * (m_ + 1) * m_), g((size_t)ncol * (m_ + 1)), sn((size_t)ncol * m_),
                             cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol),
                             cj((size_t)(m_ + 1) * ncol, 1.0), vsc((size_t)(KMAX + 2) * ncol, 1.0), nstore(ncol, 1.0),
@@ -297,11 +341,13 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     std::vector<MV> Vs(j + 1);
     for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, vprec, cap, nt);
     mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
+    if (cy.pairs) pair_sum_c(c, w.d_h, j + 1, ncol);
     if (half)   // w' straight into the next FP16 basis vector, unnormalised
       mv_multiaxpy_norm2_into_f16(c, Vs.data(), j + 1, w.d_h, d_cinv2, vn, basis(c, w.V, j + 1, level, vprec, cap, nt),
                                   d_osc, d_n2);
     else
       mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
+    if (cy.pairs) pair_sum_r(c, d_n2, ncol);
     // one copy of the dots and the norm
     const size_t nh = (size_t)(j + 1) * ncol * 2;
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
@@ -441,7 +487,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
 
 // r = b - A x into V[0] of the workspace; beta (host) = column norms, d_n2 their squares
 static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, const MV& x, const double* d_mu,
-                           bool x_is_zero, double* d_n2, std::vector<double>& beta) {
+                           bool x_is_zero, double* d_n2, std::vector<double>& beta, bool pairs = false) {
   const int prec = b.prec, ncol = nt * c->T;
   // the residual lands where gmres_cycle normalises it: V[0], or the
   // working-precision vector when the basis is stored in FP16
@@ -456,6 +502,7 @@ static void residual_norms(ddamg_ctx* c, int level, LW& w, int nt, const MV& b, 
     mv_sub(c, b, t, r);
   }
   mv_norm2(c, r, d_n2);
+  if (pairs) pair_sum_r(c, d_n2, ncol);
   beta.resize(ncol);
   copy_to_host(c, d_n2, beta.data(), ncol * sizeof(double));
   for (int i = 0; i < ncol; ++i) beta[i] = host_norm_guard(beta[i]);
@@ -833,15 +880,17 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
 static void final_check(ddamg_ctx* c, OuterJob& job, LW& w, int wmax) {
   const int T = c->T, ncol = job.ncol;
   const int cap = w.cap;
+  const bool pairs = !job.eps.empty();
   for (int c0 = 0; c0 < ncol; c0 += wmax) {
     const int n = std::min(wmax, ncol - c0);
     const int ntn = (n + T - 1) / T, nc = ntn * T;
     std::vector<int> xm(nc, -1), bm(nc, -1);
-    std::vector<double> mu(nc, 0.0);
+    std::vector<double> mu(nc, 0.0), eps(nc, 0.0);
     for (int i = 0; i < n; ++i) {
       xm[i] = c0 + i;
       bm[i] = job.rhs_of[c0 + i];
       mu[i] = job.mu[c0 + i];
+      if (pairs) eps[i] = job.eps[c0 + i];
     }
     const MV b = get(c, w.cb, 0, P64, cap, ntn), x = get(c, w.cx, 0, P64, cap, ntn);
     const MV r = get(c, w.cb2, 0, P64, cap, ntn);
@@ -850,16 +899,22 @@ static void final_check(ddamg_ctx* c, OuterJob& job, LW& w, int wmax) {
     DD_HIP(hipMemcpyAsync(d_xm, xm.data(), nc * sizeof(int), hipMemcpyHostToDevice, c->stream));
     DD_HIP(hipMemcpyAsync(d_bm, bm.data(), nc * sizeof(int), hipMemcpyHostToDevice, c->stream));
     DD_HIP(hipMemcpyAsync(w.d_muc, mu.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (pairs) DD_HIP(hipMemcpyAsync(w.d_epsc, eps.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     mv_zero(c, b);
     mv_zero(c, x);
     canon_cols(c, 0, b, d_bm, const_cast<double*>(job.b), 0);
     canon_cols(c, 0, x, d_xm, job.x, 0);
-    fine_residual(c, b, x, r, w.d_muc);
+    {
+      NDScope nd(c, pairs ? w.d_epsc : nullptr);
+      fine_residual(c, b, x, r, w.d_muc);
+    }
     double* d_n2 = w.d_h + (size_t)KMAX * cap * T * 2;
     std::vector<double> rn(nc), bn(nc);
     mv_norm2(c, r, d_n2);
+    if (pairs) pair_sum_r(c, d_n2, nc);
     copy_to_host(c, d_n2, rn.data(), nc * sizeof(double));
     mv_norm2(c, b, d_n2);
+    if (pairs) pair_sum_r(c, d_n2, nc);
     copy_to_host(c, d_n2, bn.data(), nc * sizeof(double));
     for (int i = 0; i < n; ++i) job.err[c0 + i] = bn[i] > 0 ? std::sqrt(rn[i] / bn[i]) : 0.0;
   }
@@ -868,7 +923,12 @@ static void final_check(ddamg_ctx* c, OuterJob& job, LW& w, int wmax) {
 void outer_solve(ddamg_ctx* c, OuterJob& job) {
   const int T = c->T, ncol = job.ncol;
   const int m = std::min(c->p.outer_restart, KMAX - 1);
-  const int wmax = std::max(1, std::min(ncol, job.max_active));
+  // doublets: the two columns of a pair are one Krylov vector of the doublet
+  // operator; they enter, converge and leave together (even slot counts)
+  const bool pairs = !job.eps.empty();
+  DD_CHECK(!pairs || (ncol % 2 == 0 && (int)job.eps.size() == ncol), DDAMG_EINVAL, "doublet columns come in pairs");
+  int wmax = std::max(1, std::min(ncol, job.max_active));
+  if (pairs) wmax = std::max(2, wmax - wmax % 2);
   const int ntw = (wmax + T - 1) / T;
   const int prec = c->p.precision == DDAMG_MIXED ? P32 : P64;
   LW& w = lw(c, 0, P64, ntw);
@@ -877,11 +937,13 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
   if (!w.d_map) {
     w.d_map = (int*)c->pool.alloc((size_t)cap * T * 3 * sizeof(int));
     w.d_muc = (double*)c->pool.alloc((size_t)cap * T * sizeof(double));
+    w.d_epsc = (double*)c->pool.alloc((size_t)cap * T * sizeof(double));
   }
   MV Bs[2] = {get(c, w.cb, 0, P64, cap, ntw), get(c, w.cb2, 0, P64, cap, ntw)};
   MV Xs[2] = {get(c, w.cx, 0, P64, cap, ntw), get(c, w.cx2, 0, P64, cap, ntw)};
   MV vin = get(c, w0.rho, 0, prec, w0.cap, ntw);
   Precond smooth = [&](const MV& v, const MV& z, const double* dm) {
+    NDScope diag(c, nullptr);   // doublets: the preconditioner is flavour diagonal (shifts +-mubar)
     if (c->nlev == 1) fine_smoother(c, v, z, dm);
     else mg_cycle(c, 0, dm, v, z);
   };
@@ -891,6 +953,7 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
   // FGMRES wins the accuracy back.
   const int mi = std::min(c->p.inner_iters, KMAX - 1);
   Precond pc = [&](const MV& v, const MV& z, const double* dm) {
+    NDScope diag(c, nullptr);
     const MV in = (prec == v.prec) ? v : vin.tiles(0, v.ntiles);
     if (prec != v.prec) mv_copy(c, v, in);
     if (mi > 0) {
@@ -911,6 +974,7 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
   int next = 0, cur = 0, nt = 0, total = 0;
   double* d_n2 = w.d_h + (size_t)KMAX * cap * T * 2;
   Cycle cy(cap * T, m);
+  cy.pairs = pairs;
   std::vector<double> beta, bn, tol_abs, est;
   std::vector<char> done;
   std::vector<char> leave;
@@ -935,10 +999,11 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
       keep_map.resize(ntn * T, -1);
       b_map.assign(ntn * T, -1);
       x_map.assign(ntn * T, -1);
-      std::vector<double> nmu(ntn * T, 0.0);
+      std::vector<double> nmu(ntn * T, 0.0), neps(ntn * T, 0.0);
       for (int i = 0; i < ntn * T; ++i) {
         if (nact[i] < 0) continue;
         nmu[i] = job.mu[nact[i]];
+        if (pairs) neps[i] = job.eps[nact[i]];
         if (i >= nkeep) {
           b_map[i] = job.rhs_of[nact[i]];
           if (job.use_x0) x_map[i] = nact[i];
@@ -951,6 +1016,7 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
       DD_HIP(hipMemcpyAsync(d_bmap, b_map.data(), ntn * T * sizeof(int), hipMemcpyHostToDevice, c->stream));
       DD_HIP(hipMemcpyAsync(d_xmap, x_map.data(), ntn * T * sizeof(int), hipMemcpyHostToDevice, c->stream));
       DD_HIP(hipMemcpyAsync(w.d_muc, nmu.data(), ntn * T * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      DD_HIP(hipMemcpyAsync(w.d_epsc, neps.data(), ntn * T * sizeof(double), hipMemcpyHostToDevice, c->stream));
       const int alt = act.empty() ? cur : 1 - cur;
       const MV nb = Bs[alt].tiles(0, ntn), nx = Xs[alt].tiles(0, ntn);
       if (act.empty()) {
@@ -973,6 +1039,7 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
       // right-hand-side norms of the new columns
       std::vector<double> bn2(nc);
       mv_norm2(c, nb, d_n2);
+      if (pairs) pair_sum_r(c, d_n2, nc);
       copy_to_host(c, d_n2, bn2.data(), nc * sizeof(double));
       bn.assign(nc, 0.0);
       tol_abs.assign(nc, 0.0);
@@ -994,7 +1061,8 @@ void outer_solve(ddamg_ctx* c, OuterJob& job) {
     }
     const MV b = Bs[cur].tiles(0, nt), x = Xs[cur].tiles(0, nt);
     const int nc = nt * T;
-    residual_norms(c, 0, w, nt, b, x, w.d_muc, false, d_n2, beta);
+    NDScope nd(c, pairs ? w.d_epsc : nullptr);
+    residual_norms(c, 0, w, nt, b, x, w.d_muc, false, d_n2, beta, pairs);
     bool any_leave = false;
     for (int i = 0; i < nc; ++i) {
       est[i] = beta[i];
