@@ -18,7 +18,7 @@ Plain, slow, obviously-correct numpy in complex128:
 from .dirac import WilsonTM, gammas, gamma5
 from .multigrid import (Blocking, FineLevel, CoarseOp, build_prolongator, restrict, prolong,
                         galerkin, sap, mr_smoother, block_mr, block_mr_oddeven)
-from .krylov import gmres, fgmres, block_gmres, col_norm, col_dot
+from .krylov import gmres, fgmres, block_gmres, gmres_dr, harmonic_ritz, col_norm, col_dot
 from .solver import MGParams, OracleMG
 from . import ptc
 from .nondegenerate import nd_apply, nd_mus

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["gmres", "fgmres", "block_gmres", "col_dot", "col_norm"]
+__all__ = ["gmres", "fgmres", "block_gmres", "gmres_dr", "harmonic_ritz", "col_dot", "col_norm"]
 
 
 def col_dot(a, b):
@@ -195,3 +195,97 @@ def block_gmres(apply, B, tol, maxit, X0=None):
     X = X + (Vmat @ Y).T.reshape(shape)
     relres = col_norm(B - apply(X)) / np.where(bnorm > 0, bnorm, 1.0)
     return X, dict(iters=k, relres=relres)
+
+
+def harmonic_ritz(Hbar, k):
+    """The k harmonic Ritz pairs of smallest modulus of an Arnoldi relation
+    A V_m = V_{m+1} Hbar ((m+1) x m): theta and g solve
+    (H_m + |h_{m+1,m}|^2 f e_m^T) g = theta g with f = H_m^{-H} e_m, which is
+    the standard form of Hbar^H Hbar g = theta H_m^H g."""
+    m = Hbar.shape[1]
+    Hm = Hbar[:m, :m]
+    em = np.zeros(m)
+    em[-1] = 1.0
+    f = np.linalg.solve(Hm.conj().T, em)
+    T = Hm + abs(Hbar[m, m - 1]) ** 2 * np.outer(f, em)
+    theta, G = np.linalg.eig(T)
+    idx = np.argsort(np.abs(theta), kind="stable")[:k]
+    return theta[idx], G[:, idx]
+
+
+def gmres_dr(apply, b, tol, m, k, maxit, x0=None):
+    """GMRES with deflated restarting, GMRES-DR(m, k) (section 4 of the paper:
+    deflated restarting at the coarsest level; Morgan's construction).
+
+    Each cycle runs Arnoldi to m basis vectors and takes the least-squares
+    correction.  At a restart the k harmonic Ritz vectors of smallest
+    harmonic Ritz value, together with the residual's coordinate vector, span
+    the first k+1 vectors of the next basis: with Q the orthonormal factor of
+    [g_1 .. g_k (one zero row appended), c - Hbar y], V <- V Q and
+    Hbar <- Q^H Hbar Q[:m, :k], and the residual coordinates become Q^H
+    (c - Hbar y); Arnoldi then continues from vector k+1.  k = 0 is GMRES(m).
+    Columns are independent (apply acts on the active batch).  Stops a column
+    when its least-squares residual estimate is <= tol ||b_c||, or after maxit
+    operator applications.  Returns (x, info: iters, relres (true), cycles)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.shape[0]
+    shp = b.shape[1:]
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128)
+    r = b - (apply(x, np.arange(n)) if x0 is not None else 0)
+    bnorm = col_norm(b)
+    tol_abs = tol * np.where(bnorm > 0, bnorm, 1.0)
+    iters = np.zeros(n, dtype=np.int64)
+    cycles = np.zeros(n, dtype=np.int64)
+    beta = col_norm(r)
+    # per-column state: basis (list of vectors), Hbar, residual coordinates c, start index
+    Vs = [[r[c] / beta[c]] if beta[c] > 0 else [] for c in range(n)]
+    Hs = [np.zeros((m + 1, m), dtype=np.complex128) for _ in range(n)]
+    cs = [np.concatenate([[beta[c]], np.zeros(m)]).astype(np.complex128) for c in range(n)]
+    j0 = [0] * n
+    done = [beta[c] <= tol_abs[c] for c in range(n)]
+    while True:
+        act = np.array([c for c in range(n) if not done[c]], dtype=np.int64)
+        if act.size == 0:
+            break
+        # one Arnoldi step on every active column
+        W = apply(np.stack([Vs[c][-1] for c in act]), act)
+        for a, c in enumerate(act):
+            j = len(Vs[c]) - 1
+            w = W[a]
+            for i in range(j + 1):
+                h = np.vdot(Vs[c][i], w)
+                Hs[c][i, j] = h
+                w = w - h * Vs[c][i]
+            hn = np.linalg.norm(w)
+            Hs[c][j + 1, j] = hn
+            Vs[c].append(w / hn if hn > 0 else w)
+            iters[c] += 1
+            Hj = Hs[c][:j + 2, :j + 1]
+            y, *_ = np.linalg.lstsq(Hj, cs[c][:j + 2], rcond=None)
+            rho = cs[c][:j + 2] - Hj @ y
+            conv = np.linalg.norm(rho) <= tol_abs[c] or hn == 0 or iters[c] >= maxit
+            if conv or j + 1 == m:
+                V = np.stack(Vs[c][:j + 1])
+                x[c] += np.tensordot(y, V, axes=1)
+                cycles[c] += 1
+                if conv:
+                    done[c] = True
+                    continue
+                # deflated restart
+                kk = min(k, m - 1)
+                Vm1 = np.stack(Vs[c])                              # (m+1) basis vectors
+                if kk > 0:
+                    _, G = harmonic_ritz(Hs[c], kk)
+                    P = np.concatenate([np.vstack([G, np.zeros((1, kk))]), rho[:, None]], axis=1)
+                else:
+                    P = rho[:, None]
+                Q, _ = np.linalg.qr(P)
+                Hn = Q.conj().T @ Hs[c] @ Q[:m, :kk]
+                Vs[c] = list(np.tensordot(Q.T, Vm1, axes=1))       # V_new_i = sum_l V_l Q_li
+                Hs[c] = np.zeros((m + 1, m), dtype=np.complex128)
+                Hs[c][:kk + 1, :kk] = Hn
+                cs[c] = np.zeros(m + 1, dtype=np.complex128)
+                cs[c][:kk + 1] = Q.conj().T @ rho
+                j0[c] = kk
+    relres = col_norm(b - apply(x, np.arange(n))) / np.where(bnorm > 0, bnorm, 1.0)
+    return x, dict(iters=iters, relres=relres, cycles=cycles)

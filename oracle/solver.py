@@ -27,7 +27,7 @@ import numpy as np
 from .dirac import WilsonTM
 from .multigrid import (Blocking, FineLevel, CoarseOp, build_prolongator, restrict, prolong,
                         galerkin, sap, mr_smoother)
-from .krylov import gmres, fgmres, block_gmres, col_norm
+from .krylov import gmres, fgmres, block_gmres, gmres_dr, col_norm
 
 __all__ = ["MGParams", "OracleMG"]
 
@@ -54,6 +54,8 @@ class MGParams:
     coarse_smooth_iters: int = 2        # MR steps of the middle-level smoother
     coarsest_block: bool = False
     coarse_gamma5: int = 0              # Krylov on gamma5_c D_c: 0 off, 1 coarsest, 2 every coarse level
+    bottom_dr_k: int = 0                # > 0: GMRES-DR(bottom_restart, k) at the coarsest level
+    bottom_restart: int = 63
 
 
 class OracleMG:
@@ -120,6 +122,10 @@ class OracleMG:
                                             rhs[idx], p.r_b, p.bottom_maxit)
                     ec[idx] = sol
                     self.stats["bottom_iters"].append(info["iters"])
+            elif p.bottom_dr_k > 0:
+                ec, info = gmres_dr(lambda x, act: op(x, mus[act]), rhs, p.r_b, p.bottom_restart, p.bottom_dr_k,
+                                    p.bottom_maxit)
+                self.stats["bottom_iters"].extend(list(info["iters"]))
             else:
                 ec, info = gmres(lambda x, act: op(x, mus[act]), rhs, p.r_b, p.bottom_maxit)
                 self.stats["bottom_iters"].extend(list(info["iters"]))
