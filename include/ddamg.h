@@ -125,6 +125,11 @@ typedef struct ddamg_params {
                              /* gamma5_c D_c(mu) = Q_c + i dmu mu (same solution, same residual */
                              /* norm; the shifted-Hermitian operator is normal): 0 = off,       */
                              /* 1 = the coarsest level, 2 = every coarse level                  */
+  int    bottom_restart;     /* restart length m of the coarsest-level GMRES (0: min(bottom_maxit, */
+                             /* 63))                                                             */
+  int    bottom_dr_k;        /* > 0: the coarsest level runs GMRES with deflated restarting,    */
+                             /* GMRES-DR(m, k) (section 4): k harmonic Ritz vectors carried     */
+                             /* over each restart; 0 = plain restarted GMRES                     */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

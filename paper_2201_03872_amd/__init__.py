@@ -72,6 +72,8 @@ class Params(ctypes.Structure):
         ("csw", ctypes.c_double),
         ("sap_oddeven", ctypes.c_int),
         ("coarse_gamma5", ctypes.c_int),
+        ("bottom_restart", ctypes.c_int),
+        ("bottom_dr_k", ctypes.c_int),
     ]
 
 

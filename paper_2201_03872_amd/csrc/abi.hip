@@ -102,6 +102,8 @@ void ddamg_default_params(ddamg_params* p) {
   p->csw = 0.0;
   p->sap_oddeven = 0;
   p->coarse_gamma5 = 0;
+  p->bottom_restart = 0;
+  p->bottom_dr_k = 0;
 }
 
 static void validate(const ddamg_params* p) {
@@ -139,6 +141,10 @@ static void validate(const ddamg_params* p) {
   DD_CHECK(p->outer_restart >= 1 && p->outer_restart <= 63, DDAMG_EINVAL, "outer_restart in [1, 63]");
   DD_CHECK(p->middle_restart >= 1 && p->middle_restart <= 63, DDAMG_EINVAL, "middle_restart in [1, 63]");
   DD_CHECK(p->bottom_maxit >= 1, DDAMG_EINVAL, "bottom_maxit >= 1");
+  DD_CHECK(p->bottom_restart >= 0 && p->bottom_restart <= 63, DDAMG_EINVAL, "bottom_restart in [0, 63]");
+  DD_CHECK(p->bottom_dr_k >= 0 && (p->bottom_dr_k == 0 || p->bottom_dr_k + 1 <
+                                   (p->bottom_restart > 0 ? p->bottom_restart : std::min(p->bottom_maxit, 63))),
+           DDAMG_EINVAL, "bottom_dr_k must be below the coarsest restart length minus one");
   DD_CHECK(p->setup_fine_iters >= 0 && p->setup_fine_iters <= 63, DDAMG_EINVAL, "setup_fine_iters in [0, 63]");
   DD_CHECK(p->setup_boot >= 0 && p->setup_boot <= 16, DDAMG_EINVAL, "setup_boot in [0, 16]");
   DD_CHECK(p->setup_coarse_iters >= 1 && p->setup_coarse_iters <= 63, DDAMG_EINVAL, "setup_coarse_iters in [1, 63]");
@@ -629,8 +635,14 @@ int ddamg_coarse_solve(ddamg_ctx* c, int level, int precision, int block, const 
     double* d_mu = upload_mu(c, mu, n_col, B.ncol());
     const int m = std::min(maxit, 63);
     std::vector<int> it;
-    if (block) block_gmres(c, level, d_mu, B, X, true, tol, m, maxit, &it, nullptr, nullptr);
-    else level_gmres(c, level, d_mu, B, X, tol, m, maxit, &it, nullptr, nullptr);
+    if (block) {
+      block_gmres(c, level, d_mu, B, X, true, tol, m, maxit, &it, nullptr, nullptr);
+    } else if (c->p.bottom_dr_k > 0) {   // GMRES-DR(bottom_restart, bottom_dr_k)
+      level_gmres_dr(c, level, d_mu, B, X, tol, c->p.bottom_restart > 0 ? c->p.bottom_restart : m, c->p.bottom_dr_k,
+                     maxit, &it);
+    } else {
+      level_gmres(c, level, d_mu, B, X, tol, m, maxit, &it, nullptr, nullptr);
+    }
     MV x64 = prec == P64 ? X : mv_like(c, X, P64);
     if (prec != P64) mv_copy(c, X, x64);
     from_internal(c, level, x64, n_col, x);

@@ -286,6 +286,9 @@ void block_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const
 void free_block_work(ddamg_ctx* c);
 void level_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, double tol, int m, int maxit,
                  std::vector<int>* iters, std::vector<double>* relres, int* total);
+// the same with deflated restarting, GMRES-DR(m, k)
+void level_gmres_dr(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, double tol, int m, int k,
+                    int maxit, std::vector<int>* iters);
 
 // ---- host helpers ----
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);

@@ -20,6 +20,7 @@
 #include <tuple>
 
 #include "common.h"
+#include "hess_eig.h"
 #include "device.h"
 
 namespace ddamg {
@@ -861,18 +862,307 @@ void level_gmres(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const
   if (total) *total = ko.total;
 }
 
+// ------------------------------------------------ deflated restarting ---
+// GMRES with deflated restarting, GMRES-DR(m, k) (section 4 and the outlook:
+// deflated restarting at the coarsest level), for unpreconditioned solves on
+// a level, every column with its own Arnoldi process (all columns in
+// lockstep, converged ones idle).  A cycle builds the basis to m vectors; at
+// a restart the k harmonic Ritz vectors of smallest harmonic Ritz value
+// (host: the small eigenproblem H_m + |h_{m+1,m}|^2 f e_m^T,
+// f = H_m^{-H} e_m) and the residual's coordinates c - Hbar y are
+// orthonormalised into Q ((m+1) x (k+1)); the next cycle starts from the
+// basis V Q (k+1 multi-axpys with per-column coefficients, on the device),
+// Hbar Q^H Hbar Q[:m, :k] and the residual coordinates Q^H (c - Hbar y).  The
+// least squares are kept triangular by Givens rotations (those that reduce
+// the dense leading block after a restart, then one per step).
+struct DrRot {
+  int r0;
+  double c;
+  cd s;
+};
+
+static void dr_apply_rot(const DrRot& q, cd* v) {
+  const cd a = v[q.r0], b = v[q.r0 + 1];
+  v[q.r0] = q.c * a + q.s * b;
+  v[q.r0 + 1] = -std::conj(q.s) * a + q.c * b;
+}
+
+static DrRot dr_make_rot(int r0, cd a, cd b) {
+  double cc;
+  cd ss;
+  hess_givens(a, b, cc, ss);
+  return DrRot{r0, cc, ss};
+}
+
+void krylov_dr(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, bool x_zero, double tol, int m,
+               int kdr, int maxit, KrylovOut* out) {
+  const int nt = b.ntiles, ncol = b.ncol();
+  DD_CHECK(m >= 2 && m < KMAX && kdr >= 0 && kdr < m, DDAMG_EINVAL, "GMRES-DR: need 2 <= m <= 63 and 0 <= k < m");
+  LW& w = lw(c, level, b.prec, nt, 2);   // a workspace of its own (the captured graphs keep theirs)
+  const int cap = w.cap, prec = b.prec;
+  std::vector<double> bn(ncol), tol_abs(ncol), est(ncol), beta;
+  double* d_n2 = w.d_h + (size_t)KMAX * ncol * 2;
+  mv_norm2(c, b, d_n2);
+  copy_to_host(c, d_n2, bn.data(), ncol * sizeof(double));
+  std::vector<char> done(ncol, 0);
+  for (int i = 0; i < ncol; ++i) {
+    bn[i] = host_norm_guard(bn[i]);
+    tol_abs[i] = tol * bn[i];
+    if (bn[i] == 0) done[i] = 1;
+  }
+  if (x_zero) mv_zero(c, x);
+  residual_norms(c, level, w, nt, b, x, d_mu, x_zero, d_n2, beta);
+  MV v0 = basis(c, w.V, 0, level, prec, cap, nt);
+  mv_normalize(c, v0, d_n2);
+  std::vector<int> iters(ncol, 0), kc(ncol, 0);
+  // per column: Hbar and residual coordinates (unrotated), their rotated
+  // forms, and the rotations
+  std::vector<cd> Hb((size_t)ncol * (m + 1) * m), cv((size_t)ncol * (m + 1));
+  std::vector<cd> Hr((size_t)ncol * (m + 1) * m), g((size_t)ncol * (m + 1));
+  std::vector<std::vector<DrRot>> rots(ncol);
+  std::vector<cd> hbuf((size_t)KMAX * ncol + ncol);
+  std::vector<double> hraw((size_t)KMAX * ncol * 2 + ncol);
+  for (int i = 0; i < ncol; ++i) {
+    est[i] = beta[i];
+    if (beta[i] <= tol_abs[i]) done[i] = 1;
+    cv[(size_t)i * (m + 1)] = beta[i];
+    g[(size_t)i * (m + 1)] = beta[i];
+  }
+  int total = 0, j0 = 0;
+  auto H_ = [&](std::vector<cd>& A, int i, int r, int q) -> cd& { return A[((size_t)i * (m + 1) + r) * m + q]; };
+  while (true) {
+    bool alld = true;
+    for (int i = 0; i < ncol; ++i) alld &= (bool)done[i];
+    if (alld || total >= maxit) break;
+    for (int i = 0; i < ncol; ++i) kc[i] = done[i] ? -2 : -1;   // -2: idle this cycle
+    int jend = j0;
+    for (int j = j0; j < m && total < maxit; ++j) {
+      MV vj = basis(c, w.V, j, level, prec, cap, nt);
+      MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
+      operator_apply(c, level, vj, vn, d_mu);
+      std::vector<MV> Vs(j + 1);
+      for (int q = 0; q <= j; ++q) Vs[q] = basis(c, w.V, q, level, prec, cap, nt);
+      mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
+      mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
+      copy_to_host(c, w.d_h, hraw.data(), (size_t)(j + 1) * ncol * 2 * sizeof(double));
+      copy_to_host(c, d_n2, hraw.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
+      mv_normalize(c, vn, d_n2);
+      ++total;
+      jend = j + 1;
+      bool all_now = true;
+      for (int i = 0; i < ncol; ++i) {
+        if (kc[i] != -1) continue;
+        iters[i]++;
+        const double hn = host_norm_guard(hraw[(size_t)KMAX * ncol * 2 + i]);
+        for (int q = 0; q <= j; ++q)
+          H_(Hb, i, q, j) = cd(hraw[((size_t)q * ncol + i) * 2], hraw[((size_t)q * ncol + i) * 2 + 1]);
+        H_(Hb, i, j + 1, j) = hn;
+        std::vector<cd> col(m + 1, cd(0));
+        for (int q = 0; q <= j + 1; ++q) col[q] = H_(Hb, i, q, j);
+        for (const DrRot& r : rots[i]) dr_apply_rot(r, col.data());
+        const DrRot nr = dr_make_rot(j, col[j], col[j + 1]);
+        dr_apply_rot(nr, col.data());
+        rots[i].push_back(nr);
+        cd* gi = &g[(size_t)i * (m + 1)];
+        dr_apply_rot(nr, gi);
+        for (int q = 0; q <= j + 1; ++q) H_(Hr, i, q, j) = col[q];
+        est[i] = std::abs(gi[j + 1]);
+        if (est[i] <= tol_abs[i] || hn == 0) kc[i] = j + 1;
+        else all_now = false;
+      }
+      if (all_now) break;
+    }
+    // least squares and x += V y for every column that worked this cycle
+    std::vector<double> coef((size_t)jend * ncol * 2, 0.0);
+    std::vector<std::vector<cd>> ys(ncol);
+    for (int i = 0; i < ncol; ++i) {
+      if (kc[i] == -2) continue;
+      const int k = kc[i] >= 0 ? kc[i] : jend;
+      if (kc[i] >= 0) done[i] = 1;
+      std::vector<cd> y(k);
+      const cd* gi = &g[(size_t)i * (m + 1)];
+      for (int q = k - 1; q >= 0; --q) {
+        cd acc = gi[q];
+        for (int p2 = q + 1; p2 < k; ++p2) acc -= H_(Hr, i, q, p2) * y[p2];
+        const cd d = H_(Hr, i, q, q);
+        y[q] = std::abs(d) > 0 ? acc / d : cd(0);
+      }
+      for (int q = 0; q < k; ++q) {
+        coef[((size_t)q * ncol + i) * 2] = y[q].real();
+        coef[((size_t)q * ncol + i) * 2 + 1] = y[q].imag();
+      }
+      ys[i] = std::move(y);
+    }
+    {
+      std::vector<MV> Vs(jend);
+      for (int q = 0; q < jend; ++q) Vs[q] = basis(c, w.V, q, level, prec, cap, nt);
+      DD_HIP(hipMemcpyAsync(w.d_aux, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      mv_multiaxpy(c, Vs.data(), jend, w.d_aux, x, +1);
+      DD_HIP(hipStreamSynchronize(c->stream));   // coef is host memory of this scope
+    }
+    bool alld2 = true;
+    for (int i = 0; i < ncol; ++i) alld2 &= (bool)done[i];
+    if (alld2 || total >= maxit) break;
+    // deflated restart of the columns still working (jend == m for them)
+    const int kk = std::min(kdr, m - 1);
+    std::vector<double> qcoef((size_t)(kk + 1) * (m + 1) * ncol * 2, 0.0);   // [new i][old l][col] complex
+    for (int i = 0; i < ncol; ++i) {
+      if (done[i]) {   // idle column: keep its first vectors (nothing reads them)
+        for (int q = 0; q <= kk; ++q) qcoef[(((size_t)q * (m + 1) + q) * ncol + i) * 2] = 1.0;
+        continue;
+      }
+      const std::vector<cd>& y = ys[i];
+      // rho = c - Hbar y
+      std::vector<cd> rho(m + 1);
+      for (int r = 0; r <= m; ++r) {
+        cd acc = cv[(size_t)i * (m + 1) + r];
+        for (int q = 0; q < m; ++q) acc -= H_(Hb, i, r, q) * y[q];
+        rho[r] = acc;
+      }
+      // harmonic Ritz vectors: T = H_m + |h_{m+1,m}|^2 f e_m^T, H_m^H f = e_m
+      std::vector<cd> P((size_t)(m + 1) * (kk + 1), cd(0));   // [row][col]
+      if (kk > 0) {
+        std::vector<cd> A((size_t)m * m), f(m, cd(0));
+        for (int r = 0; r < m; ++r)
+          for (int q = 0; q < m; ++q) A[(size_t)r * m + q] = std::conj(H_(Hb, i, q, r));   // H_m^H
+        f[m - 1] = 1.0;
+        // solve H_m^H f = e_m (lower Hessenberg) by Gaussian elimination with partial pivoting
+        {
+          std::vector<cd> M(A);
+          std::vector<cd> rhs(f);
+          for (int col = 0; col < m; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < m; ++r)
+              if (std::abs(M[(size_t)r * m + col]) > std::abs(M[(size_t)piv * m + col])) piv = r;
+            if (piv != col) {
+              for (int q = 0; q < m; ++q) std::swap(M[(size_t)col * m + q], M[(size_t)piv * m + q]);
+              std::swap(rhs[col], rhs[piv]);
+            }
+            const cd d = M[(size_t)col * m + col];
+            DD_CHECK(std::abs(d) > 0, DDAMG_EBREAKDOWN, "GMRES-DR: singular H_m at a restart");
+            for (int r = col + 1; r < m; ++r) {
+              const cd fct = M[(size_t)r * m + col] / d;
+              if (fct == cd(0)) continue;
+              for (int q = col; q < m; ++q) M[(size_t)r * m + q] -= fct * M[(size_t)col * m + q];
+              rhs[r] -= fct * rhs[col];
+            }
+          }
+          for (int r = m - 1; r >= 0; --r) {
+            cd acc = rhs[r];
+            for (int q = r + 1; q < m; ++q) acc -= M[(size_t)r * m + q] * f[q];
+            f[r] = acc / M[(size_t)r * m + r];
+          }
+        }
+        const double h2 = std::norm(H_(Hb, i, m, m - 1));
+        std::vector<cd> T((size_t)m * m);
+        for (int r = 0; r < m; ++r)
+          for (int q = 0; q < m; ++q) T[(size_t)r * m + q] = H_(Hb, i, r, q) + (q == m - 1 ? h2 * f[r] : cd(0));
+        std::vector<cd> ev, vec;
+        DD_CHECK(hess_eig(m, T, ev, vec), DDAMG_EBREAKDOWN, "GMRES-DR: harmonic Ritz problem did not converge");
+        std::vector<int> idx(m);
+        for (int q = 0; q < m; ++q) idx[q] = q;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b2) { return std::abs(ev[a]) < std::abs(ev[b2]); });
+        for (int q = 0; q < kk; ++q)
+          for (int r = 0; r < m; ++r) P[(size_t)r * (kk + 1) + q] = vec[(size_t)r * m + idx[q]];
+      }
+      for (int r = 0; r <= m; ++r) P[(size_t)r * (kk + 1) + kk] = rho[r];
+      // Q = orthonormal factor of P (modified Gram-Schmidt, twice)
+      for (int q = 0; q <= kk; ++q) {
+        for (int pass = 0; pass < 2; ++pass)
+          for (int p2 = 0; p2 < q; ++p2) {
+            cd d = 0;
+            for (int r = 0; r <= m; ++r) d += std::conj(P[(size_t)r * (kk + 1) + p2]) * P[(size_t)r * (kk + 1) + q];
+            for (int r = 0; r <= m; ++r) P[(size_t)r * (kk + 1) + q] -= d * P[(size_t)r * (kk + 1) + p2];
+          }
+        double nq = 0;
+        for (int r = 0; r <= m; ++r) nq += std::norm(P[(size_t)r * (kk + 1) + q]);
+        nq = std::sqrt(nq);
+        DD_CHECK(nq > 0, DDAMG_EBREAKDOWN, "GMRES-DR: dependent deflation vectors");
+        for (int r = 0; r <= m; ++r) P[(size_t)r * (kk + 1) + q] /= nq;
+      }
+      // Hbar_new = Q^H Hbar Q[:m, :kk], c_new = Q^H rho
+      std::vector<cd> HQ((size_t)(m + 1) * kk, cd(0));
+      for (int r = 0; r <= m; ++r)
+        for (int q = 0; q < kk; ++q) {
+          cd acc = 0;
+          for (int l = 0; l < m; ++l) acc += H_(Hb, i, r, l) * P[(size_t)l * (kk + 1) + q];
+          HQ[(size_t)r * kk + q] = acc;
+        }
+      for (int r = 0; r <= m; ++r)
+        for (int q = 0; q < m; ++q) H_(Hb, i, r, q) = 0;
+      for (int r = 0; r <= kk; ++r)
+        for (int q = 0; q < kk; ++q) {
+          cd acc = 0;
+          for (int l = 0; l <= m; ++l) acc += std::conj(P[(size_t)l * (kk + 1) + r]) * HQ[(size_t)l * kk + q];
+          H_(Hb, i, r, q) = acc;
+        }
+      cd* ci = &cv[(size_t)i * (m + 1)];
+      std::vector<cd> cn(m + 1, cd(0));
+      for (int r = 0; r <= kk; ++r) {
+        cd acc = 0;
+        for (int l = 0; l <= m; ++l) acc += std::conj(P[(size_t)l * (kk + 1) + r]) * rho[l];
+        cn[r] = acc;
+      }
+      for (int r = 0; r <= m; ++r) ci[r] = cn[r];
+      // rotated system: triangularise the dense (kk+1) x kk block
+      rots[i].clear();
+      cd* gi = &g[(size_t)i * (m + 1)];
+      for (int r = 0; r <= m; ++r) gi[r] = ci[r];
+      for (int r = 0; r <= m; ++r)
+        for (int q = 0; q < m; ++q) H_(Hr, i, r, q) = H_(Hb, i, r, q);
+      for (int q = 0; q < kk; ++q)
+        for (int r = kk; r > q; --r) {
+          const DrRot rt = dr_make_rot(r - 1, H_(Hr, i, r - 1, q), H_(Hr, i, r, q));
+          for (int q2 = 0; q2 < kk; ++q2) {
+            cd colv[2] = {H_(Hr, i, r - 1, q2), H_(Hr, i, r, q2)};
+            DrRot loc{0, rt.c, rt.s};
+            dr_apply_rot(loc, colv);
+            H_(Hr, i, r - 1, q2) = colv[0];
+            H_(Hr, i, r, q2) = colv[1];
+          }
+          dr_apply_rot(rt, gi);
+          rots[i].push_back(rt);
+        }
+      est[i] = std::abs(gi[kk]);
+      for (int r = 0; r <= m; ++r)
+        for (int q = 0; q <= kk; ++q) {
+          const cd v = P[(size_t)r * (kk + 1) + q];
+          qcoef[(((size_t)q * (m + 1) + r) * ncol + i) * 2] = v.real();
+          qcoef[(((size_t)q * (m + 1) + r) * ncol + i) * 2 + 1] = v.imag();
+        }
+    }
+    // the next basis V_new_q = sum_l V_l Q_lq, formed in Z and copied back
+    std::vector<MV> Vs(m + 1);
+    for (int l = 0; l <= m; ++l) Vs[l] = basis(c, w.V, l, level, prec, cap, nt);
+    for (int q = 0; q <= kk; ++q) {
+      MV zq = basis(c, w.Z, q, level, prec, cap, nt);
+      mv_zero(c, zq);
+      DD_HIP(hipMemcpyAsync(w.d_aux, qcoef.data() + (size_t)q * (m + 1) * ncol * 2,
+                            (size_t)(m + 1) * ncol * 2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      mv_multiaxpy(c, Vs.data(), m + 1, w.d_aux, zq, +1);
+      DD_HIP(hipStreamSynchronize(c->stream));   // w.d_aux is refilled for the next vector
+    }
+    for (int q = 0; q <= kk; ++q) mv_copy(c, basis(c, w.Z, q, level, prec, cap, nt), Vs[q]);
+    j0 = kk;
+  }
+  if (out) {
+    out->iters = iters;
+    out->relres.resize(ncol);
+    for (int i = 0; i < ncol; ++i) out->relres[i] = bn[i] > 0 ? est[i] / bn[i] : 0.0;
+    out->total = total;
+  }
+}
+
+void level_gmres_dr(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& x, double tol, int m, int k,
+                    int maxit, std::vector<int>* iters) {
+  KrylovOut ko;
+  krylov_dr(c, level, d_mu, b, x, true, tol, m, k, maxit, &ko);
+  if (iters) *iters = ko.iters;
+}
+
 // ------------------------------------------------------- outer solve ---
 void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e);
 
-// The top-level FP64 flexible GMRES over a batch of columns (column i: shift
-// mu[i], right-hand side field rhs_of[i] of b, solution field i of x, both in
-// the canonical layout on the device).  A scheduler keeps at most `max_active`
-// columns in the internal layout at once.  At every restart the true FP64
-// residual of each active column is recomputed; columns that meet tol (or
-// have used max_outer iterations) write their solution back and leave, and
-// waiting columns take their place.  When the membership changes, the active
-// columns are gathered into dense tiles (ping-pong buffers), so converged
-// columns cost nothing afterwards (section 3: shrinking the vector bundle).
 // An independent FP64 check of every column as the caller receives it: x
 // and b are read back from the canonical arrays into the outer solve's FP64
 // buffers, wmax columns at a time, r = b - D(mu) x with the FP64 stencil,
@@ -920,6 +1210,15 @@ static void final_check(ddamg_ctx* c, OuterJob& job, LW& w, int wmax) {
   }
 }
 
+// The top-level FP64 flexible GMRES over a batch of columns (column i: shift
+// mu[i], right-hand side field rhs_of[i] of b, solution field i of x, both in
+// the canonical layout on the device).  A scheduler keeps at most `max_active`
+// columns in the internal layout at once.  At every restart the true FP64
+// residual of each active column is recomputed; columns that meet tol (or
+// have used max_outer iterations) write their solution back and leave, and
+// waiting columns take their place.  When the membership changes, the active
+// columns are gathered into dense tiles (ping-pong buffers), so converged
+// columns cost nothing afterwards (section 3: shrinking the vector bundle).
 void outer_solve(ddamg_ctx* c, OuterJob& job) {
   const int T = c->T, ncol = job.ncol;
   const int m = std::min(c->p.outer_restart, KMAX - 1);
@@ -1170,10 +1469,16 @@ void mg_cycle(ddamg_ctx* c, int l, const double* d_mu, const MV& r, const MV& e)
                 nullptr, nullptr, &total);
     c->st.bottom_calls++;
     c->st.bottom_iters += total;
+  } else if (bottom && c->p.bottom_dr_k > 0) {
+    G5Scope gs(c, l + 1, g5);
+    const int mr = c->p.bottom_restart > 0 ? c->p.bottom_restart : std::min(c->p.bottom_maxit, KMAX - 1);
+    krylov_dr(c, l + 1, d_mu, rc, ec, true, c->p.r_b, mr, c->p.bottom_dr_k, c->p.bottom_maxit, &ko);
+    c->st.bottom_calls++;
+    c->st.bottom_iters += ko.total;
   } else if (bottom) {
     G5Scope gs(c, l + 1, g5);
-    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, std::min(c->p.bottom_maxit, KMAX - 1), c->p.bottom_maxit,
-           nullptr, prec, false, &ko);
+    const int mr = c->p.bottom_restart > 0 ? c->p.bottom_restart : std::min(c->p.bottom_maxit, KMAX - 1);
+    krylov(c, l + 1, d_mu, rc, ec, true, c->p.r_b, mr, c->p.bottom_maxit, nullptr, prec, false, &ko);
     c->st.bottom_calls++;
     c->st.bottom_iters += ko.total;
   } else {

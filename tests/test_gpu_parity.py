@@ -511,6 +511,51 @@ def test_block_gmres_iterates_match_oracle(torch_cuda, dd):
     ctx.close()
 
 
+def test_gmres_dr_iterates_match_oracle(torch_cuda, dd):
+    """GMRES with deflated restarting on the GPU (device Arnoldi and basis
+    recombination, host harmonic Ritz pairs and least squares) against the
+    oracle's GMRES-DR(m, k): after a fixed number of steps spanning several
+    restarts the iterates agree to rounding, column by column; with k = 0 it
+    is restarted GMRES(m)."""
+    torch = torch_cuda
+    say("GMRES-DR iterates")
+    dims, agg, N = (8, 4, 4, 8), (2, 2, 2, 2), 8
+    U = S.gauge_field(dims, 0.3, 61)
+    V = S.volume(dims)
+    tv = S.gaussian_spinors(N, V, 81).reshape(N, V, 12)
+    blk = Blocking(dims, agg)
+    coarse = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), build_prolongator(tv, blk), blk)
+    mus = np.array([0.01, 0.01, 0.07, 0.2, 0.003, 0.05, 0.1, 0.3, 0.02, 0.15])     # 10 columns: two tiles
+    b = S.gaussian_coarse(len(mus), blk.nblocks, 2 * N, 83)
+    for m, k, steps, tol in ((10, 4, 27, 1e-14), (12, 0, 30, 1e-14), (8, 6, 22, 1e-14), (6, 3, 60, 1e-8)):
+        p = dd.default_params(dims=dims, kappa=0.15, n_levels=2, sap_block=agg, agg=[agg, agg], n_tv=[N, 8],
+                              setup_rounds=1, bottom_restart=m, bottom_dr_k=k, bottom_maxit=steps)
+        ctx = dd.Context(p, U)
+        ctx.set_test_vectors(0, tv)
+        x, it = ctx.coarse_solve(1, dd.FP64, False, mus, torch.from_numpy(b).cuda(), tol, steps)
+        x = x.cpu().numpy()
+        xr, info = O.gmres_dr(lambda X, act: coarse.apply(X, mus[act]), b, tol, m, k, steps)
+        err = np.max(relerr_cols(x, xr))
+        say(f"  GMRES-DR({m}, {k}), {steps} steps, tol {tol}: max rel. difference {err:.2e}, "
+            f"oracle residual {info['relres'].max():.2e}, iterations {list(it)}")
+        assert err < 1e-9
+        if tol > 1e-12:   # a clear convergence decision: same step counts
+            assert list(it) == [int(v) for v in info["iters"]]
+        ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_three_level_gmres_dr(torch_cuda, dd, precision):
+    """Three-level solve with GMRES-DR on the coarsest level (gamma5 form):
+    every column reaches the true FP64 residual 1e-10 by the oracle."""
+    w = S.workload("tm_8x8x8x8_3level")
+    say("solve", w.name, "GMRES-DR bottom, precision", precision)
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, precision, coarse_gamma5=1, bottom_restart=12,
+                                     bottom_dr_k=4)
+    assert st == dd.OK
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+
+
 @pytest.mark.parametrize("precision,mfma", [("FP64", 0), ("FP32", 0), ("FP32", 1)])
 def test_block_gmres_converges(torch_cuda, dd, precision, mfma):
     """Block and per-column GMRES on the GPU reach the tolerance by the FP64
