@@ -56,6 +56,10 @@ SMALL_ONE = dict(n_levels=1, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, outer_
                  inner_tol=1e-2, inner_fp16=1, max_outer=3000)
 SMALL_TWO = dict(MG2, outer_restart=40, max_outer=400)
 SMALL_THREE = dict(SMALL_TWO, n_levels=3, middle_restart=25, middle_maxit=50)
+# the coarsest level with a short restart, plain and with deflated restarting
+# (GMRES-DR(10, 4): 4 harmonic Ritz vectors kept across restarts)
+SMALL_THREE_R10 = dict(SMALL_THREE, bottom_restart=10)
+SMALL_THREE_DR = dict(SMALL_THREE_R10, bottom_dr_k=4)
 
 # the kernel classes the library can time live (ddamg.h, DDAMG_KNOB_TIME_SAP)
 TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
@@ -461,6 +465,8 @@ def main():
         small = {}
         for name, prec, solver in (("one_level", dd.MIXED, SMALL_ONE), ("two_level", dd.MIXED, SMALL_TWO),
                                    ("three_level", dd.MIXED, SMALL_THREE),
+                                   ("three_level_bottom_gmres10", dd.MIXED, SMALL_THREE_R10),
+                                   ("three_level_bottom_gmres_dr10_4", dd.MIXED, SMALL_THREE_DR),
                                    ("two_level_plain_fp64", dd.PLAIN_FP64, SMALL_TWO)):
             c, r = run_form(dd, torch, ws, Us, bs, ms, prec, solver, 1, 12, ws.n_col, None, "16^3x32 " + name)
             r.pop("x")
@@ -490,7 +496,9 @@ def main():
         small["config"] = {"workload": ws.name, "lattice": "16x16x16x32", "kappa": ws.kappa, "columns": ws.n_col,
                            "one_level": "FP64 FGMRES(4) over FP32 FGMRES(40, FP16 basis) over SAP",
                            "two_level": "FP64 FGMRES(40) over the two-level cycle (4^4 aggregates, N = 24)",
-                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)"}
+                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)",
+                           "three_level_bottom_gmres10": "three_level, coarsest GMRES restarted every 10 steps",
+                           "three_level_bottom_gmres_dr10_4": "three_level, coarsest GMRES-DR(10, 4)"}
 
     cpu = cpu_baseline(raw_cpu, st, tuned["outer_iters_mean"], ncol, V, Vc) if raw_cpu else None
 

@@ -194,6 +194,7 @@ int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
       if (c->p.col_tile == 0) c->p.col_tile = 8;
       c->T = 8;
       c->stream = (hipStream_t)hip_stream;
+      c->pool.stream = c->stream;
       c->nlev = p->n_levels;
       c->m0 = 1.0 / (2.0 * p->kappa) - 4.0;
       c->diag = 4.0 + c->m0;
@@ -213,6 +214,7 @@ int ddamg_setup(const ddamg_params* p, const double* gauge, int gauge_on_device,
       if (p->csw != 0.0) build_clover(c);
       build_hierarchy(c, tv_init);
       DD_HIP(hipStreamSynchronize(c->stream));
+      c->pool.trim();
     } catch (...) {
       c->pool.clear();
       delete c;
@@ -868,6 +870,7 @@ int ddamg_autotune(ddamg_ctx* c, int n_col, int* values) {
     // lattices) sizes its own
     DD_HIP(hipStreamSynchronize(c->stream));
     free_work(c);
+    c->pool.trim();
     if (values)
       for (int k = 0; k < DDAMG_N_KNOBS; ++k) values[k] = *knob_slot(c, k);
     return DDAMG_OK;

@@ -18,21 +18,46 @@ constexpr int MAXK = 64;
 
 // ------------------------------------------------------------- pool ---
 void* DevPool::alloc(size_t bytes) {
+  size_t want = ((bytes ? bytes : 16) + 255) & ~(size_t)255;
+  if (want >= ((size_t)1 << 20)) want = (want + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1);
+  auto it = cache.lower_bound(want);
+  if (it != cache.end() && it->first <= want + want / 4) {
+    void* p = it->second;
+    const size_t sz = it->first;
+    cache.erase(it);
+    cached_bytes -= sz;
+    DD_HIP(hipStreamSynchronize(stream));
+    blocks.push_back({p, sz});
+    return p;
+  }
   void* p = nullptr;
-  DD_HIP(hipMalloc(&p, bytes ? bytes : 16));
-  blocks.push_back(p);
+  hipError_t e = hipMalloc(&p, want);
+  if (e == hipErrorOutOfMemory && !cache.empty()) {
+    (void)hipGetLastError();
+    trim();
+    e = hipMalloc(&p, want);
+  }
+  DD_HIP(e);
+  blocks.push_back({p, want});
   return p;
 }
 void DevPool::release(void* p) {
   for (size_t i = 0; i < blocks.size(); ++i)
-    if (blocks[i] == p) {
-      (void)hipFree(p);
+    if (blocks[i].first == p) {
+      cache.insert({blocks[i].second, p});
+      cached_bytes += blocks[i].second;
       blocks.erase(blocks.begin() + i);
       return;
     }
 }
+void DevPool::trim() {
+  for (auto& kv : cache) (void)hipFree(kv.second);
+  cache.clear();
+  cached_bytes = 0;
+}
 void DevPool::clear() {
-  for (void* p : blocks) (void)hipFree(p);
+  trim();
+  for (auto& b : blocks) (void)hipFree(b.first);
   blocks.clear();
 }
 

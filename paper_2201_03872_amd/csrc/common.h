@@ -23,6 +23,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -113,12 +114,21 @@ struct Coarse {
   int g5out = 0;              // 1: the stencil applies gamma5_c D_c(mu) (Hermitian form + i dmu mu)
 };
 
-// Simple device allocation pool: every buffer is released at context destruction.
+// Device allocation pool.  Released buffers are kept for reuse by a later
+// request of about the same size (the workspaces of one solve serve the next
+// one: a fresh hipMalloc of a multi-GB buffer costs hundreds of ms).  A
+// reused buffer may still be read by work queued before its release, so
+// reuse first waits for `stream`.  When hipMalloc runs out of memory the
+// cached buffers are freed and the request is tried once more.
 struct DevPool {
-  std::vector<void*> blocks;
+  std::vector<std::pair<void*, size_t>> blocks;   // live
+  std::multimap<size_t, void*> cache;             // released, kept
+  size_t cached_bytes = 0;
+  hipStream_t stream = nullptr;
   void* alloc(size_t bytes);
   void release(void* p);
-  void clear();
+  void trim();    // free every cached buffer
+  void clear();   // free everything
 };
 
 struct Stats {
