@@ -45,21 +45,25 @@ SMALL = "tm_16x16x16x32_12rhs_4shift"
 # reduced 4^4 blocks, coarse GMRES on the gamma5-Hermitian form to 0.1.
 MG2 = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds=3, setup_boot=1,
            coarse_gamma5=1, bottom_maxit=100, inner_iters=0)
-# 40^3x80: FP64 FGMRES(4) over the cycle, 8 columns in flight (HBM budget)
-TUNED = dict(MG2, outer_restart=4, max_outer=300, max_active_cols=8)
+# 40^3x80, 8 columns in flight (HBM budget).  Plain form: FP64 FGMRES(4)
+# over the cycle, all in FP64.  Tuned form: FP64 FGMRES(1) over an FP32
+# FGMRES(8) to 1e-2 whose basis is stored in FP16, over the FP32 cycle with
+# BF16 coarse blocks (the nested solve fits in HBM because its basis is FP16)
+PLAIN = dict(MG2, outer_restart=4, max_outer=300, max_active_cols=8)
+TUNED = dict(PLAIN, outer_restart=1, inner_iters=8, inner_tol=1e-2, inner_fp16=1)
 # the three-level hierarchy of the workload definition (4^4 then 2^4
 # aggregates, 24 / 32 test vectors): middle FGMRES to 7e-2, coarsest GMRES to 0.1
-THREE = dict(TUNED, n_levels=3, middle_restart=25, middle_maxit=50)
+THREE = dict(PLAIN, n_levels=3, middle_restart=25, middle_maxit=50)
+# its coarsest level with a short restart, plain and with deflated restarting
+# (GMRES-DR(10, 4): 4 harmonic Ritz vectors kept across restarts)
+THREE_R10 = dict(THREE, bottom_restart=10)
+THREE_DR = dict(THREE_R10, bottom_dr_k=4)
 # 16^3x32 forms: one-level (FP64 FGMRES(4) over an FP32 FGMRES(40) with an FP16
 # basis around SAP), two- and three-level (FP64 FGMRES(40) over the cycle)
 SMALL_ONE = dict(n_levels=1, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, outer_restart=4, inner_iters=40,
                  inner_tol=1e-2, inner_fp16=1, max_outer=3000)
 SMALL_TWO = dict(MG2, outer_restart=40, max_outer=400)
 SMALL_THREE = dict(SMALL_TWO, n_levels=3, middle_restart=25, middle_maxit=50)
-# the coarsest level with a short restart, plain and with deflated restarting
-# (GMRES-DR(10, 4): 4 harmonic Ritz vectors kept across restarts)
-SMALL_THREE_R10 = dict(SMALL_THREE, bottom_restart=10)
-SMALL_THREE_DR = dict(SMALL_THREE_R10, bottom_dr_k=4)
 
 # the kernel classes the library can time live (ddamg.h, DDAMG_KNOB_TIME_SAP)
 TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
@@ -129,7 +133,8 @@ def summary(r, precision_note):
             "outer_iters_mean": r["outer_iters_mean"], "avg_bottom_iters": s["avg_bottom_iters"],
             "n_bottom_solves": s["n_bottom_solves"], "avg_middle_iters": s["avg_middle_iters"],
             "n_middle_solves": s["n_middle_solves"], "inner_iters": s["n_inner_iters"],
-            "setup_s": r["setup_s"], "hierarchy_s": r["hierarchy_s"], "precision": precision_note}
+            "setup_s": r["setup_s"], "hierarchy_s": r["hierarchy_s"], "precision": precision_note,
+            "device_GB_peak": s["device_bytes_peak"] / 1e9}
 
 
 # --------------------------------------------------------------- CPU baseline ---
@@ -259,7 +264,7 @@ def cpu_baseline(raw, tuned_stats, outer_per_col, ncol, V_fine, Vc):
                 sample=(f"FP64 numpy oracle, one column per process on {cores} processes at once (one thread "
                         f"each): per-operation timings of the two-level method on 8x8x8x16 sub-lattices drawn "
                         f"with the 40^3x80 recipe ({raw['c5_wall']:.0f}s wall), scaled per site to 40x40x40x80 "
-                        f"and multiplied by the GPU tuned solve's counts per column ({n_cycles:.0f} cycles of "
+                        f"and multiplied by the GPU solve's counts per column ({n_cycles:.0f} cycles of "
                         f"{bottom:.1f} coarse GMRES steps, {outer:.1f} outer steps): {per_col:.0f}s per column; "
                         f"extrapolated, not a full solve"),
                 c1_full_solves={"columns": 6, "wall_s": raw["c1_wall"], "solves_per_s": 6 / raw["c1_wall"],
@@ -444,17 +449,23 @@ def main():
 
     plain = None
     if not args.no_plain:
-        pctx, plain = run_form(dd, torch, w, U, b, mus, dd.PLAIN_FP64, TUNED, args.steps, wu, 8, None, "plain")
+        pctx, plain = run_form(dd, torch, w, U, b, mus, dd.PLAIN_FP64, PLAIN, args.steps, wu, 8, None, "plain")
         plain.pop("x")
         pctx.close()
         torch.cuda.empty_cache()
     three = None
     if not args.no_three:
-        tctx, three = run_form(dd, torch, w, U, b[:1].contiguous(), mus, dd.MIXED, THREE, 1, 1, 8, None,
-                               "three-level")
-        three.pop("x")
-        tctx.close()
-        torch.cuda.empty_cache()
+        # one wave (1 rhs x 8 shifts): the three-level hierarchy, and its
+        # coarsest GMRES restarted every 10 steps without and with deflation
+        three = {}
+        for name, form in (("bottom_gmres63", THREE), ("bottom_gmres10", THREE_R10),
+                           ("bottom_gmres_dr10_4", THREE_DR)):
+            tctx, r = run_form(dd, torch, w, U, b[:1].contiguous(), mus, dd.MIXED, form, 1, 1, 8, None,
+                               "three-level " + name)
+            r.pop("x")
+            tctx.close()
+            torch.cuda.empty_cache()
+            three[name] = summary(r, "f64 outer / f32 cycle")
 
     small = None
     if not args.no_small:
@@ -465,8 +476,6 @@ def main():
         small = {}
         for name, prec, solver in (("one_level", dd.MIXED, SMALL_ONE), ("two_level", dd.MIXED, SMALL_TWO),
                                    ("three_level", dd.MIXED, SMALL_THREE),
-                                   ("three_level_bottom_gmres10", dd.MIXED, SMALL_THREE_R10),
-                                   ("three_level_bottom_gmres_dr10_4", dd.MIXED, SMALL_THREE_DR),
                                    ("two_level_plain_fp64", dd.PLAIN_FP64, SMALL_TWO)):
             c, r = run_form(dd, torch, ws, Us, bs, ms, prec, solver, 1, 12, ws.n_col, None, "16^3x32 " + name)
             r.pop("x")
@@ -496,11 +505,16 @@ def main():
         small["config"] = {"workload": ws.name, "lattice": "16x16x16x32", "kappa": ws.kappa, "columns": ws.n_col,
                            "one_level": "FP64 FGMRES(4) over FP32 FGMRES(40, FP16 basis) over SAP",
                            "two_level": "FP64 FGMRES(40) over the two-level cycle (4^4 aggregates, N = 24)",
-                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)",
-                           "three_level_bottom_gmres10": "three_level, coarsest GMRES restarted every 10 steps",
-                           "three_level_bottom_gmres_dr10_4": "three_level, coarsest GMRES-DR(10, 4)"}
+                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)"}
 
-    cpu = cpu_baseline(raw_cpu, st, tuned["outer_iters_mean"], ncol, V, Vc) if raw_cpu else None
+    # the oracle runs the plain method (FP64 FGMRES over the cycle): its
+    # counts per column are the plain GPU form's (the tuned form's if the
+    # plain one was skipped, its inner steps counted as outer ones)
+    if plain:
+        cnt, outer_col = plain["stats"], plain["outer_iters_mean"]
+    else:
+        cnt, outer_col = st, tuned["outer_iters_mean"] + st["n_inner_iters"] / (ncol // 8)
+    cpu = cpu_baseline(raw_cpu, cnt, outer_col, ncol, V, Vc) if raw_cpu else None
 
     out = {
         "metric": "rhs*shift solves/s at true FP64 relative residual 1e-10 (tuned form); dslash HBM GB/s",
@@ -517,15 +531,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": "40x40x40x80", "kappa": w.kappa, "eps": w.eps, "n_rhs": w.n_rhs,
                    "shifts": list(w.mus), "columns": ncol, "tol": 1e-10, "columns_in_flight": 8,
-                   "solver": "FP64 FGMRES(4) over the two-level aggregation MG cycle in FP32 (4^4 aggregates, "
-                             "N = 24, one bootstrap round; red-black SAP 1 cycle of 4 MR steps on the odd-even "
-                             "reduced 4^4 blocks; coarse GMRES on gamma5_c D_c to 0.1, BF16 MFMA stencil)"},
+                   "solver": "FP64 FGMRES(1) over FP32 FGMRES(8, FP16 basis) to 1e-2 over the two-level "
+                             "aggregation MG cycle in FP32 (4^4 aggregates, N = 24, one bootstrap round; red-black "
+                             "SAP 1 cycle of 4 MR steps on the odd-even reduced 4^4 blocks; coarse GMRES on "
+                             "gamma5_c D_c to 0.1, BF16 MFMA stencil)",
+                   "plain_solver": "FP64 FGMRES(4) over the same two-level cycle, every step in FP64"},
         "all_converged": tuned["allconv"],
         "worst_true_rel_res": tuned["worst"],
         "tuned": summary(tuned, "f64 outer / f32 cycle / bf16 coarse blocks"),
         "plain_fp64": summary(plain, "f64") if plain else None,
         "tuned_over_plain": (value / plain["solves_per_s"]) if plain and plain["solves_per_s"] else None,
-        "three_level_one_wave": summary(three, "f64 outer / f32 cycle") if three else None,
+        "three_level_one_wave": three,
         "autotuned": tuned["tuned"],
         "dslash_40x40x40x80_8col": {"fp32_us": t32 * 1e6, "fp32_GBs": bytes32 / t32 / 1e9,
                                     "fp32_GFLOPs": 1320 * V * 8 / t32 / 1e9,

@@ -164,6 +164,9 @@ typedef struct ddamg_stats {
                              /* launches of the last solve (else 0)                               */
   long long n_sap_kernels;   /* ... the number of those launches                                  */
   long long n_sap_kernel_tiles; /* ... and the sum of their column tiles (8 columns each)         */
+  long long device_bytes;    /* device memory the context holds now (in use, or released and   */
+                             /* kept for reuse by later requests of about the same size)         */
+  long long device_bytes_peak; /* the largest device_bytes since the context was created        */
 } ddamg_stats;
 
 /* Fill p with the defaults of the two-level 4^4 case; callers overwrite fields. */

@@ -96,6 +96,7 @@ class Stats(ctypes.Structure):
         ("col_removals", ctypes.c_int), ("n_inner_iters", ctypes.c_longlong),
         ("n_fp16_restores", ctypes.c_longlong), ("sap_kernel_ms", ctypes.c_double),
         ("n_sap_kernels", ctypes.c_longlong), ("n_sap_kernel_tiles", ctypes.c_longlong),
+        ("device_bytes", ctypes.c_longlong), ("device_bytes_peak", ctypes.c_longlong),
     ]
 
 

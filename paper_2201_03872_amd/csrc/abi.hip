@@ -682,6 +682,8 @@ int ddamg_get_stats(ddamg_ctx* c, ddamg_stats* s) {
     s->sap_kernel_ms = c->st.sap_kernel_ms;
     s->n_sap_kernels = c->st.sap_kernel_launches;
     s->n_sap_kernel_tiles = c->st.sap_kernel_tiles;
+    s->device_bytes = (long long)c->pool.held;
+    s->device_bytes_peak = (long long)c->pool.peak;
     return DDAMG_OK;
   });
 }

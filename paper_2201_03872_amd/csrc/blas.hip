@@ -39,6 +39,8 @@ void* DevPool::alloc(size_t bytes) {
   }
   DD_HIP(e);
   blocks.push_back({p, want});
+  held += want;
+  if (held > peak) peak = held;
   return p;
 }
 void DevPool::release(void* p) {
@@ -53,12 +55,14 @@ void DevPool::release(void* p) {
 void DevPool::trim() {
   for (auto& kv : cache) (void)hipFree(kv.second);
   cache.clear();
+  held -= cached_bytes;
   cached_bytes = 0;
 }
 void DevPool::clear() {
   trim();
   for (auto& b : blocks) (void)hipFree(b.first);
   blocks.clear();
+  held = 0;
 }
 
 MV mv_alloc(ddamg_ctx* c, int level, int prec, int ncol_min) {

@@ -124,6 +124,7 @@ struct DevPool {
   std::vector<std::pair<void*, size_t>> blocks;   // live
   std::multimap<size_t, void*> cache;             // released, kept
   size_t cached_bytes = 0;
+  size_t held = 0, peak = 0;                      // bytes in use or cached, and their maximum
   hipStream_t stream = nullptr;
   void* alloc(size_t bytes);
   void release(void* p);
