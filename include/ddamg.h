@@ -348,7 +348,20 @@ int ddamg_time_op(ddamg_ctx* h, int op, int level, int precision, int n_col, int
                                             3 the restriction 0 -> 1, 4 the prolongation 1 -> 0,
                                             5 the fine stencil */
 #define DDAMG_KNOB_TIME_KERNEL       DDAMG_KNOB_TIME_SAP
-#define DDAMG_N_KNOBS 9
+#define DDAMG_KNOB_GRAM_ONE_REDUCTION 9  /* Arnoldi steps of (F)GMRES with FP32 or FP64 bases
+                                            (communication-avoiding Gram-Schmidt, the outlook of
+                                            sections 4 and 5: fewer global reductions per step):
+                                            1 (default) one reduction per step - the dots with
+                                            the basis and the new vector's own squared norm in
+                                            one pass; the norm of the orthogonalised vector is
+                                            predicted from them (Pythagoras), so the update pass
+                                            stores it already normalised and measures its norm
+                                            on the way, which gives h_{j+1,j} and decides whether
+                                            a correcting rescale is needed (it is when the
+                                            prediction cancelled); 0: dots, update with norm,
+                                            then a normalisation pass; 2: as 1 with the
+                                            correcting rescale at every step (test form) */
+#define DDAMG_N_KNOBS 10
 int ddamg_set_tuning(ddamg_ctx* h, int knob, int value);
 int ddamg_get_tuning(ddamg_ctx* h, int knob, int* value);
 

@@ -331,14 +331,18 @@ class Context:
         return x, [_info(i) for i in info], st
 
     def solve_batch(self, systems, x0=None):
-        """systems: list of (mus, b) with b a [n_rhs][V][4][3] complex128 CUDA
-        tensor; all systems are solved in one simultaneous batch.  Returns
-        (list of x [n_rhs*n_shift][V][4][3] per system, list of info lists, status)."""
+        """systems: list of (mus, b) with b a [n_rhs][V][4][3] complex128
+        tensor (CUDA, or host memory: then the right-hand sides are gathered on
+        the host and copied to the device once); all systems are solved in one
+        simultaneous batch.  Returns (list of x [n_rhs*n_shift][V][4][3] per
+        system, list of info lists, status)."""
         import torch
         n_rhs = [int(b.shape[0]) for _, b in systems]
         n_shift = [len(np.atleast_1d(m)) for m, _ in systems]
         mu = np.ascontiguousarray(np.concatenate([np.atleast_1d(np.asarray(m, dtype=np.float64)) for m, _ in systems]))
-        b = torch.cat([bb for _, bb in systems]).contiguous()
+        b = torch.cat([torch.as_tensor(bb) for _, bb in systems]).contiguous()
+        if not b.is_cuda:
+            b = b.to(self.device)
         ncol = sum(r * k for r, k in zip(n_rhs, n_shift))
         x = x0.clone() if x0 is not None else torch.zeros((ncol,) + tuple(b.shape[1:]), dtype=torch.complex128,
                                                           device=self.device)
@@ -372,7 +376,8 @@ class Context:
 
     KNOBS = {"dslash_sites_fp64": 0, "dslash_sites_fp32": 1, "fp32_links": 2, "coarse_mfma": 3,
              "sap_variant": 4,
-             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7, "time_sap": 8, "time_kernel": 8}
+             "dslash_order": 5, "walk_segments": 6, "fp16_rescale": 7, "time_sap": 8, "time_kernel": 8,
+             "gram_one_reduction": 9}
 
     # ---- learned smoother ----
     def set_smoother_weights(self, w1, w2):

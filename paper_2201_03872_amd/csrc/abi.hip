@@ -762,6 +762,7 @@ static int* knob_slot(ddamg_ctx* c, int knob) {
     case DDAMG_KNOB_WALK_SEGMENTS: return &c->walk_seg;
     case DDAMG_KNOB_FP16_RESCALE: return &c->fp16_rescale;
     case DDAMG_KNOB_TIME_SAP: return &c->time_sap;
+    case DDAMG_KNOB_GRAM_ONE_REDUCTION: return &c->gram_lowsync;
     default: throw Error{DDAMG_EINVAL, "unknown knob"};
   }
 }
@@ -777,6 +778,7 @@ static bool knob_valid(int knob, int value) {
     case DDAMG_KNOB_WALK_SEGMENTS: return value == 1 || value == 2 || value == 4 || value == 8;
     case DDAMG_KNOB_FP16_RESCALE: return value >= 1 && value <= 1024;
     case DDAMG_KNOB_TIME_SAP: return value >= 0 && value <= 5;
+    case DDAMG_KNOB_GRAM_ONE_REDUCTION: return value >= 0 && value <= 2;
     default: return false;
   }
 }

@@ -37,7 +37,9 @@ void* DevPool::alloc(size_t bytes) {
     trim();
     e = hipMalloc(&p, want);
   }
-  DD_HIP(e);
+  if (e != hipSuccess)
+    throw Error{e == hipErrorOutOfMemory ? DDAMG_ENOMEM : DDAMG_EDEVICE,
+                "device allocation of " + std::to_string(want) + " bytes: " + hipGetErrorString(e)};
   blocks.push_back({p, want});
   held += want;
   if (held > peak) peak = held;
@@ -781,10 +783,12 @@ __global__ void k_multiaxpy_chunk(PtrPack Vs, int k, const double* __restrict__ 
 // The coefficients of the tile's T columns are staged in LDS in the
 // accumulation type ACC (FP32 for an FP16 basis, whose 2^-11 relative error
 // dominates; FP64 otherwise).
+// With osc (per column, may be null) the stored result is (w + ...) * osc.
 template <typename RV, typename RWt, int RW, typename ACC>
 __global__ void __launch_bounds__(256) k_multiaxpy_norm(PtrPack Vs, int k, const double* __restrict__ coef,
                                                         RWt* __restrict__ w, int T, size_t tile_units, int ncol,
-                                                        double scale, double* __restrict__ part) {
+                                                        double scale, double* __restrict__ part,
+                                                        const double* __restrict__ osc) {
   __shared__ ACC cf[MAXK][TTB][2];
   __shared__ double red[4][TTB];
   const int tile = blockIdx.y;
@@ -797,6 +801,7 @@ __global__ void __launch_bounds__(256) k_multiaxpy_norm(PtrPack Vs, int k, const
   __syncthreads();
   const int t = threadIdx.x % T;
   const size_t base = (size_t)tile * tile_units;
+  const ACC sc = osc ? (ACC)osc[tile * T + t] : (ACC)1;
   double n2 = 0;
   for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < tile_units; u += (size_t)gridDim.x * blockDim.x) {
     ACC acc[RW];
@@ -818,7 +823,7 @@ __global__ void __launch_bounds__(256) k_multiaxpy_norm(PtrPack Vs, int k, const
     RWt* wp = w + (base + u) * RW;
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
-      const RWt o = (RWt)((ACC)wp[r] + acc[r]);
+      const RWt o = osc ? (RWt)(((ACC)wp[r] + acc[r]) * sc) : (RWt)((ACC)wp[r] + acc[r]);
       wp[r] = o;
       n2 += (double)o * (double)o;
     }
@@ -963,6 +968,41 @@ void mv_multiaxpy(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const
   DD_HIP(hipGetLastError());
 }
 
+static int multiaxpy_blocks(const MV& w) {
+  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
+  return (int)std::max<size_t>(1, std::min<size_t>((tile_units + 255) / 256, 3072 / w.ntiles));
+}
+
+size_t multiaxpy_partials(const MV& w) { return (size_t)multiaxpy_blocks(w) * w.ncol(); }
+
+static void multiaxpy_norm_launch(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
+                                  const double* d_osc, double* d_n2, double* part) {
+  PtrPack pk;
+  for (int j = 0; j < k; ++j) {
+    DD_CHECK(Vs[j].nsites == w.nsites && Vs[j].dof == w.dof && Vs[j].ntiles == w.ntiles && Vs[j].prec == Vs[0].prec,
+             DDAMG_EINVAL, "mv_multiaxpy_norm2: shape");
+    pk.p[j] = Vs[j].p;
+  }
+  const bool half = Vs[0].prec == P16 && w.prec == P32;
+  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
+  const int nb = multiaxpy_blocks(w);
+  const int ncol = w.ncol();
+  if (!part) part = scratch(c, (size_t)nb * ncol * sizeof(double));
+  const dim3 grid(nb, w.ntiles);
+  if (half)
+    hipLaunchKernelGGL((k_multiaxpy_norm<_Float16, float, 4, float>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<float>(), w.T, tile_units, ncol, (double)sign / Vs[0].hscale, part, d_osc);
+  else if (w.prec == P64)
+    hipLaunchKernelGGL((k_multiaxpy_norm<double, double, 2, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<double>(), w.T, tile_units, ncol, (double)sign, part, d_osc);
+  else
+    hipLaunchKernelGGL((k_multiaxpy_norm<float, float, 4, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
+                       w.as<float>(), w.T, tile_units, ncol, (double)sign, part, d_osc);
+  DD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3(ncol), dim3(64), 0, c->stream, part, d_n2, nb, ncol);
+  DD_HIP(hipGetLastError());
+}
+
 // w += sign * sum_j coef V_j and d_n2[col] = ||w_col||^2 of the result in one
 // pass over w (same-precision or FP16 bases; other pairs take the two-pass form)
 void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
@@ -974,29 +1014,15 @@ void mv_multiaxpy_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef,
     mv_norm2(c, w, d_n2);
     return;
   }
-  PtrPack pk;
-  for (int j = 0; j < k; ++j) {
-    DD_CHECK(Vs[j].nsites == w.nsites && Vs[j].dof == w.dof && Vs[j].ntiles == w.ntiles && Vs[j].prec == Vs[0].prec,
-             DDAMG_EINVAL, "mv_multiaxpy_norm2: shape");
-    pk.p[j] = Vs[j].p;
-  }
-  const size_t tile_units = (size_t)w.nchunk * w.nsites * w.T;
-  const int nb = (int)std::max<size_t>(1, std::min<size_t>((tile_units + 255) / 256, 3072 / w.ntiles));
-  const int ncol = w.ncol();
-  double* part = scratch(c, (size_t)nb * ncol * sizeof(double));
-  const dim3 grid(nb, w.ntiles);
-  if (half)
-    hipLaunchKernelGGL((k_multiaxpy_norm<_Float16, float, 4, float>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
-                       w.as<float>(), w.T, tile_units, ncol, (double)sign / Vs[0].hscale, part);
-  else if (w.prec == P64)
-    hipLaunchKernelGGL((k_multiaxpy_norm<double, double, 2, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
-                       w.as<double>(), w.T, tile_units, ncol, (double)sign, part);
-  else
-    hipLaunchKernelGGL((k_multiaxpy_norm<float, float, 4, double>), grid, dim3(256), 0, c->stream, pk, k, d_coef,
-                       w.as<float>(), w.T, tile_units, ncol, (double)sign, part);
-  DD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_rows, dim3(ncol), dim3(64), 0, c->stream, part, d_n2, nb, ncol);
-  DD_HIP(hipGetLastError());
+  multiaxpy_norm_launch(c, Vs, k, d_coef, w, sign, nullptr, d_n2, nullptr);
+}
+
+void mv_multiaxpy_scale_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
+                              const double* d_osc, double* d_n2, double* part) {
+  DD_CHECK(k >= 1 && k <= MAXK, DDAMG_EINVAL, "mv_multiaxpy_scale_norm2: k");
+  DD_CHECK(Vs[0].prec == w.prec && (w.prec == P32 || w.prec == P64) && w.T == TTB, DDAMG_EINVAL,
+           "mv_multiaxpy_scale_norm2: FP32 or FP64 basis of the vector's precision");
+  multiaxpy_norm_launch(c, Vs, k, d_coef, w, sign, d_osc, d_n2, part);
 }
 
 // w' = w - sum_j (coef_j / c_j^2) V_j for an FP16 basis stored unnormalised

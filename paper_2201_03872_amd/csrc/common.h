@@ -187,6 +187,7 @@ struct ddamg_ctx {
   int walk_seg = 2;             // t-walk stencil: segments of the t direction (one workgroup each)
   int fp16_rescale = 4;         // FP16 Arnoldi basis: bound on the entry scales of the stored vectors
   int time_sap = 0;             // kernel class timed with HIP events at every launch of a solve (0 off)
+  int gram_lowsync = 1;         // Arnoldi steps with one reduction (DDAMG_KNOB_GRAM_ONE_REDUCTION)
   std::vector<hipEvent_t> sap_ev;   // event pool, (start, stop) pairs, reused by every solve
   std::vector<int> sap_ev_tiles;    // column tiles of each timed launch
   size_t sap_ev_used = 0;
@@ -226,6 +227,12 @@ void mv_multiaxpy_norm2_into_f16(ddamg_ctx* c, const MV* Vs, int k, const double
 // variants on caller-owned buffers (no context scratch: safe to capture in a graph)
 size_t multidot_partials(const MV& w, int k);
 void mv_multidot_buf(ddamg_ctx* c, const MV* Vs, int k, const MV& w, double* d_out, double* part);
+// w <- (w + sign * sum_j coef_j V_j) * osc[col] and d_n2[col] = |result|^2 in
+// one pass (same-precision FP32 or FP64 bases); part: partial sums buffer of
+// multiaxpy_partials(w) doubles, or null for the context scratch
+void mv_multiaxpy_scale_norm2(ddamg_ctx* c, const MV* Vs, int k, const double* d_coef, const MV& w, int sign,
+                              const double* d_osc, double* d_n2, double* part);
+size_t multiaxpy_partials(const MV& w);
 void mv_norm2_buf(ddamg_ctx* c, const MV& a, double* d_out, double* cbuf, double* part);
 void mv_dot(ddamg_ctx* c, const MV& a, const MV& b, double* d_out);  // per column complex
 // masked scaling: columns with mask==0 are zeroed

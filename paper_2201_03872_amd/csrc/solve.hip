@@ -66,6 +66,67 @@ void mv_normalize(ddamg_ctx* c, const MV& x, const double* d_n2) {
   DD_HIP(hipGetLastError());
 }
 
+// One-reduction Arnoldi step.  dots: [j+2][ncol] complex, <V_q, w> for q <= j
+// and <w, w> last.  osc[col] = 1 / ||w - V h|| predicted as
+// sqrt(<w, w> - sum_q |h_q|^2) (Pythagoras: the orthogonalised vector and the
+// projection are orthogonal); when that difference is not safely positive
+// (cancellation) the scale falls back to 1 / ||w||, and the norm measured in
+// the update pass corrects it.  A zero w gets osc = 0.
+__global__ void k_lowsync_scale(int j, int ncol, const double* __restrict__ dots, double* __restrict__ osc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncol) return;
+  const double om = dots[((size_t)(j + 1) * ncol + i) * 2];
+  double s = om;
+  for (int q = 0; q <= j; ++q) {
+    const double re = dots[((size_t)q * ncol + i) * 2], im = dots[((size_t)q * ncol + i) * 2 + 1];
+    s -= re * re + im * im;
+  }
+  osc[i] = om > 0 ? 1.0 / sqrt(s > 1e-6 * om ? s : om) : 0.0;
+}
+
+// The correcting rescale of the one-reduction step: columns whose stored
+// vector's squared norm n2 is off 1 by more than tau are divided by sqrt(n2);
+// the others are left untouched (and not read).
+template <typename C>
+__global__ void k_renorm(C* __restrict__ x, const double* __restrict__ n2, size_t nunits, int T, size_t tile_units,
+                         double tau) {
+  for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < nunits; u += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = (u / tile_units) * T + u % T;
+    const double v = n2[col];
+    if (!(v > 0) || fabs(v - 1.0) <= tau) continue;
+    C a = x[u];
+    if constexpr (sizeof(a.x) == 8) {
+      const double sc = 1.0 / sqrt(v);
+      a.x *= sc; a.y *= sc;
+    } else {
+      const float sc = (float)(1.0 / sqrt(v));
+      a.x *= sc; a.y *= sc; a.z *= sc; a.w *= sc;
+    }
+    x[u] = a;
+  }
+}
+
+// Tolerance on |n2 - 1| below which the predicted normalisation stands: far
+// above the prediction's rounding error (FP64 dots) and the stored vector's
+// own rounding, so that only a prediction that cancelled is corrected.
+static double renorm_tau(const ddamg_ctx* c, int prec) {
+  if (c->gram_lowsync == 2) return -1.0;
+  return prec == P64 ? 1e-12 : 1e-6;
+}
+
+static void mv_renorm(ddamg_ctx* c, const MV& x, const double* d_n2, double tau) {
+  const size_t tile_units = (size_t)x.nchunk * x.nsites * x.T, nunits = tile_units * x.ntiles;
+  size_t g = (nunits + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (x.prec == P64)
+    hipLaunchKernelGGL(k_renorm<double2>, dim3((unsigned)g), dim3(256), 0, c->stream, (double2*)x.p, d_n2, nunits,
+                       x.T, tile_units, tau);
+  else
+    hipLaunchKernelGGL(k_renorm<float4>, dim3((unsigned)g), dim3(256), 0, c->stream, (float4*)x.p, d_n2, nunits,
+                       x.T, tile_units, tau);
+  DD_HIP(hipGetLastError());
+}
+
 // Doublets: the two columns of a pair form one vector, so their dots and
 // squared norms are summed and the sum given to both.  h: [nq][ncol] complex.
 __global__ void k_pair_sum_c(double* __restrict__ h, int nq, int ncol) {
@@ -156,6 +217,7 @@ struct LW {
   double* d_h = nullptr;         // [KMAX][ncol] complex dots + [ncol] norm
   double* d_aux = nullptr;       // [ncol] complex scratch for MR / coefficients
   double* d_vsc = nullptr;       // FP16 basis: [KMAX+1][ncol] 1/c_j^2 of the stored vectors + [ncol] store scale
+  double* d_osc = nullptr;       // [ncol] output scales of the one-reduction Arnoldi step
   int* d_map = nullptr;          // [3][ncol] column maps of the outer solve's scheduler
   double* d_muc = nullptr;       // [ncol] shifts of the active columns
   double* d_epsc = nullptr;      // [ncol] doublet coupling epsbar of the active columns
@@ -169,9 +231,10 @@ struct LW {
 // is reallocated (which destroys the graphs).
 struct GraphState {
   int nt = -1, m = 0, ncol = 0, g5 = 0;
-  int knobs[6] = {0, 0, 0, 0, 0, 0};
+  int knobs[7] = {0, 0, 0, 0, 0, 0, 0};
   double *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr, *d_tol = nullptr, *d_est = nullptr;
   double *d_n2 = nullptr, *d_cbuf = nullptr, *d_part = nullptr, *d_mu = nullptr, *d_coef = nullptr;
+  double *d_osc = nullptr, *d_apart = nullptr;   // one-reduction step: output scales, update partials
   int *d_kc = nullptr, *d_done = nullptr;
   std::vector<hipGraph_t> graph;
   std::vector<hipGraphExec_t> exec;
@@ -184,7 +247,7 @@ static void destroy_graphs(ddamg_ctx* c, GraphState* g) {
   for (auto q : g->graph)
     if (q) hipGraphDestroy(q);
   double* dbl[] = {g->d_H, g->d_cs, g->d_sn, g->d_g, g->d_tol, g->d_est, g->d_n2, g->d_cbuf, g->d_part, g->d_mu,
-                   g->d_coef};
+                   g->d_coef, g->d_osc, g->d_apart};
   for (double* p : dbl)
     if (p) c->pool.release(p);
   if (g->d_kc) c->pool.release(g->d_kc);
@@ -224,6 +287,7 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     if (w.d_h) c->pool.release(w.d_h);
     if (w.d_aux) c->pool.release(w.d_aux);
     if (w.d_vsc) c->pool.release(w.d_vsc);
+    if (w.d_osc) c->pool.release(w.d_osc);
     if (w.d_map) c->pool.release(w.d_map);
     if (w.d_muc) c->pool.release(w.d_muc);
     if (w.d_epsc) c->pool.release(w.d_epsc);
@@ -238,6 +302,7 @@ static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
     w.d_h = (double*)c->pool.alloc(((size_t)KMAX * ncol * 2 + ncol) * sizeof(double));
     w.d_aux = (double*)c->pool.alloc((size_t)KMAX * ncol * 2 * sizeof(double));
     w.d_vsc = (double*)c->pool.alloc((size_t)(KMAX + 2) * ncol * sizeof(double));
+    w.d_osc = (double*)c->pool.alloc((size_t)ncol * sizeof(double));
   }
   return w;
 }
@@ -271,11 +336,12 @@ struct Cycle {
   // FP16 basis stored unnormalised: entry scale c_j of each stored vector,
   // 1/c_j^2 and the store scale of the next vector (uploaded each step)
   std::vector<double> cj, vsc, nstore, osc_exact;
+  std::vector<double> osc;      // one-reduction step: output scales of the last step (host copy)
   bool pairs = false;           // doublets: columns 2i, 2i+1 form one Krylov vector
   Cycle(int ncol, int m_) : m(m_), H((size_t)ncol * (m_ + 1) * m_), g((size_t)ncol * (m_ + 1)), sn((size_t)ncol * m_),
                             cs((size_t)ncol * m_), hbuf((size_t)KMAX * ncol * 2 + ncol), kc(ncol),
                             cj((size_t)(m_ + 1) * ncol, 1.0), vsc((size_t)(KMAX + 2) * ncol, 1.0), nstore(ncol, 1.0),
-                            osc_exact(ncol, 1.0) {}
+                            osc_exact(ncol, 1.0), osc(ncol, 1.0) {}
 };
 
 // One (F)GMRES cycle on the first nt tiles of the level's workspace: V[0]
@@ -339,8 +405,23 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     } else {
       operator_apply(c, level, z, vn, d_mu);
     }
-    std::vector<MV> Vs(j + 1);
+    const bool one_red = !half && c->gram_lowsync != 0 && (vprec == P32 || vprec == P64);
+    std::vector<MV> Vs(j + 2);
     for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, vprec, cap, nt);
+    if (one_red) {
+      // one reduction per step: the dots with the basis and |w|^2 together,
+      // then w - V h stored already scaled by the predicted 1 / h_{j+1,j},
+      // its norm measured in the same pass (DDAMG_KNOB_GRAM_ONE_REDUCTION)
+      Vs[j + 1] = vn;
+      mv_multidot(c, Vs.data(), j + 2, vn, w.d_h);
+      if (cy.pairs) pair_sum_c(c, w.d_h, j + 2, ncol);
+      hipLaunchKernelGGL(k_lowsync_scale, dim3((ncol + 63) / 64), dim3(64), 0, c->stream, j, ncol, w.d_h, w.d_osc);
+      DD_HIP(hipGetLastError());
+      mv_multiaxpy_scale_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, w.d_osc, d_n2, nullptr);
+      if (cy.pairs) pair_sum_r(c, d_n2, ncol);
+      mv_renorm(c, vn, d_n2, renorm_tau(c, vprec));
+      copy_to_host(c, w.d_osc, cy.osc.data(), ncol * sizeof(double));
+    } else {
     mv_multidot(c, Vs.data(), j + 1, vn, w.d_h);
     if (cy.pairs) pair_sum_c(c, w.d_h, j + 1, ncol);
     if (half)   // w' straight into the next FP16 basis vector, unnormalised
@@ -349,11 +430,12 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
     else
       mv_multiaxpy_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, d_n2);
     if (cy.pairs) pair_sum_r(c, d_n2, ncol);
+    }
     // one copy of the dots and the norm
     const size_t nh = (size_t)(j + 1) * ncol * 2;
     copy_to_host(c, w.d_h, cy.hbuf.data(), nh * sizeof(double));
     copy_to_host(c, d_n2, cy.hbuf.data() + (size_t)KMAX * ncol * 2, ncol * sizeof(double));
-    if (!half) mv_normalize(c, vn, d_n2);
+    if (!half && !one_red) mv_normalize(c, vn, d_n2);
     ++total;
     jj = j + 1;
     bool alld = true;
@@ -401,7 +483,8 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
         Hc[(size_t)q * m + j] =
             cd(cy.hbuf[((size_t)q * ncol + i) * 2], cy.hbuf[((size_t)q * ncol + i) * 2 + 1]) / cq;
       }
-      const double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+      double hn = host_norm_guard(cy.hbuf[(size_t)KMAX * ncol * 2 + i]);
+      if (one_red) hn = cy.osc[i] > 0 ? hn / cy.osc[i] : 0.0;   // |w - V h| = sqrt(n2) / osc
       Hc[(size_t)(j + 1) * m + j] = hn;
       if (done[i] && cy.kc[i] >= 0) continue;
       // apply the previous rotations to column j
@@ -530,7 +613,8 @@ __global__ void k_g_init(const double* __restrict__ n2, const double* __restrict
 }
 
 __global__ void k_g_step(int j, int m, int ncol, const double* __restrict__ dots, const double* __restrict__ n2,
-                         double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                         const double* __restrict__ osc, double* __restrict__ H, double* __restrict__ cs,
+                         double* __restrict__ sn,
                          double* __restrict__ g, int* __restrict__ kc, int* __restrict__ done,
                          const double* __restrict__ tol, double* __restrict__ est) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -540,7 +624,10 @@ __global__ void k_g_step(int j, int m, int ncol, const double* __restrict__ dots
     Hc[((size_t)q * m + j) * 2] = dots[((size_t)q * ncol + i) * 2];
     Hc[((size_t)q * m + j) * 2 + 1] = dots[((size_t)q * ncol + i) * 2 + 1];
   }
-  const double hn = n2[i] > 0 ? sqrt(n2[i]) : 0.0;
+  // with the one-reduction step the stored vector is (w - V h) * osc, whose
+  // measured norm sqrt(n2) gives |w - V h| = sqrt(n2) / osc
+  double hn = n2[i] > 0 ? sqrt(n2[i]) : 0.0;
+  if (osc) hn = osc[i] > 0 ? hn / osc[i] : 0.0;
   Hc[((size_t)(j + 1) * m + j) * 2] = hn;
   Hc[((size_t)(j + 1) * m + j) * 2 + 1] = 0.0;
   if (done[i] && kc[i] >= 0) return;
@@ -627,21 +714,22 @@ static hipStream_t capture_stream(ddamg_ctx* c) {
   return c->cap_stream;
 }
 
-static void knob_state(ddamg_ctx* c, int (&k)[6]) {
+static void knob_state(ddamg_ctx* c, int (&k)[7]) {
   k[0] = c->dslash_rs[0];
   k[1] = c->dslash_rs[1];
   k[2] = c->fp32_links;
   k[3] = c->coarse_mfma;
   k[4] = c->sap_variant;
   k[5] = c->dslash_order;
+  k[6] = c->gram_lowsync;
 }
 
 static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {
-  int k[6];
+  int k[7];
   knob_state(c, k);
   GraphState* g = w.gs;
   const int g5 = level > 0 ? c->coarse[level].g5out : 0;
-  const bool same = g && g->nt == nt && g->m == m && g->g5 == g5 && std::equal(k, k + 6, g->knobs);
+  const bool same = g && g->nt == nt && g->m == m && g->g5 == g5 && std::equal(k, k + 7, g->knobs);
   if (same) return *g;
   destroy_graphs(c, g);
   g = new GraphState();
@@ -650,7 +738,7 @@ static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {
   g->m = m;
   g->g5 = g5;
   g->ncol = nt * c->T;
-  std::copy(k, k + 6, g->knobs);
+  std::copy(k, k + 7, g->knobs);
   const size_t n = g->ncol;
   auto dal = [&](size_t cnt) { return (double*)c->pool.alloc(std::max<size_t>(cnt, 1) * sizeof(double)); };
   g->d_H = dal(n * (m + 1) * m * 2);
@@ -667,6 +755,8 @@ static GraphState& graph_state(ddamg_ctx* c, LW& w, int level, int nt, int m) {
   const MV v0 = basis(c, w.V, 0, level, w.prec, w.cap, nt);
   for (int q = 1; q <= m + 1; ++q) part = std::max(part, multidot_partials(v0, q));
   g->d_part = dal(part);
+  g->d_osc = dal(n);
+  g->d_apart = dal(multiaxpy_partials(v0));
   g->d_kc = (int*)c->pool.alloc(n * sizeof(int));
   g->d_done = (int*)c->pool.alloc(n * sizeof(int));
   g->graph.assign(m, nullptr);
@@ -681,14 +771,27 @@ static void arnoldi_step_device(ddamg_ctx* c, int level, LW& w, GraphState& g, i
   MV vj = basis(c, w.V, j, level, prec, cap, nt);
   MV vn = basis(c, w.V, j + 1, level, prec, cap, nt);
   operator_apply(c, level, vj, vn, g.d_mu);
-  std::vector<MV> Vs(j + 1);
+  std::vector<MV> Vs(j + 2);
   for (int i = 0; i <= j; ++i) Vs[i] = basis(c, w.V, i, level, prec, cap, nt);
-  mv_multidot_buf(c, Vs.data(), j + 1, vn, w.d_h, g.d_part);
-  mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
-  mv_norm2_buf(c, vn, g.d_n2, g.d_cbuf, g.d_part);
-  mv_normalize(c, vn, g.d_n2);
+  const bool one_red = c->gram_lowsync != 0;
+  if (one_red) {
+    // one reduction: the dots with the basis and |w|^2 together; the update
+    // pass stores w - V h already scaled by the predicted 1 / h_{j+1,j}
+    Vs[j + 1] = vn;
+    mv_multidot_buf(c, Vs.data(), j + 2, vn, w.d_h, g.d_part);
+    hipLaunchKernelGGL(k_lowsync_scale, dim3((g.ncol + 63) / 64), dim3(64), 0, c->stream, j, g.ncol, w.d_h, g.d_osc);
+    DD_HIP(hipGetLastError());
+    mv_multiaxpy_scale_norm2(c, Vs.data(), j + 1, w.d_h, vn, -1, g.d_osc, g.d_n2, g.d_apart);
+    mv_renorm(c, vn, g.d_n2, renorm_tau(c, prec));
+  } else {
+    mv_multidot_buf(c, Vs.data(), j + 1, vn, w.d_h, g.d_part);
+    mv_multiaxpy(c, Vs.data(), j + 1, w.d_h, vn, -1);
+    mv_norm2_buf(c, vn, g.d_n2, g.d_cbuf, g.d_part);
+    mv_normalize(c, vn, g.d_n2);
+  }
   hipLaunchKernelGGL(k_g_step, dim3((g.ncol + 63) / 64), dim3(64), 0, c->stream, j, g.m, g.ncol, w.d_h, g.d_n2,
-                     g.d_H, g.d_cs, g.d_sn, g.d_g, g.d_kc, g.d_done, g.d_tol, g.d_est);
+                     one_red ? g.d_osc : (const double*)nullptr, g.d_H, g.d_cs, g.d_sn, g.d_g, g.d_kc, g.d_done,
+                     g.d_tol, g.d_est);
   DD_HIP(hipGetLastError());
 }
 

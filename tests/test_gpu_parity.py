@@ -544,6 +544,49 @@ def test_gmres_dr_iterates_match_oracle(torch_cuda, dd):
         ctx.close()
 
 
+def test_one_reduction_arnoldi_matches_oracle(torch_cuda, dd):
+    """The one-reduction Arnoldi step (DDAMG_KNOB_GRAM_ONE_REDUCTION: dots and
+    the new vector's own norm in one pass, normalisation predicted and fused
+    into the update, measured norm giving h_{j+1,j}) builds the same Krylov
+    space as classical Gram-Schmidt: coarse GMRES iterates after 12 steps (far
+    from converged) equal the oracle's GMRES (its GMRES-DR with k = 0 and one
+    cycle) to rounding in FP64, with graphs and host-driven steps, with the
+    correcting rescale on demand (1) and at every step (2), and the FP32
+    iterates of the three forms agree to FP32 rounding."""
+    torch = torch_cuda
+    say("one-reduction Arnoldi")
+    dims, agg, N = (8, 4, 4, 8), (2, 2, 2, 2), 8
+    U = S.gauge_field(dims, 0.3, 61)
+    V = S.volume(dims)
+    tv = S.gaussian_spinors(N, V, 81).reshape(N, V, 12)
+    blk = Blocking(dims, agg)
+    coarse = galerkin(FineLevel(O.WilsonTM(U, dims, kappa=0.15)), build_prolongator(tv, blk), blk)
+    mus = np.array([0.01, 0.01, 0.07, 0.2, 0.003, 0.05, 0.1, 0.3, 0.02, 0.15])     # 10 columns: two tiles
+    b = S.gaussian_coarse(len(mus), blk.nblocks, 2 * N, 84)
+    bg = torch.from_numpy(b).cuda()
+    m = steps = 12
+    xr, info = O.gmres_dr(lambda X, act: coarse.apply(X, mus[act]), b, 1e-14, m, 0, steps)
+    say(f"  oracle residual after {steps} steps: {info['relres'].min():.1e} .. {info['relres'].max():.1e}")
+    for graphs in (1, 0):
+        p = dd.default_params(dims=dims, kappa=0.15, n_levels=2, sap_block=agg, agg=[agg, agg], n_tv=[N, 8],
+                              setup_rounds=1, bottom_restart=m, bottom_maxit=steps, use_graphs=graphs)
+        ctx = dd.Context(p, U)
+        ctx.set_test_vectors(0, tv)
+        x32 = {}
+        for knob in (1, 0, 2):
+            ctx.set_tuning("gram_one_reduction", knob)
+            x, it = ctx.coarse_solve(1, dd.FP64, False, mus, bg, 1e-14, steps)
+            err = np.max(relerr_cols(x.cpu().numpy(), xr))
+            x32[knob] = ctx.coarse_solve(1, dd.FP32, False, mus, bg, 1e-14, steps)[0].cpu().numpy()
+            say(f"  graphs {graphs} knob {knob}: FP64 vs oracle {err:.2e}, steps {max(it)}")
+            assert err < 1e-9
+        for knob in (1, 2):
+            d = np.max(relerr_cols(x32[knob], x32[0]))
+            say(f"  graphs {graphs} FP32 knob {knob} vs knob 0: {d:.2e}")
+            assert d < 1e-4
+        ctx.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_three_level_gmres_dr(torch_cuda, dd, precision):
     """Three-level solve with GMRES-DR on the coarsest level (gamma5 form):
