@@ -1,0 +1,165 @@
+"""Multigrid solves at the workloads' full sizes, each column checked by the
+FP64 oracle's operator on the whole field, through the C ABI.
+
+* 16^3x32, 12 Z2 rhs x 4 shifts = 48 columns, the two-level solve (FP64
+  FGMRES(40) over the FP32 cycle with BF16 coarse blocks): every column.
+* 32^3x64, the whole uneven set of 24 independent solves
+  (``c3_solve_counts(24, 403)``, 211 columns, shifts log-spaced in [1e-3, 1])
+  in one ``ddamg_solve_batch`` call with the nested two-level form (FP64
+  FGMRES(1) over FP32 FGMRES(8) with an FP16 basis): every column by the
+  library's own FP64 check, six of them (the first and last column of the
+  set and one of each of the four smallest shifts) by the oracle.
+* 40^3x80, one rhs x the 8 shifts with the same nested form: the smallest
+  and the largest shift by the oracle.
+
+Bars: the oracle's true relative residual ||b - D(mu) x|| / ||b|| <= 1e-10
+per column (the goal of the solve), and the library's after-solve check
+``err_vs_fp64`` equal to the oracle's residual to 1e-13 (both are FP64
+evaluations of the same residual; they differ by summation order only).
+"""
+import gc
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synthetic as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TWO_LEVEL = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds=3, setup_boot=1,
+                 coarse_gamma5=1, bottom_maxit=100, inner_iters=0)
+NESTED = dict(TWO_LEVEL, outer_restart=1, inner_iters=8, inner_tol=1e-2, inner_fp16=1, max_outer=300)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2201_03872_amd as m
+    m.load()
+    return m
+
+
+def oracle_residuals(op, b_cols, x_cols, mus, chunk=8):
+    """||b_c - D(mu_c) x_c|| / ||b_c|| by the oracle, a few columns at a time."""
+    out = []
+    for s in range(0, len(mus), chunk):
+        e = min(s + chunk, len(mus))
+        r = b_cols[s:e] - op.apply(x_cols[s:e], mus[s:e])
+        n = len(range(s, e))
+        out += list(np.linalg.norm(r.reshape(n, -1), axis=1) / np.linalg.norm(b_cols[s:e].reshape(n, -1), axis=1))
+    return np.array(out)
+
+
+def check(rel, info_cols):
+    err = np.array([i["err_vs_fp64"] for i in info_cols])
+    say(f"  oracle residuals: max {rel.max():.2e}; |library check - oracle| max {np.max(np.abs(err - rel)):.1e}")
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+    assert np.max(np.abs(err - rel)) < 1e-13
+
+
+@pytest.mark.timeout(300)
+def test_two_level_16x16x16x32_all_48_columns(torch_cuda, dd):
+    torch = torch_cuda
+    w = S.workload("tm_16x16x16x32_12rhs_4shift")
+    say("16^3x32: 48 columns, two-level solve")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    b = S.rhs_for(w)
+    mus = np.array(w.mus)
+    ctx = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, outer_restart=40, max_outer=400, **TWO_LEVEL), U)
+    t0 = time.time()
+    x, info, st = ctx.solve(mus, torch.from_numpy(b).cuda())
+    say(f"  solve {time.time() - t0:.2f}s, status {st}")
+    assert st == dd.OK
+    xs = x.cpu().numpy()
+    ctx.close()
+    ns = len(mus)
+    cols = np.arange(len(info))
+    bb = b[cols // ns]
+    rel = oracle_residuals(O.WilsonTM(U, w.dims, kappa=w.kappa), bb, xs, mus[cols % ns])
+    check(rel, info)
+
+
+@pytest.mark.timeout(500)
+def test_nested_32x32x32x64_whole_uneven_set(torch_cuda, dd):
+    torch = torch_cuda
+    w = S.workload("tm_32x32x32x64_batched")
+    say("32^3x64: generating the gauge field and the 24 systems")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    V = S.volume(w.dims)
+    counts = S.c3_solve_counts(24, 403)
+    systems = [(np.asarray(m), S.gaussian_spinors(nr, V, 203 + i)) for i, (nr, m) in enumerate(counts)]
+    ncol = sum(b.shape[0] * len(m) for m, b in systems)
+    say(f"  {len(systems)} systems, {ncol} columns")
+    ctx = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, **NESTED), U)
+    t0 = time.time()
+    # right-hand sides handed over from host memory (copied to the device once)
+    xs, infos, st = ctx.solve_batch([(m, torch.from_numpy(b)) for m, b in systems])
+    stats = ctx.stats()
+    say(f"  solve_batch {time.time() - t0:.1f}s, status {st}, compactions {stats['col_removals']}, "
+        f"device peak {stats['device_bytes_peak'] / 2**30:.0f} GiB")
+    assert st == dd.OK
+    flat = [(si, c) for si, inf in enumerate(infos) for c in range(len(inf))]
+    assert len(flat) == ncol
+    worst = max(i["err_vs_fp64"] for inf in infos for i in inf)
+    say(f"  library FP64 check over all {ncol} columns: max {worst:.2e}")
+    assert all(i["converged"] for inf in infos for i in inf)
+    assert worst <= 1e-10 * (1 + 1e-6)
+    # oracle on six columns: first, last, and one of each of the four smallest shifts
+    mu_of = {}
+    for si, c in flat:
+        m = systems[si][0]
+        mu_of[(si, c)] = float(m[c % len(m)])
+    pick = [flat[0], flat[-1]]
+    for mu in sorted(set(mu_of.values()))[:4]:
+        pick.append(next(k for k in flat if mu_of[k] == mu and k not in pick))
+    op = O.WilsonTM(U, w.dims, kappa=w.kappa)
+    rel, inf_sel = [], []
+    for si, c in pick:
+        m, b = systems[si]
+        xc = xs[si][c].cpu().numpy()[None]
+        r = oracle_residuals(op, b[c // len(m)][None], xc, np.array([mu_of[(si, c)]]))
+        say(f"  system {si} column {c} (mu {mu_of[(si, c)]:.3g}): oracle {r[0]:.2e}")
+        rel.append(r[0])
+        inf_sel.append(infos[si][c])
+    check(np.array(rel), inf_sel)
+    ctx.close()
+    del xs
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(400)
+def test_nested_40x40x40x80_one_rhs_eight_shifts(torch_cuda, dd):
+    torch = torch_cuda
+    w = S.workload("tm_40x40x40x80_4rhs_8shift")
+    gc.collect()
+    torch.cuda.empty_cache()    # the hierarchy of this lattice needs most of the device
+    say("40^3x80: generating the gauge field")
+    U = S.gauge_field(w.dims, w.eps, w.seed_gauge)
+    b = S.rhs_for(w)[:1]
+    mus = np.array(w.mus)
+    ctx = dd.Context(dd.params_for_workload(w, precision=dd.MIXED, max_active_cols=8, **NESTED), U)
+    t0 = time.time()
+    x, info, st = ctx.solve(mus, torch.from_numpy(b).cuda())
+    say(f"  solve {time.time() - t0:.1f}s, status {st}, iterations {[i['outer_iters'] for i in info]}")
+    assert st == dd.OK
+    ctx.close()
+    pick = [0, len(mus) - 1]
+    xs = np.stack([x[c].cpu().numpy() for c in pick])
+    del x
+    torch.cuda.empty_cache()
+    rel = oracle_residuals(O.WilsonTM(U, w.dims, kappa=w.kappa), np.repeat(b, 2, axis=0), xs, mus[pick], chunk=1)
+    check(rel, [info[c] for c in pick])
