@@ -72,6 +72,30 @@ TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
 ROOFLINE_CLASS = "coarse1"
 
 
+# counter summary of the roofline kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes calibrated by the copy kernel); its traffic figure holds while the
+# kernel source is the one the counters were taken with
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                       "k_coarse_mfma_t1_48_40x40x40x80_8col.md")
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2201_03872_amd", "csrc", "coarse.hip")
+
+
+def counter_traffic():
+    """Calibrated HBM traffic per launch (bytes) of the roofline kernel, or
+    None when the summary is missing or the kernel source has changed since."""
+    import hashlib
+    import re
+    try:
+        txt = open(PROFILE).read()
+        sha = re.search(r"SHA-256 of \S+coarse.hip when the counters were taken \| ([0-9a-f]{64})", txt).group(1)
+        gb = float(re.search(r"traffic per launch \(calibrated fetch \+ write\) \| ([0-9.]+) GB", txt).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != sha:
+        return None
+    return gb * 1e9
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -441,7 +465,9 @@ def main():
     achieved = alg_bytes / (ms_l * 1e-3) / 1e9 if n_l else None
     roofline = {"kernel": "k_coarse_mfma_t1<48> (level-1 coarse stencil, BF16 MFMA, FP32 accumulation)",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic(),
+                "traffic_source": "profiles/k_coarse_mfma_t1_48_40x40x40x80_8col.md (FETCH_SIZE x 2.0 + "
+                                  "WRITE_SIZE x 1.0 per launch, factors from the copy kernel)",
                 "us_per_launch": us_launch, "launches_timed": n_l, "timed_in": "the timed solves",
                 "algorithmic_bytes_per_launch": alg_bytes / n_l if n_l else None,
                 "mfma_TFLOPs": (n_l and tiles_l * flops_tile / (ms_l * 1e-3) / 1e12),
