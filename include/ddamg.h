@@ -130,6 +130,10 @@ typedef struct ddamg_params {
   int    bottom_dr_k;        /* > 0: the coarsest level runs GMRES with deflated restarting,    */
                              /* GMRES-DR(m, k) (section 4): k harmonic Ritz vectors carried     */
                              /* over each restart; 0 = plain restarted GMRES                     */
+  int    coarse_fp16;        /* 1: the Krylov bases of the coarse levels' solves (MIXED       */
+                             /* precision) are stored in FP16 like the inner FGMRES basis      */
+                             /* (unnormalised, per-column entry scales), halving the bytes of   */
+                             /* their Gram-Schmidt passes; such solves run host-driven steps   */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

@@ -74,6 +74,7 @@ class Params(ctypes.Structure):
         ("coarse_gamma5", ctypes.c_int),
         ("bottom_restart", ctypes.c_int),
         ("bottom_dr_k", ctypes.c_int),
+        ("coarse_fp16", ctypes.c_int),
     ]
 
 

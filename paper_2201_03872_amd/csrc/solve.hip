@@ -275,8 +275,11 @@ void free_work(ddamg_ctx* c) {
 // for the inner FGMRES of the outer solve (same level, its own basis).
 static LW& lw(ddamg_ctx* c, int level, int prec, int ntiles, int role = 0) {
   LW& w = work(c).lw[{level, prec, role}];
-  // the inner FGMRES of the outer solve may keep its basis in FP16
-  if (w.vprec < 0) w.vprec = (role == 1 && prec == P32 && c->p.inner_fp16) ? P16 : prec;
+  // the inner FGMRES of the outer solve, and (coarse_fp16) the solves of the
+  // coarse levels, may keep their bases in FP16
+  if (w.vprec < 0)
+    w.vprec = (prec == P32 && ((role == 1 && c->p.inner_fp16) || (role == 0 && level > 0 && c->p.coarse_fp16)))
+                  ? P16 : prec;
   if (ntiles > w.cap) {
     for (auto& m : w.V) mv_free(c, m);
     for (auto& m : w.Z) mv_free(c, m);
@@ -905,7 +908,8 @@ void krylov(ddamg_ctx* c, int level, const double* d_mu, const MV& b, const MV& 
   // captured graphs record no timing events: a level whose stencil is being
   // timed live runs the host-driven steps (identical iterates)
   const bool timed = level == 1 && c->time_sap == TIMED_COARSE1;
-  if (!pc && !fixed && role == 0 && c->p.use_graphs && !timed) {
+  const bool f16_basis = role == 0 && level > 0 && b.prec == P32 && c->p.coarse_fp16;
+  if (!pc && !fixed && role == 0 && c->p.use_graphs && !timed && !f16_basis) {
     krylov_graph(c, level, d_mu, b, x, x_zero, tol, m, maxit, out);
     return;
   }

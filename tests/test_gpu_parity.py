@@ -587,6 +587,18 @@ def test_one_reduction_arnoldi_matches_oracle(torch_cuda, dd):
         ctx.close()
 
 
+@pytest.mark.parametrize("levels", [2, 3])
+def test_solve_coarse_fp16_bases(torch_cuda, dd, levels):
+    """Coarse-level Krylov bases stored in FP16 (coarse_fp16, MIXED): the
+    two- and three-level solves (gamma5 form) still bring every column to the
+    true FP64 residual 1e-10 by the oracle."""
+    w = S.workload("tm_8x8x8x8_3level" if levels == 3 else "tm_4x4x4x4_2rhs_3shift")
+    say("solve", w.name, "coarse FP16 bases")
+    rel, info, st = _solve_and_check(torch_cuda, dd, w, 1, coarse_gamma5=1, coarse_fp16=1)
+    assert st == dd.OK
+    assert np.all(rel <= 1e-10 * (1 + 1e-6))
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solve_three_level_gmres_dr(torch_cuda, dd, precision):
     """Three-level solve with GMRES-DR on the coarsest level (gamma5 form):
