@@ -134,6 +134,10 @@ typedef struct ddamg_params {
                              /* precision) are stored in FP16 like the inner FGMRES basis      */
                              /* (unnormalised, per-column entry scales), halving the bytes of   */
                              /* their Gram-Schmidt passes; such solves run host-driven steps   */
+  int    transfer_fp16;      /* 1: the FP32 restriction and prolongation between the fine     */
+                             /* level and level 1 read P in FP16 (half the bytes of the        */
+                             /* largest array they stream; entries of the orthonormal P are    */
+                             /* about 1/sqrt(6 |aggregate|), far inside the FP16 range)        */
 } ddamg_params;
 
 typedef struct ddamg_col_info {

@@ -75,6 +75,7 @@ class Params(ctypes.Structure):
         ("bottom_restart", ctypes.c_int),
         ("bottom_dr_k", ctypes.c_int),
         ("coarse_fp16", ctypes.c_int),
+        ("transfer_fp16", ctypes.c_int),
     ]
 
 

@@ -105,6 +105,7 @@ void ddamg_default_params(ddamg_params* p) {
   p->bottom_restart = 0;
   p->bottom_dr_k = 0;
   p->coarse_fp16 = 0;
+  p->transfer_fp16 = 0;
 }
 
 static void validate(const ddamg_params* p) {
@@ -147,6 +148,7 @@ static void validate(const ddamg_params* p) {
                                    (p->bottom_restart > 0 ? p->bottom_restart : std::min(p->bottom_maxit, 63))),
            DDAMG_EINVAL, "bottom_dr_k must be below the coarsest restart length minus one");
   DD_CHECK(p->coarse_fp16 == 0 || p->coarse_fp16 == 1, DDAMG_EINVAL, "coarse_fp16 must be 0 or 1");
+  DD_CHECK(p->transfer_fp16 == 0 || p->transfer_fp16 == 1, DDAMG_EINVAL, "transfer_fp16 must be 0 or 1");
   DD_CHECK(p->setup_fine_iters >= 0 && p->setup_fine_iters <= 63, DDAMG_EINVAL, "setup_fine_iters in [0, 63]");
   DD_CHECK(p->setup_boot >= 0 && p->setup_boot <= 16, DDAMG_EINVAL, "setup_boot in [0, 16]");
   DD_CHECK(p->setup_coarse_iters >= 1 && p->setup_coarse_iters <= 63, DDAMG_EINVAL, "setup_coarse_iters in [1, 63]");

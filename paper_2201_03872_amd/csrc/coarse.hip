@@ -349,12 +349,13 @@ void coarse_masked(ddamg_ctx* c, int level, const MV& x, const MV& y, int mode, 
 // y(a)[s*N + j] = sum_{x in A_a} sum_{k of chirality s} conj(P[x][k][j]) x(x)[k]
 // A dense contraction per aggregate, Y (2N x T) = P_a^dag X_a, streaming P
 // once: one workgroup of four waves per (aggregate, tile); lane (s, j) of a
-// wave owns row s*N + j for all T columns of the tile, the waves take every
-// fourth site and their partial sums meet in LDS.  Per site and 16-byte
-// chunk of the vector (CPC components of one chirality) the lanes read their
-// P entries (consecutive j: coalesced) and the chunk of every column (the
-// same addresses on every lane of a chirality: one broadcast line), then do
-// CPC * T multiply-adds.
+// wave owns row s*N + j for all T columns of the tile.  The aggregate's sites
+// are taken in batches whose vector chunks (all T columns) the workgroup
+// first stages in LDS with coalesced 16-byte loads (one distinct chunk per
+// lane); the waves then take every fourth site of the batch, each lane
+// reading its P entries from memory (consecutive j: coalesced) and the
+// chunks of the site from LDS (the same address on every lane of a
+// chirality: a broadcast), and their partial sums meet in LDS at the end.
 template <typename R>
 __global__ void __launch_bounds__(256) k_restrict(const R* __restrict__ x, R* __restrict__ y, const R* __restrict__ P,
                                                   const int* __restrict__ blk_of_coarse, int Vf, int dof, int N, int gs,
@@ -362,7 +363,9 @@ __global__ void __launch_bounds__(256) k_restrict(const R* __restrict__ x, R* __
   using C = typename Chunk<R>::type;
   constexpr int RW = Chunk<R>::RW;
   constexpr int CPC = RW / 2;
-  constexpr int NWR = 4;   // waves per aggregate, each over every NWR-th site; partial sums meet in LDS
+  constexpr int NWR = 4;          // waves per aggregate, each over every NWR-th site of a batch
+  constexpr int XS = 1536;        // staged chunks (24 KB)
+  __shared__ C xs[XS];
   __shared__ cx<R> part[NWR - 1][TC][64];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int a = wg % Vc, tile = wg / Vc;
@@ -373,29 +376,44 @@ __global__ void __launch_bounds__(256) k_restrict(const R* __restrict__ x, R* __
   const int b = blk_of_coarse[a];
   const C* xt = reinterpret_cast<const C*>(x + (size_t)tile * tile_f);
   const cx<R>* Pc = reinterpret_cast<const cx<R>*>(P);
+  const int nchs = dof / CPC;                 // chunks per site
+  const int per_site = nchs * TC;             // staged units per site
+  const int sb = XS / per_site;               // sites per batch
   cx<R> acc[TC];
 #pragma unroll
   for (int t = 0; t < TC; ++t) acc[t] = {0, 0};
   const int c0 = sig * h / CPC, nch = h / CPC;
-  for (int q = wv; q < gs; q += NWR) {
-    const int s = b * gs + q;
-    for (int cc = 0; cc < nch; ++cc) {
-      const int ch = c0 + cc;
-      cx<R> pv[CPC];
+  for (int q0 = 0; q0 < gs; q0 += sb) {
+    const int nsb = gs - q0 < sb ? gs - q0 : sb;
+    // stage: unit u = (chunk ch, site qq, column t), site fastest after t so
+    // that consecutive lanes read consecutive 16-byte chunks of memory
+    for (int u = threadIdx.x; u < nsb * per_site; u += blockDim.x) {
+      const int t = u % TC, rest = u / TC;
+      const int qq = rest % nsb, ch = rest / nsb;
+      xs[(qq * nchs + ch) * TC + t] = xt[((size_t)ch * Vf + (size_t)b * gs + q0 + qq) * TC + t];
+    }
+    __syncthreads();
+    for (int qq = wv; qq < nsb; qq += NWR) {
+      const int s = b * gs + q0 + qq;
+      for (int cc = 0; cc < nch; ++cc) {
+        const int ch = c0 + cc;
+        cx<R> pv[CPC];
 #pragma unroll
-      for (int e = 0; e < CPC; ++e) pv[e] = Pc[((size_t)s * dof + ch * CPC + e) * N + j];
-      const C* xc = xt + ((size_t)ch * Vf + s) * TC;
+        for (int e = 0; e < CPC; ++e) pv[e] = Pc[((size_t)s * dof + ch * CPC + e) * N + j];
+        const C* xc = xs + (qq * nchs + ch) * TC;
 #pragma unroll
-      for (int t = 0; t < TC; ++t) {
-        const C v = xc[t];
-        if constexpr (CPC == 1) {
-          cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
-        } else {
-          cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
-          cmac_conj(acc[t], pv[1], cx<R>{v.z, v.w});
+        for (int t = 0; t < TC; ++t) {
+          const C v = xc[t];
+          if constexpr (CPC == 1) {
+            cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
+          } else {
+            cmac_conj(acc[t], pv[0], cx<R>{v.x, v.y});
+            cmac_conj(acc[t], pv[1], cx<R>{v.z, v.w});
+          }
         }
       }
     }
+    __syncthreads();
   }
   if (wv > 0) {
 #pragma unroll
@@ -412,6 +430,173 @@ __global__ void __launch_bounds__(256) k_restrict(const R* __restrict__ x, R* __
   for (int t = 0; t < TC; ++t) store_one(yt, Vc, TC, a, t, r, acc[t]);
 }
 
+// ---- FP16 P (transfer_fp16, level 0): layout P16T[k/2][q][site][4] with
+// q = (k % 2) * N/4 + j/4 and 4 consecutive j per 16-byte chunk, so that the
+// lanes of consecutive sites read consecutive chunks (prolongation) and the
+// lanes j of one site read 4-byte entries of a few chunks (restriction).
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ size_t p16t_index(int k, int j, int s, int N, int Vf) {
+  return ((((size_t)(k / 2) * (N / 2) + (k % 2) * (N / 4) + j / 4) * Vf + s) * 4 + j % 4);
+}
+
+__global__ void k_to_p16t(const double* __restrict__ P, h2v* __restrict__ out, int Vf, int dof, int N) {
+  const size_t total = (size_t)Vf * dof * N;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i % N);
+    const int k = (int)((i / N) % dof);
+    const int s = (int)(i / ((size_t)N * dof));
+    h2v v;
+    v.x = (_Float16)P[i * 2];
+    v.y = (_Float16)P[i * 2 + 1];
+    out[p16t_index(k, j, s, N, Vf)] = v;
+  }
+}
+
+// The restriction of k_restrict<float> with P read from P16T.
+__global__ void __launch_bounds__(256) k_restrict16(const float* __restrict__ x, float* __restrict__ y,
+                                                    const h2v* __restrict__ P, const int* __restrict__ blk_of_coarse,
+                                                    int Vf, int dof, int N, int gs, int Vc, size_t tile_f,
+                                                    size_t tile_c) {
+  using C = float4;
+  constexpr int NWR = 4;
+  constexpr int XS = 1536;
+  __shared__ C xs[XS];
+  __shared__ cx<float> part[NWR - 1][TC][64];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = wg % Vc, tile = wg / Vc;
+  const int r = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const bool live = r < 2 * N;
+  const int sig = live ? r / N : 0, j = live ? r % N : 0;
+  const int h = dof / 2;
+  const int b = blk_of_coarse[a];
+  const C* xt = reinterpret_cast<const C*>(x + (size_t)tile * tile_f);
+  const int nchs = dof / 2;
+  const int per_site = nchs * TC;
+  const int sb = XS / per_site;
+  cx<float> acc[TC];
+#pragma unroll
+  for (int t = 0; t < TC; ++t) acc[t] = {0, 0};
+  const int c0 = sig * h / 2, nch = h / 2;
+  for (int q0 = 0; q0 < gs; q0 += sb) {
+    const int nsb = gs - q0 < sb ? gs - q0 : sb;
+    for (int u = threadIdx.x; u < nsb * per_site; u += blockDim.x) {
+      const int t = u % TC, rest = u / TC;
+      const int qq = rest % nsb, ch = rest / nsb;
+      xs[(qq * nchs + ch) * TC + t] = xt[((size_t)ch * Vf + (size_t)b * gs + q0 + qq) * TC + t];
+    }
+    __syncthreads();
+    for (int qq = wv; qq < nsb; qq += NWR) {
+      const int s = b * gs + q0 + qq;
+      for (int cc = 0; cc < nch; ++cc) {
+        const int ch = c0 + cc;
+        cx<float> pv[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const h2v v = P[p16t_index(ch * 2 + e, j, s, N, Vf)];
+          pv[e] = cx<float>{(float)v.x, (float)v.y};
+        }
+        const C* xc = xs + (qq * nchs + ch) * TC;
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+          const C v = xc[t];
+          cmac_conj(acc[t], pv[0], cx<float>{v.x, v.y});
+          cmac_conj(acc[t], pv[1], cx<float>{v.z, v.w});
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < TC; ++t) part[wv - 1][t][r] = acc[t];
+  }
+  __syncthreads();
+  if (wv > 0 || !live) return;
+#pragma unroll
+  for (int t = 0; t < TC; ++t)
+#pragma unroll
+    for (int w = 0; w < NWR - 1; ++w) acc[t] = acc[t] + part[w][t][r];
+  float* yt = y + (size_t)tile * tile_c;
+#pragma unroll
+  for (int t = 0; t < TC; ++t) store_one(yt, Vc, TC, a, t, r, acc[t]);
+}
+
+// y(x)[k] (+)= sum_j P[x][k][j] xc(a(x))[s(k)*N + j] with P from P16T: one
+// lane per (row pair c, fine site) computing both rows of the pair for the T
+// columns of a tile.  Each wave's 64 sites lie in one aggregate (aggregates of
+// a multiple of 64 sites), whose coarse vector half (N complexes x T columns)
+// the wave stages in LDS; the lane then streams its 2 x N/4 chunks of P
+// (consecutive sites: consecutive chunks) and reads the coarse values from
+// LDS (one address per wave: a broadcast).
+template <int NN>
+__global__ void __launch_bounds__(256) k_prolong16(const float* __restrict__ xc, float* __restrict__ y,
+                                                   const h2v* __restrict__ P, const int* __restrict__ coarse_of_blk,
+                                                   int Vf, int dof, int gs, int Vc, size_t tile_f, size_t tile_c,
+                                                   int accumulate) {
+  __shared__ float4 xs[4][NN / 2][TC];   // per wave: pairs of complexes (j, j+1) per column
+  const int npair = dof / 2;
+  const int nsblk = Vf / 256;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int sbk = blk % nsblk;
+  const int c = (blk / nsblk) % npair;
+  const int tile = blk / (nsblk * npair);
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int s = sbk * 256 + threadIdx.x;
+  const int a = coarse_of_blk[(sbk * 256 + wv * 64) / gs];
+  const int sig = (2 * c) / (dof / 2);
+  const float4* ct = reinterpret_cast<const float4*>(xc + (size_t)tile * tile_c);
+  for (int u = lane; u < (NN / 2) * TC; u += 64) {
+    const int t = u % TC, jp = u / TC;
+    xs[wv][jp][t] = ct[((size_t)(sig * (NN / 2) + jp) * Vc + a) * TC + t];
+  }
+  __syncthreads();
+  cx<float> acc[2][TC];
+#pragma unroll
+  for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+    for (int t = 0; t < TC; ++t) acc[rr][t] = {0, 0};
+  const uint4* Pc = reinterpret_cast<const uint4*>(P);
+#pragma unroll
+  for (int rr = 0; rr < 2; ++rr) {
+#pragma unroll 3
+    for (int q4 = 0; q4 < NN / 4; ++q4) {
+      const uint4 raw = Pc[((size_t)c * (NN / 2) + rr * (NN / 4) + q4) * Vf + s];
+      const h2v* pe = reinterpret_cast<const h2v*>(&raw);
+#pragma unroll
+      for (int e = 0; e < 4; e += 2) {
+        const cx<float> p0{(float)pe[e].x, (float)pe[e].y}, p1{(float)pe[e + 1].x, (float)pe[e + 1].y};
+        const int jp = (q4 * 4 + e) / 2;
+#pragma unroll
+        for (int t = 0; t < TC; ++t) {
+          const float4 v = xs[wv][jp][t];
+          cmac(acc[rr][t], p0, cx<float>{v.x, v.y});
+          cmac(acc[rr][t], p1, cx<float>{v.z, v.w});
+        }
+      }
+    }
+  }
+  float4* yt = reinterpret_cast<float4*>(y + (size_t)tile * tile_f);
+#pragma unroll
+  for (int t = 0; t < TC; ++t) {
+    float4* out = yt + ((size_t)c * Vf + s) * TC + t;
+    float4 o = {acc[0][t].re, acc[0][t].im, acc[1][t].re, acc[1][t].im};
+    if (accumulate) {
+      const float4 p = *out;
+      o.x += p.x; o.y += p.y; o.z += p.z; o.w += p.w;
+    }
+    *out = o;
+  }
+}
+
+void convert_P16T(ddamg_ctx* c, int level) {
+  const LevelGeom& g = c->geom[level];
+  const size_t n = (size_t)g.V * g.dof * c->tr[level].N;
+  hipLaunchKernelGGL(k_to_p16t, grid1(n), dim3(256), 0, c->stream, c->tr[level].d_P64, (h2v*)c->tr[level].d_P16T,
+                     g.V, g.dof, c->tr[level].N);
+  DD_HIP(hipGetLastError());
+}
+
 void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
   const LevelGeom& gf = c->geom[level];
   const LevelGeom& gc = c->geom[level + 1];
@@ -425,6 +610,10 @@ void restrict_mv(ddamg_ctx* c, int level, const MV& x, const MV& y) {
   if (x.prec == P64)
     hipLaunchKernelGGL(k_restrict<double>, grid, blk, 0, c->stream, x.as<double>(), y.as<double>(), c->tr[level].d_P64,
                        gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
+  else if (c->tr[level].d_P16T)
+    hipLaunchKernelGGL(k_restrict16, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(),
+                       (const h2v*)c->tr[level].d_P16T, gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V,
+                       x.tile_reals(), y.tile_reals());
   else
     hipLaunchKernelGGL(k_restrict<float>, grid, blk, 0, c->stream, x.as<float>(), y.as<float>(), c->tr[level].d_P32,
                        gc.d_blk_of_coarse, gf.V, gf.dof, N, gf.gsize, gc.V, x.tile_reals(), y.tile_reals());
@@ -546,10 +735,20 @@ void prolong_mv(ddamg_ctx* c, int level, const MV& x, const MV& y, int accumulat
            "prolong: shape");
   const int cpc = reals_per_chunk(x.prec) / 2;
   DD_CHECK(N % cpc == 0, DDAMG_EINVAL, "prolong: N must be whole chunks");
+  DD_CHECK(x.prec == P64 || c->tr[level].d_P32 || (c->tr[level].d_P16T && (N == 24 || N == 32)), DDAMG_ESTATE,
+           "prolong: no FP32 or FP16 P for this level");
   if (level == 0) kernel_timing_begin(c, TIMED_PROLONG0);
   if (x.prec == P64)
     prolong_dispatch<double>(c, x.as<double>(), y.as<double>(), c->tr[level].d_P64, gf, gc, N, y.tile_reals(),
                              x.tile_reals(), accumulate, x.ntiles);
+  else if (c->tr[level].d_P16T && N == 24)
+    hipLaunchKernelGGL(k_prolong16<24>, dim3((unsigned)((size_t)x.ntiles * (gf.dof / 2) * (gf.V / 256))), dim3(256),
+                       0, c->stream, x.as<float>(), y.as<float>(), (const h2v*)c->tr[level].d_P16T,
+                       gf.d_coarse_of_blk, gf.V, gf.dof, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate);
+  else if (c->tr[level].d_P16T && N == 32)
+    hipLaunchKernelGGL(k_prolong16<32>, dim3((unsigned)((size_t)x.ntiles * (gf.dof / 2) * (gf.V / 256))), dim3(256),
+                       0, c->stream, x.as<float>(), y.as<float>(), (const h2v*)c->tr[level].d_P16T,
+                       gf.d_coarse_of_blk, gf.V, gf.dof, gf.gsize, gc.V, y.tile_reals(), x.tile_reals(), accumulate);
   else
     prolong_dispatch<float>(c, x.as<float>(), y.as<float>(), c->tr[level].d_P32, gf, gc, N, y.tile_reals(),
                             x.tile_reals(), accumulate, x.ntiles);
@@ -709,7 +908,11 @@ __global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, size_
 void convert_P32(ddamg_ctx* c, int level) {
   const LevelGeom& g = c->geom[level];
   const size_t n = (size_t)g.V * g.dof * c->tr[level].N * 2;
-  hipLaunchKernelGGL(k_d2f, grid1(n), dim3(256), 0, c->stream, c->tr[level].d_P64, c->tr[level].d_P32, n);
+  if (c->tr[level].d_P32) {
+    hipLaunchKernelGGL(k_d2f, grid1(n), dim3(256), 0, c->stream, c->tr[level].d_P64, c->tr[level].d_P32, n);
+    DD_HIP(hipGetLastError());
+  }
+  if (c->tr[level].d_P16T) convert_P16T(c, level);
   DD_HIP(hipGetLastError());
 }
 

@@ -104,6 +104,9 @@ struct Transfer {
   int N = 0;                 // test vectors; coarse dof = 2N
   double* d_P64 = nullptr;   // [V_l][dof_l][N] complex, orthonormal per (aggregate, chirality)
   float* d_P32 = nullptr;
+  // level 0 with transfer_fp16: P in FP16, [k/2][2 rows x N/4 chunks][V] chunks of
+  // 4 complexes (16 bytes): consecutive sites contiguous for each (row pair, chunk)
+  void* d_P16T = nullptr;
 };
 
 struct Coarse {

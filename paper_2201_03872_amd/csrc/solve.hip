@@ -1664,7 +1664,14 @@ void build_transition(ddamg_ctx* c, int l, const MV& tv) {
   const size_t nP = (size_t)g.V * g.dof * N * 2;
   if (!c->tr[l].d_P64) {
     c->tr[l].d_P64 = (double*)c->pool.alloc(nP * sizeof(double));
-    c->tr[l].d_P32 = (float*)c->pool.alloc(nP * sizeof(float));
+    if (l == 0 && c->p.transfer_fp16 && c->p.precision == DDAMG_MIXED) {
+      // the FP32 transfers of this level read the FP16 copy only: no FP32 copy
+      DD_CHECK(N % 4 == 0 && (N == 24 || N == 32) && g.gsize % 64 == 0 && g.V % 256 == 0 && g.dof % 2 == 0,
+               DDAMG_EINVAL, "transfer_fp16 needs N = 24 or 32 and aggregates of a multiple of 64 sites");
+      c->tr[l].d_P16T = c->pool.alloc(nP * sizeof(_Float16));
+    } else {
+      c->tr[l].d_P32 = (float*)c->pool.alloc(nP * sizeof(float));
+    }
   }
   gather_test_vectors(c, l, tv, c->tr[l].d_P64);
   orthonormalise_P(c, l, c->tr[l].d_P64);

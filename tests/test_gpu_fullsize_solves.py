@@ -5,8 +5,9 @@ FP64 oracle's operator on the whole field, through the C ABI.
   FGMRES(40) over the FP32 cycle with BF16 coarse blocks): every column.
 * 32^3x64, the whole uneven set of 24 independent solves
   (``c3_solve_counts(24, 403)``, 211 columns, shifts log-spaced in [1e-3, 1])
-  in one ``ddamg_solve_batch`` call with the nested two-level form (FP64
-  FGMRES(1) over FP32 FGMRES(8) with an FP16 basis, FP16 coarse bases): every column by the
+  in one ``ddamg_solve_batch`` call with the nested two-level form of the
+  benchmark (FP64 FGMRES(1) over FP32 FGMRES(12) with an FP16 basis, FP16
+  coarse bases, FP16 P in the level-0 transfers): every column by the
   library's own FP64 check, six of them (the first and last column of the
   set and one of each of the four smallest shifts) by the oracle.
 * 40^3x80, one rhs x the 8 shifts with the same nested form: the smallest
@@ -31,7 +32,8 @@ pytestmark = pytest.mark.gpu
 
 TWO_LEVEL = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds=3, setup_boot=1,
                  coarse_gamma5=1, bottom_maxit=100, inner_iters=0)
-NESTED = dict(TWO_LEVEL, outer_restart=1, inner_iters=8, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1, max_outer=300)
+NESTED = dict(TWO_LEVEL, setup_boot=2, outer_restart=1, inner_iters=12, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1,
+              transfer_fp16=1, max_outer=300)
 
 
 def say(*a):

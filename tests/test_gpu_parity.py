@@ -215,12 +215,12 @@ def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
     ctx.close()
 
 
-def _two_level_case(dd, dims, agg, N, n_levels=2, agg2=(2, 2, 2, 2), N2=8):
+def _two_level_case(dd, dims, agg, N, n_levels=2, agg2=(2, 2, 2, 2), N2=8, **extra):
     U = S.gauge_field(dims, 0.3, 61)
     V = S.volume(dims)
     tv = S.gaussian_spinors(N, V, 62)
     kw = dict(dims=dims, kappa=0.15, n_levels=n_levels, sap_block=agg, agg=[agg, agg2], n_tv=[N, N2],
-              setup_rounds=1)
+              setup_rounds=1, **extra)
     p = dd.default_params(**kw)
     tv_init = [tv]
     if n_levels == 3:
@@ -293,6 +293,42 @@ def test_transfer_fp32_parity(torch_cuda, dd, dims, agg, N):
         say(f"  ncol {ncol}: R rel err {e_r:.2e} (bar {6 * blk.bsize * u:.1e}), P rel err {e_p:.2e} (bar {N * u:.1e})")
         assert e_r < 6 * blk.bsize * u
         assert e_p < N * u
+    ctx.close()
+
+
+@pytest.mark.parametrize("N", [24, 32])
+def test_transfer_fp16_p_parity(torch_cuda, dd, N):
+    """FP32 restriction and prolongation with P stored in FP16 (transfer_fp16,
+    the tuned form's level-0 transfers) against the oracle's FP64 R and P with
+    the same test vectors, on 8^4 with 4^4 aggregates, two tiles (the second
+    ragged) and one.  Bar: every P entry carries the FP16 rounding 2^-11
+    relative; the sums over K = 6 |A| (R) or N (P) products average those
+    errors, so the relative error per column stays near 2^-11 = 4.9e-4; the
+    bar is 4 * 2^-11 (the measured error is printed).  A layout or index
+    mistake would give O(1) errors."""
+    torch = torch_cuda
+    dims, agg = (8, 8, 8, 8), (4, 4, 4, 4)
+    say("transfer FP16 P", dims, agg, N)
+    ctx, U, V = _two_level_case(dd, dims, agg, N, transfer_fp16=1, precision=dd.MIXED)
+    tv = S.gaussian_spinors(N, V, 67).reshape(N, V, 12)
+    ctx.set_test_vectors(0, tv)
+    blk = Blocking(dims, agg)
+    P = build_prolongator(tv, blk)
+    bar = 4 * 2.0 ** -11
+    for ncol in (10, 3):
+        x = S.gaussian_spinors(ncol, V, 168 + ncol)
+        rc_ref = restrict(P, blk, x.reshape(ncol, V, 12))
+        rc = ctx.restrict(0, dd.FP32, torch.from_numpy(x).cuda()).cpu().numpy()
+        e_r = np.max(relerr_cols(rc, rc_ref))
+        xc = S.gaussian_coarse(ncol, blk.nblocks, 2 * N, 180 + ncol)
+        pr_ref = prolong(P, blk, xc).reshape(ncol, V, 4, 3)
+        pr = ctx.prolong(0, dd.FP32, torch.from_numpy(xc).cuda()).cpu().numpy()
+        e_p = np.max(relerr_cols(pr, pr_ref))
+        say(f"  ncol {ncol}: R rel err {e_r:.2e}, P rel err {e_p:.2e} (bar {bar:.1e})")
+        assert e_r < bar and e_p < bar
+        # FP64 transfers keep the FP64 P
+        rc64 = ctx.restrict(0, dd.FP64, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.max(relerr_cols(rc64, rc_ref)) < 1e-13
     ctx.close()
 
 
