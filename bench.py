@@ -106,11 +106,13 @@ def log(*a):
 def coarse1_bytes_flops(Vc, d, ncol_tiles):
     """Algorithmic bytes and flops of one launch of the level-1 coarse stencil
     on BF16 MFMA: the 9 blocks of each coarse site once in the MFMA operand
-    form [Re A | Im A] (d x 2d BF16, 4 d^2 bytes per block), the FP32 input
-    and output vectors (8 bytes per complex, 8 columns per tile); flops 8 per
-    complex multiply-add, 9 d^2 per site and column."""
+    form [Re A | Im A] (d x 2d BF16, 4 d^2 bytes per block), the input vector
+    as the coarse GMRES stores it (an FP16 basis vector, 4 bytes per complex;
+    the few restart residuals read FP32) and the FP32 output (8 bytes per
+    complex), 8 columns per tile; flops 8 per complex multiply-add, 9 d^2 per
+    site and column."""
     ncol = 8 * ncol_tiles
-    bytes_ = Vc * (9 * 4 * d * d + 2 * 8 * d * ncol)
+    bytes_ = Vc * (9 * 4 * d * d + (4 + 8) * d * ncol)
     flops = Vc * 9 * d * d * 8 * ncol
     return bytes_, flops
 
@@ -467,7 +469,8 @@ def main():
     alg_bytes = n_l * blocks_bytes + tiles_l * (bytes_tile - blocks_bytes)
     us_launch = ms_l * 1e3 / n_l if n_l else None
     achieved = alg_bytes / (ms_l * 1e-3) / 1e9 if n_l else None
-    roofline = {"kernel": "k_coarse_mfma_t1<48> (level-1 coarse stencil, BF16 MFMA, FP32 accumulation)",
+    roofline = {"kernel": "k_coarse_mfma_t1<48, _Float16> (level-1 coarse stencil on the FP16 basis vector, BF16 "
+                          "MFMA, FP32 accumulation)",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic(),
                 "traffic_source": "profiles/k_coarse_mfma_t1_48_40x40x40x80_8col.md (FETCH_SIZE x 2.0 + "

@@ -200,12 +200,17 @@ __global__ void __launch_bounds__(256) k_coarse_mfma(const float* __restrict__ x
 // site and its 8 neighbours (9 d complexes per column) is staged in LDS once
 // by coalesced 16-byte loads and shared by the d/16 waves (each owns 16
 // rows); the A operand streams from memory once per workgroup.
-template <int D>
-__global__ void __launch_bounds__(64 * (D / 16)) k_coarse_mfma_t1(const float* __restrict__ x, float* __restrict__ y,
+// XT = _Float16: x is an FP16 Krylov basis vector (the FP32 layout with
+// 2-byte reals, entries stored times 1/xscale), read and scaled on the way
+// into LDS, so the coarse GMRES with an FP16 basis needs no FP32 copy first.
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+template <int D, typename XT>
+__global__ void __launch_bounds__(64 * (D / 16)) k_coarse_mfma_t1(const XT* __restrict__ x, float* __restrict__ y,
                                                                  const bf16x8* __restrict__ A,
                                                                  const int* __restrict__ nbr,
                                                                  const double* __restrict__ mu, double muf, int V,
-                                                                 int g5o) {
+                                                                 int g5o, float xscale) {
   constexpr int MT = D / 16, KS = D / 16, NCH = D / 2;   // row tiles, k steps, 2-complex chunks per site
   constexpr int NT = 64 * MT;
   __shared__ float4 xs[9][NCH][TC];
@@ -215,10 +220,15 @@ __global__ void __launch_bounds__(64 * (D / 16)) k_coarse_mfma_t1(const float* _
   nb[0] = s;
 #pragma unroll
   for (int p = 1; p < 9; ++p) nb[p] = nbr[(size_t)(p - 1) * V + s];
-  const float4* xg = reinterpret_cast<const float4*>(x);
   for (int q = threadIdx.x; q < 9 * NCH * TC; q += NT) {
     const int t = q % TC, c = (q / TC) % NCH, p = q / (TC * NCH);
-    xs[p][c][t] = xg[((size_t)c * V + nb[p]) * TC + t];
+    const size_t src = ((size_t)c * V + nb[p]) * TC + t;
+    if constexpr (sizeof(XT) == 4) {
+      xs[p][c][t] = reinterpret_cast<const float4*>(x)[src];
+    } else {
+      const h4v h = reinterpret_cast<const h4v*>(x)[src];
+      xs[p][c][t] = float4{(float)h.x * xscale, (float)h.y * xscale, (float)h.z * xscale, (float)h.w * xscale};
+    }
   }
   __syncthreads();
   const int n = lane % 16, kb = lane / 16;
@@ -276,6 +286,13 @@ static bool use_mfma(ddamg_ctx* c, int level, const MV& x) {
   return x.prec == P32 && c->coarse_mfma && d % 16 == 0 && d <= 64 && c->coarse[level].d_blk16 != nullptr;
 }
 
+// The coarse stencil takes an FP16 input directly (one-tile MFMA form).
+bool coarse_takes_f16(ddamg_ctx* c, int level, int ntiles) {
+  const int d = c->geom[level].dof;
+  return level > 0 && ntiles == 1 && c->coarse_mfma && d % 16 == 0 && d >= 16 && d <= 64 &&
+         c->coarse[level].d_blk16 != nullptr;
+}
+
 static void coarse_apply_launch(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);
 
 void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
@@ -287,20 +304,33 @@ void coarse_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const doubl
 static void coarse_apply_launch(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu) {
   const LevelGeom& g = c->geom[level];
   const int d = g.dof;
-  if (use_mfma(c, level, x) && x.ntiles == 1) {
+  DD_CHECK(x.prec != P16 || x.ntiles == 1, DDAMG_EINVAL, "coarse stencil: FP16 input needs one column tile");
+  if ((use_mfma(c, level, x) || x.prec == P16) && x.ntiles == 1) {
+    DD_CHECK(x.prec == P32 || (x.prec == P16 && y.prec == P32 && coarse_takes_f16(c, level, 1)), DDAMG_EINVAL,
+             "coarse stencil: FP16 input needs the one-tile MFMA form");
     const bf16x8* A = (const bf16x8*)c->coarse[level].d_blk16;
     const double muf = c->coarse[level].mu_factor;
     const int g5o = c->coarse[level].g5out;
-    switch (d) {
-      case 16: hipLaunchKernelGGL(k_coarse_mfma_t1<16>, dim3(g.V), dim3(64), 0, c->stream, x.as<float>(), y.as<float>(),
-                                  A, g.d_nbr, d_mu, muf, g.V, g5o); break;
-      case 32: hipLaunchKernelGGL(k_coarse_mfma_t1<32>, dim3(g.V), dim3(128), 0, c->stream, x.as<float>(),
-                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
-      case 48: hipLaunchKernelGGL(k_coarse_mfma_t1<48>, dim3(g.V), dim3(192), 0, c->stream, x.as<float>(),
-                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
-      default: hipLaunchKernelGGL(k_coarse_mfma_t1<64>, dim3(g.V), dim3(256), 0, c->stream, x.as<float>(),
-                                  y.as<float>(), A, g.d_nbr, d_mu, muf, g.V, g5o); break;
+#define DD_T1(DD, XT, NTH)                                                                                     \
+  hipLaunchKernelGGL((k_coarse_mfma_t1<DD, XT>), dim3(g.V), dim3(NTH), 0, c->stream, x.as<XT>(), y.as<float>(), A, \
+                     g.d_nbr, d_mu, muf, g.V, g5o, xs)
+    const float xs = x.prec == P16 ? (float)(1.0 / x.hscale) : 1.0f;
+    if (x.prec == P16) {
+      switch (d) {
+        case 16: DD_T1(16, _Float16, 64); break;
+        case 32: DD_T1(32, _Float16, 128); break;
+        case 48: DD_T1(48, _Float16, 192); break;
+        default: DD_T1(64, _Float16, 256); break;
+      }
+    } else {
+      switch (d) {
+        case 16: DD_T1(16, float, 64); break;
+        case 32: DD_T1(32, float, 128); break;
+        case 48: DD_T1(48, float, 192); break;
+        default: DD_T1(64, float, 256); break;
+      }
     }
+#undef DD_T1
     DD_HIP(hipGetLastError());
     return;
   }

@@ -313,6 +313,7 @@ void level_gmres_dr(ddamg_ctx* c, int level, const double* d_mu, const MV& b, co
 
 // ---- host helpers ----
 void operator_apply(ddamg_ctx* c, int level, const MV& x, const MV& y, const double* d_mu);
+bool coarse_takes_f16(ddamg_ctx* c, int level, int ntiles);
 double* scratch(ddamg_ctx* c, size_t bytes);          // reduction partials (grows)
 double* small_buffer(ddamg_ctx* c, int n_doubles);    // short-lived small device results (grows)
 void mv_convert(ddamg_ctx* c, const MV& s, const MV& d);

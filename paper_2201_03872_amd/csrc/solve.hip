@@ -390,7 +390,9 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
   int jj = 0;
   for (int j = 0; j < m && j < budget; ++j) {
     MV vj = basis(c, w.V, j, level, vprec, cap, nt);
-    if (half && !pc_f16) {
+    // the one-tile MFMA coarse stencil reads the FP16 basis vector itself
+    const bool op_f16 = half && !pc && level > 0 && coarse_takes_f16(c, level, nt);
+    if (half && !pc_f16 && !op_f16) {
       MV v32 = get(c, w.vi, level, prec, cap, nt);
       mv_copy(c, vj, v32);
       vj = v32;
@@ -401,7 +403,7 @@ static int gmres_cycle(ddamg_ctx* c, int level, LW& w, int nt, const MV& x, cons
       (*pc)(vj, z, d_mu);
     }
     MV vn = half ? get(c, w.wt, level, prec, cap, nt) : basis(c, w.V, j + 1, level, vprec, cap, nt);
-    if (z.prec != prec) {
+    if (z.prec != prec && !op_f16) {
       MV zt = get(c, w.zt, level, prec, cap, nt);
       mv_copy(c, z, zt);
       operator_apply(c, level, zt, vn, d_mu);
