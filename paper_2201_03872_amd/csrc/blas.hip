@@ -217,10 +217,86 @@ __global__ void k_canon_cols(R* __restrict__ in, double* __restrict__ canon, con
   }
 }
 
+// The same conversion as a transpose through LDS: one workgroup per (tile,
+// group of SG internal sites) stages the T columns of its sites as
+// [column][site][component] complexes, so that both sides are read and
+// written in runs of consecutive addresses (the canonical side per column
+// and site, the internal side per chunk across sites and columns).  Rows of
+// the staging buffer are padded by two complexes against bank conflicts.
+template <typename R, int SG>
+__global__ void __launch_bounds__(256) k_canon_cols_lds(R* __restrict__ in, double* __restrict__ canon,
+                                                        const int* __restrict__ int2can, const int* __restrict__ map,
+                                                        int V, int dof, int dir) {
+  constexpr int RW = Chunk<R>::RW, CPC = RW / 2, T = TTB;
+  extern __shared__ double2 buf[];          // [T][SG * dof + 2]
+  const int rowlen = SG * dof + 2;
+  const int ngrp = (V + SG - 1) / SG;
+  const int tile = blockIdx.x / ngrp, s0 = (blockIdx.x % ngrp) * SG;
+  const int nchunk = 2 * dof / RW;
+  R* it = in + (size_t)tile * nchunk * V * T * RW;
+  const int nu = T * SG * dof;
+  if (dir == 0) {   // canonical -> LDS (runs along the components of one column and site)
+    for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+      const int k = u % dof, rest = u / dof, sl = rest % SG, t = rest / SG;
+      const int f = map[tile * T + t], s = s0 + sl;
+      if (f < 0 || s >= V) continue;
+      const double* d = canon + (((size_t)f * V + int2can[s]) * dof + k) * 2;
+      buf[t * rowlen + sl * dof + k] = double2{d[0], d[1]};
+    }
+    __syncthreads();
+    // LDS -> internal (runs along the columns and sites of one chunk)
+    for (int u = threadIdx.x; u < T * SG * nchunk; u += blockDim.x) {
+      const int t = u % T, rest = u / T, sl = rest % SG, ch = rest / SG;
+      const int f = map[tile * T + t], s = s0 + sl;
+      if (f < 0 || s >= V) continue;
+      R* q = it + (((size_t)ch * V + s) * T + t) * RW;
+#pragma unroll
+      for (int e = 0; e < CPC; ++e) {
+        const double2 v = buf[t * rowlen + sl * dof + ch * CPC + e];
+        q[2 * e] = (R)v.x;
+        q[2 * e + 1] = (R)v.y;
+      }
+    }
+  } else {          // internal -> LDS -> canonical
+    for (int u = threadIdx.x; u < T * SG * nchunk; u += blockDim.x) {
+      const int t = u % T, rest = u / T, sl = rest % SG, ch = rest / SG;
+      const int f = map[tile * T + t], s = s0 + sl;
+      if (f < 0 || s >= V) continue;
+      const R* q = it + (((size_t)ch * V + s) * T + t) * RW;
+#pragma unroll
+      for (int e = 0; e < CPC; ++e) buf[t * rowlen + sl * dof + ch * CPC + e] = double2{(double)q[2 * e], (double)q[2 * e + 1]};
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+      const int k = u % dof, rest = u / dof, sl = rest % SG, t = rest / SG;
+      const int f = map[tile * T + t], s = s0 + sl;
+      if (f < 0 || s >= V) continue;
+      const double2 v = buf[t * rowlen + sl * dof + k];
+      double* d = canon + (((size_t)f * V + int2can[s]) * dof + k) * 2;
+      d[0] = v.x;
+      d[1] = v.y;
+    }
+  }
+}
+
 void canon_cols(ddamg_ctx* c, int level, const MV& mv, const int* d_map, double* canon, int dir) {
   const LevelGeom& g = c->geom[level];
   DD_CHECK(mv.nsites == g.V && mv.dof == g.dof, DDAMG_EINVAL, "canon_cols: shape");
   const size_t n = (size_t)mv.ncol() * g.V * g.dof;
+  constexpr int SG = 32;
+  const size_t lds = (size_t)TTB * (SG * g.dof + 2) * sizeof(double2);
+  if (mv.T == TTB && lds <= 64 * 1024 && (mv.prec == P64 || mv.prec == P32)) {
+    const int ngrp = (g.V + SG - 1) / SG;
+    const dim3 grid((unsigned)(ngrp * mv.ntiles));
+    if (mv.prec == P64)
+      hipLaunchKernelGGL((k_canon_cols_lds<double, SG>), grid, dim3(256), lds, c->stream, mv.as<double>(), canon,
+                         g.d_int2can, d_map, g.V, g.dof, dir);
+    else
+      hipLaunchKernelGGL((k_canon_cols_lds<float, SG>), grid, dim3(256), lds, c->stream, mv.as<float>(), canon,
+                         g.d_int2can, d_map, g.V, g.dof, dir);
+    DD_HIP(hipGetLastError());
+    return;
+  }
   if (mv.prec == P64)
     hipLaunchKernelGGL(k_canon_cols<double>, grid_for(n), dim3(256), 0, c->stream, mv.as<double>(), canon,
                        g.d_int2can, d_map, mv.ncol(), g.V, g.dof, mv.T, dir);
