@@ -861,9 +861,7 @@ __device__ __forceinline__ cx<double> block_sum(cx<double> v, cx<double>* red) {
 // (gs * dof/2) x N matrix P by modified Gram-Schmidt applied twice; the
 // diagonal of R comes out real and positive, so the result equals any other
 // QR of full-rank input with that convention.
-__global__ void __launch_bounds__(256) k_orthonormalise(double* __restrict__ P, int dof, int N, int gs) {
-  __shared__ cx<double> red[4];
-  const int b = blockIdx.x / 2, sig = blockIdx.x % 2;
+__device__ void mgs_group(double* __restrict__ P, int dof, int N, int gs, int b, int sig, cx<double>* red) {
   const int h = dof / 2;
   const int nrows = gs * h;
   cx<double>* Pc = reinterpret_cast<cx<double>*>(P);
@@ -898,10 +896,140 @@ __global__ void __launch_bounds__(256) k_orthonormalise(double* __restrict__ P, 
   }
 }
 
+__global__ void __launch_bounds__(256) k_orthonormalise(double* __restrict__ P, int dof, int N, int gs) {
+  __shared__ cx<double> red[4];
+  mgs_group(P, dof, N, gs, blockIdx.x / 2, blockIdx.x % 2, red);
+}
+
+// The same orthonormalisation by Cholesky QR applied twice: per (group,
+// chirality) one pass forms the Gram matrix G = A^H A (rows staged in LDS in
+// chunks, one or more (i, j) entries per lane), a wave factors G = R^H R
+// (Cholesky, real positive diagonal) and every lane then replaces its rows a
+// by a R^-1 (forward substitution against R in LDS).  Two passes give
+// orthonormal columns to rounding for test vectors far from dependent, and
+// the same Q as Gram-Schmidt (the QR with a real positive diagonal is unique).
+// A group whose Gram matrix has a pivot that is not safely positive (nearly
+// dependent vectors) orthonormalises its current rows by Gram-Schmidt instead
+// (same span, same unique Q); *fallbacks counts such groups.
+constexpr int OQ_NMAX = 32;
+constexpr int OQ_CH = 64;   // staged rows per chunk
+__global__ void __launch_bounds__(256) k_orthonormalise_cq(double* __restrict__ P, int dof, int N, int gs,
+                                                           int* __restrict__ fallbacks) {
+  __shared__ cx<double> rows[OQ_CH][OQ_NMAX];
+  __shared__ cx<double> G[OQ_NMAX][OQ_NMAX + 1];
+  __shared__ cx<double> red[4];
+  __shared__ int bad;
+  const int b = blockIdx.x / 2, sig = blockIdx.x % 2;
+  const int h = dof / 2;
+  const int nrows = gs * h;
+  const int npair = N * (N + 1) / 2;
+  cx<double>* Pc = reinterpret_cast<cx<double>*>(P);
+  auto rowp = [&](int row) -> cx<double>* {
+    const int s = b * gs + row / h, k = sig * h + row % h;
+    return Pc + ((size_t)s * dof + k) * N;
+  };
+  if (threadIdx.x == 0) bad = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    // Gram matrix: lane entries e = threadIdx.x, threadIdx.x + 256, ... of the upper triangle
+    cx<double> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int ei[3], ej[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      int e = threadIdx.x + q * 256, i = 0;
+      while (e >= N - i && i < N) { e -= N - i; ++i; }
+      ei[q] = i;
+      ej[q] = i + e;
+    }
+    for (int r0 = 0; r0 < nrows; r0 += OQ_CH) {
+      const int nr = nrows - r0 < OQ_CH ? nrows - r0 : OQ_CH;
+      __syncthreads();
+      for (int u = threadIdx.x; u < nr * N; u += blockDim.x) rows[u / N][u % N] = rowp(r0 + u / N)[u % N];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (threadIdx.x + q * 256 >= npair) break;
+        for (int r = 0; r < nr; ++r) cmac_conj(acc[q], rows[r][ei[q]], rows[r][ej[q]]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (threadIdx.x + q * 256 < npair) {
+        G[ei[q]][ej[q]] = acc[q];
+        G[ej[q]][ei[q]] = cx<double>{acc[q].re, -acc[q].im};
+      }
+    __syncthreads();
+    // Cholesky G = R^H R on wave 0 (R upper, kept in the upper triangle of G)
+    // (one wave: its LDS accesses complete in issue order; wave_barrier only
+    // keeps the compiler from moving them across the steps)
+    if (threadIdx.x < 64) {
+      const int ln = threadIdx.x;
+      double gmax = 0;
+      for (int k = 0; k < N; ++k) gmax = G[k][k].re > gmax ? G[k][k].re : gmax;
+      for (int k = 0; k < N; ++k) {
+        const double dkk = G[k][k].re;
+        // a pivot below 1e-13 of the largest diagonal: the condition number
+        // is beyond what Cholesky QR twice orthonormalises to rounding
+        if (!(dkk > 1e-13 * gmax)) {
+          if (ln == 0) bad = 1;
+          break;
+        }
+        const double d = sqrt(dkk);
+        // row k of R: R_kj = G_kj / d (j >= k)
+        for (int j = k + ln; j < N; j += 64) G[k][j] = cx<double>{G[k][j].re / d, G[k][j].im / d};
+        __builtin_amdgcn_wave_barrier();
+        // trailing update G_ij -= conj(R_ki) R_kj for k < i <= j
+        for (int ij = ln; ij < (N - k - 1) * (N - k - 1); ij += 64) {
+          const int i = k + 1 + ij / (N - k - 1), j = k + 1 + ij % (N - k - 1);
+          if (j < i) continue;
+          const cx<double> rki = G[k][i], rkj = G[k][j];
+          G[i][j] = cx<double>{G[i][j].re - (rki.re * rkj.re + rki.im * rkj.im),
+                               G[i][j].im - (rki.re * rkj.im - rki.im * rkj.re)};
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    if (bad) {   // uniform: written before the barrier above
+      mgs_group(P, dof, N, gs, b, sig, red);
+      if (threadIdx.x == 0) atomicAdd(fallbacks, 1);
+      return;
+    }
+    // rows: a <- a R^-1 (a R_new = a_old, forward substitution over the columns)
+    for (int row = threadIdx.x; row < nrows; row += blockDim.x) {
+      cx<double>* a = rowp(row);
+      cx<double> v[OQ_NMAX];
+      for (int j = 0; j < N; ++j) v[j] = a[j];
+      for (int j = 0; j < N; ++j) {
+        cx<double> t = v[j];
+        for (int p = 0; p < j; ++p) {
+          const cx<double> rpj = G[p][j];
+          t = cx<double>{t.re - (v[p].re * rpj.re - v[p].im * rpj.im), t.im - (v[p].re * rpj.im + v[p].im * rpj.re)};
+        }
+        const double d = G[j][j].re;
+        v[j] = cx<double>{t.re / d, t.im / d};
+      }
+      for (int j = 0; j < N; ++j) a[j] = v[j];
+    }
+  }
+}
+
 void orthonormalise_P(ddamg_ctx* c, int level, double* d_P) {
   const LevelGeom& g = c->geom[level];
   const int nblk = g.V / g.gsize;
-  hipLaunchKernelGGL(k_orthonormalise, dim3(2 * nblk), dim3(256), 0, c->stream, d_P, g.dof, c->tr[level].N, g.gsize);
+  const int N = c->tr[level].N;
+  if (N <= OQ_NMAX) {
+    int* d_fb = (int*)c->pool.alloc(sizeof(int));
+    DD_HIP(hipMemsetAsync(d_fb, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL(k_orthonormalise_cq, dim3(2 * nblk), dim3(256), 0, c->stream, d_P, g.dof, N, g.gsize, d_fb);
+    DD_HIP(hipGetLastError());
+    int fb = 0;
+    DD_HIP(hipMemcpyAsync(&fb, d_fb, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    DD_HIP(hipStreamSynchronize(c->stream));
+    c->pool.release(d_fb);
+    c->st.orth_fallbacks += fb;
+    return;
+  }
+  hipLaunchKernelGGL(k_orthonormalise, dim3(2 * nblk), dim3(256), 0, c->stream, d_P, g.dof, N, g.gsize);
   DD_HIP(hipGetLastError());
 }
 

@@ -144,6 +144,7 @@ struct Stats {
   int col_removals = 0;
   long long inner_iters = 0;
   long long fp16_restores = 0;
+  long long orth_fallbacks = 0;      // aggregate groups orthonormalised by Gram-Schmidt (setup)
   double sap_kernel_ms = 0;          // HIP-event time of the SAP kernels (when timed)
   long long sap_kernel_launches = 0, sap_kernel_tiles = 0;
 };

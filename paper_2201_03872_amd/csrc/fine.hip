@@ -797,7 +797,9 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
   const FIN* ft = f + (size_t)tile * tile_reals;
   R* xt = x + (size_t)tile * tile_reals;
   const R m = (R)mu[tile * TT + t];
-  const R den = diag * diag + m * m;
+  // D_ee^-1 = (diag - i mu gamma5) / (diag^2 + mu^2): one reciprocal per
+  // lane instead of a division per component and call
+  const R inv_den = R(1) / (diag * diag + m * m);
   const GlobalLinks<R, LK> gl{U, V};
 
   // (diag + i mu gamma5) v and its inverse, in place
@@ -812,7 +814,7 @@ __global__ void __launch_bounds__(128 * K, sizeof(R) == 4 ? 3 : 1) k_sap_oe(cons
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const R g = k < 6 ? -m : m;
-      v[k] = {(diag * v[k].re - g * v[k].im) / den, (diag * v[k].im + g * v[k].re) / den};
+      v[k] = {(diag * v[k].re - g * v[k].im) * inv_den, (diag * v[k].im + g * v[k].re) * inv_den};
     }
   };
   auto to_lds = [&](C* arr, const cx<R>(&v)[12]) {
