@@ -533,6 +533,14 @@ def main():
             r.pop("x")
             c.close()
             small[name] = summary(r, "f64" if prec == dd.PLAIN_FP64 else "f64 outer / f32 cycle")
+        # the paper's "old" mode: the plain FP64 two-level solver taking one
+        # column (one rhs, one shift) at a time, on the 8 columns of the first
+        # two right-hand sides (the batched forms above take all 48 at once)
+        c, r = run_form(dd, torch, ws, Us, bs[:2].contiguous(), ms, dd.PLAIN_FP64, dict(SMALL_TWO, max_active_cols=1),
+                        1, 1, ws.n_col, None, "16^3x32 two_level_plain_fp64_one_column_at_a_time")
+        r.pop("x")
+        c.close()
+        small["two_level_plain_fp64_one_column_at_a_time"] = summary(r, "f64")
         # non-degenerate doublets on the same lattice and hierarchy: the 12 Z2
         # fields as 6 flavour doublets, mubar = 0.12, epsbar = 0.11, FP64
         # FGMRES over the flavour-diagonal two-level cycle
@@ -557,7 +565,9 @@ def main():
         small["config"] = {"workload": ws.name, "lattice": "16x16x16x32", "kappa": ws.kappa, "columns": ws.n_col,
                            "one_level": "FP64 FGMRES(4) over FP32 FGMRES(40, FP16 basis) over SAP",
                            "two_level": "FP64 FGMRES(40) over the two-level cycle (4^4 aggregates, N = 24)",
-                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)"}
+                           "three_level": "FP64 FGMRES(40) over the three-level cycle (4^4 then 2^4, N = 24 / 32)",
+                           "two_level_plain_fp64_one_column_at_a_time": "the plain FP64 two-level form with one "
+                           "column in flight (no batching of rhs and shifts), 8 columns"}
 
     # the oracle runs the plain method (FP64 FGMRES over the cycle): its
     # counts per column are the plain GPU form's (the tuned form's if the
