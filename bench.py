@@ -49,11 +49,14 @@ MG2 = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds
 # over the cycle, all in FP64.  Tuned form: FP64 FGMRES(1) over an FP32
 # FGMRES(12) to 1e-2 whose basis is stored in FP16, over the FP32 cycle with
 # BF16 coarse blocks (the nested solve fits in HBM because its basis is FP16);
-# the coarse GMRES basis is stored in FP16 as well, the level-0 transfers read
-# P in FP16, and the setup runs two bootstrap rounds
-PLAIN = dict(MG2, outer_restart=4, max_outer=300, max_active_cols=8)
-TUNED = dict(PLAIN, setup_boot=2, outer_restart=1, inner_iters=12, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1,
-             transfer_fp16=1)
+# the coarse GMRES basis is stored in FP16 as well and the level-0 transfers
+# read P in FP16
+# the 40^3x80 hierarchy and cycle: two setup smoothing rounds and two
+# bootstrap rounds, SAP with 5 MR steps, coarse GMRES to 0.15 (one-wave and
+# full sweeps on this workload, in the design notes)
+MG2_40 = dict(MG2, setup_rounds=2, setup_boot=2, sap_mr_iters=5, r_b=0.15)
+PLAIN = dict(MG2_40, outer_restart=4, max_outer=300, max_active_cols=8)
+TUNED = dict(PLAIN, outer_restart=1, inner_iters=12, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1, transfer_fp16=1)
 # the three-level hierarchy of the workload definition (4^4 then 2^4
 # aggregates, 24 / 32 test vectors): middle FGMRES to 7e-2, coarsest GMRES to 0.1
 THREE = dict(PLAIN, n_levels=3, middle_restart=25, middle_maxit=50)
@@ -594,11 +597,12 @@ def main():
         "config": {"workload": w.name, "lattice": "40x40x40x80", "kappa": w.kappa, "eps": w.eps, "n_rhs": w.n_rhs,
                    "shifts": list(w.mus), "columns": ncol, "tol": 1e-10, "columns_in_flight": 8,
                    "solver": "FP64 FGMRES(1) over FP32 FGMRES(12, FP16 basis) to 1e-2 over the two-level "
-                             "aggregation MG cycle in FP32 (4^4 aggregates, N = 24, two bootstrap rounds, FP16 P in "
-                             "the transfers; red-black "
-                             "SAP 1 cycle of 4 MR steps on the odd-even reduced 4^4 blocks; coarse GMRES on "
-                             "gamma5_c D_c to 0.1 with an FP16 basis, BF16 MFMA stencil)",
-                   "plain_solver": "FP64 FGMRES(4) over the same two-level cycle, every step in FP64"},
+                             "aggregation MG cycle in FP32 (4^4 aggregates, N = 24, two setup rounds and two "
+                             "bootstrap rounds, FP16 P in the transfers; red-black SAP 1 cycle of 5 MR steps on "
+                             "the odd-even reduced 4^4 blocks; coarse GMRES on gamma5_c D_c to 0.15 with an FP16 "
+                             "basis, BF16 MFMA stencil)",
+                   "plain_solver": "FP64 FGMRES(4) over the same two-level hierarchy and cycle, every step in "
+                                   "FP64"},
         "all_converged": tuned["allconv"],
         "worst_true_rel_res": tuned["worst"],
         "tuned": summary(tuned, "f64 outer / f32 cycle / bf16 coarse blocks"),

@@ -32,8 +32,8 @@ pytestmark = pytest.mark.gpu
 
 TWO_LEVEL = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds=3, setup_boot=1,
                  coarse_gamma5=1, bottom_maxit=100, inner_iters=0)
-NESTED = dict(TWO_LEVEL, setup_boot=2, outer_restart=1, inner_iters=12, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1,
-              transfer_fp16=1, max_outer=300)
+NESTED = dict(TWO_LEVEL, setup_rounds=2, setup_boot=2, sap_mr_iters=5, r_b=0.15, outer_restart=1, inner_iters=12,
+              inner_tol=1e-2, inner_fp16=1, coarse_fp16=1, transfer_fp16=1, max_outer=300)
 
 
 def say(*a):
