@@ -73,31 +73,37 @@ SMALL_THREE = dict(SMALL_TWO, n_levels=3, middle_restart=25, middle_maxit=50)
 
 # the kernel classes the library can time live (ddamg.h, DDAMG_KNOB_TIME_SAP)
 TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
-# roofline kernel of the tuned solve: the level-1 coarse stencil (BF16 MFMA),
-# the largest share of the solve's kernel time in the committed trace
-ROOFLINE_CLASS = "coarse1"
+# roofline kernel of the tuned solve: the FP32 odd-even SAP half sweep, the
+# largest share of the solve's kernel time in the committed trace; the level-1
+# coarse stencil (BF16 MFMA) is reported beside it
+ROOFLINE_CLASS = "sap"
 
 
 # counter summary of the roofline kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes calibrated by the copy kernel); its traffic figure holds while the
 # kernel source is the one the counters were taken with
-PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                       "k_coarse_mfma_t1_48_40x40x40x80_8col.md")
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2201_03872_amd", "csrc", "coarse.hip")
+_HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE = os.path.join(_HERE, "profiles", "k_coarse_mfma_t1_48_40x40x40x80_8col.md")
+KERNEL_SRC = os.path.join(_HERE, "paper_2201_03872_amd", "csrc", "coarse.hip")
+SAP_PROFILE = os.path.join(_HERE, "profiles", "k_sap_oe_fp32_40x40x40x80_8col.md")
+SAP_SRC = os.path.join(_HERE, "paper_2201_03872_amd", "csrc", "fine.hip")
 
 
-def counter_traffic():
-    """Calibrated HBM traffic per launch (bytes) of the roofline kernel, or
-    None when the summary is missing or the kernel source has changed since."""
+def counter_traffic(profile=None, src=None):
+    """Calibrated HBM traffic per launch (bytes) of a kernel from its counter
+    summary, or None when the summary is missing or the kernel's source file
+    has changed since the counters were taken (its SHA-256 is recorded)."""
     import hashlib
     import re
+    profile = PROFILE if profile is None else profile
+    src = KERNEL_SRC if src is None else src
     try:
-        txt = open(PROFILE).read()
-        sha = re.search(r"SHA-256 of \S+coarse.hip when the counters were taken \| ([0-9a-f]{64})", txt).group(1)
+        txt = open(profile).read()
+        sha = re.search(r"SHA-256 of \S+ when the counters were taken \| ([0-9a-f]{64})", txt).group(1)
         gb = float(re.search(r"traffic per launch \(calibrated fetch \+ write\) \| ([0-9.]+) GB", txt).group(1))
     except (OSError, AttributeError, ValueError):
         return None
-    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != sha:
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != sha:
         return None
     return gb * 1e9
 
@@ -118,6 +124,19 @@ def coarse1_bytes_flops(Vc, d, ncol_tiles):
     bytes_ = Vc * (9 * 4 * d * d + (4 + 8) * d * ncol)
     flops = Vc * 9 * d * d * 8 * ncol
     return bytes_, flops
+
+
+def sap_oe_flops_per_tile(V, k_mr):
+    """Algorithmic flops of one launch of the odd-even SAP half sweep over one
+    8-column tile: per pair of an even and an odd site of the active colour
+    (V / 4 pairs) and column, k_mr Schur steps of 12 in-block hops (165 flop
+    each: projection, SU(3) products, reconstruction), D_ee^-1 and D_oo (72
+    each), the hop sum (48), the inner products (144) and the axpys (192); the
+    right-hand side and the back substitution (2 * (6 * 165 + 48 + 72)); the
+    block-leaving hops of the block residual (2 per site, second half sweep
+    only: counted at half)."""
+    per_pair = k_mr * (12 * 165 + 72 + 72 + 48 + 144 + 192) + 2 * (6 * 165 + 48 + 72) + 2 * 2 * 165 // 2
+    return (V // 4) * 8 * per_pair
 
 
 def run_form(dd, torch, w, U, b, mus, precision, solver, steps, warmup_rhs, tune_cols, timed_class=None,
@@ -460,28 +479,47 @@ def main():
     t_copy = ctx.time_op(5, 0, dd.FP64, 8, 5)
     copy_bytes = 2 * V * 12 * 16 * 8
     tuned.pop("x")
+    # the level-1 coarse stencil, timed live in one more (untimed) solve of
+    # one wave (1 rhs x 8 shifts)
+    ctx.set_tuning("time_kernel", TIMED["coarse1"])
+    ctx.solve(mus, b[:1].contiguous())
+    st_c = ctx.stats()
+    ctx.set_tuning("time_kernel", 0)
     ctx.close()
     torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel: the level-1 coarse stencil on BF16
-    # MFMA, HBM bound (its blocks, 1.7 GB, stream from HBM at every launch)
+    # roofline of the dominant kernel: the FP32 odd-even SAP half sweep, bound
+    # by its arithmetic issue (the counter summary in profiles/), against the
+    # published FP32 vector peak
     n_l, ms_l, tiles_l = st["n_sap_kernels"], st["sap_kernel_ms"], st["n_sap_kernel_tiles"]
-    bytes_tile, flops_tile = coarse1_bytes_flops(Vc, dc, 1)
+    k_mr = TUNED["sap_mr_iters"]
+    flops_tile = sap_oe_flops_per_tile(V, k_mr)
+    achieved = tiles_l * flops_tile / (ms_l * 1e-3) / 1e12 if n_l else None
+    roofline = {"kernel": f"k_sap_oe<float, 2, float, 2> (FP32 odd-even SAP half sweep, {k_mr} MR steps, one "
+                          "8-column tile per launch)",
+                "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS if achieved else None, "traffic": counter_traffic(SAP_PROFILE, SAP_SRC),
+                "traffic_source": "profiles/k_sap_oe_fp32_40x40x40x80_8col.md (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 "
+                                  "per launch, factors from the copy kernel)",
+                "us_per_launch": ms_l * 1e3 / n_l if n_l else None, "launches_timed": n_l,
+                "timed_in": "the timed solves", "algorithmic_flops_per_launch": tiles_l * flops_tile / n_l if n_l else None,
+                "frac_of_unpacked_fp32": achieved / (FP32_PEAK_TFLOPS / 2) if achieved else None}
+    # the level-1 coarse stencil on BF16 MFMA, HBM bound (its blocks, 1.7 GB,
+    # stream from HBM at every launch)
+    n_c, ms_c, tiles_c = st_c["n_sap_kernels"], st_c["sap_kernel_ms"], st_c["n_sap_kernel_tiles"]
+    bytes_tile, cflops_tile = coarse1_bytes_flops(Vc, dc, 1)
     blocks_bytes = Vc * 9 * 4 * dc * dc
-    # bytes per launch: the blocks once, the vectors per column tile
-    alg_bytes = n_l * blocks_bytes + tiles_l * (bytes_tile - blocks_bytes)
-    us_launch = ms_l * 1e3 / n_l if n_l else None
-    achieved = alg_bytes / (ms_l * 1e-3) / 1e9 if n_l else None
-    roofline = {"kernel": "k_coarse_mfma_t1<48, _Float16> (level-1 coarse stencil on the FP16 basis vector, BF16 "
-                          "MFMA, FP32 accumulation)",
-                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": counter_traffic(),
-                "traffic_source": "profiles/k_coarse_mfma_t1_48_40x40x40x80_8col.md (FETCH_SIZE x 2.0 + "
-                                  "WRITE_SIZE x 1.0 per launch, factors from the copy kernel)",
-                "us_per_launch": us_launch, "launches_timed": n_l, "timed_in": "the timed solves",
-                "algorithmic_bytes_per_launch": alg_bytes / n_l if n_l else None,
-                "mfma_TFLOPs": (n_l and tiles_l * flops_tile / (ms_l * 1e-3) / 1e12),
-                "mfma_frac_of_bf16_peak": (n_l and tiles_l * flops_tile / (ms_l * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)}
+    alg_bytes = n_c * blocks_bytes + tiles_c * (bytes_tile - blocks_bytes)
+    c_ach = alg_bytes / (ms_c * 1e-3) / 1e9 if n_c else None
+    roofline_coarse = {"kernel": "k_coarse_mfma_t1<48, _Float16> (level-1 coarse stencil on the FP16 basis vector, "
+                                 "BF16 MFMA, FP32 accumulation)",
+                       "bound": "hbm", "achieved": c_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": c_ach / HBM_PEAK_GBS if c_ach else None, "traffic": counter_traffic(),
+                       "traffic_source": "profiles/k_coarse_mfma_t1_48_40x40x40x80_8col.md",
+                       "us_per_launch": ms_c * 1e3 / n_c if n_c else None, "launches_timed": n_c,
+                       "timed_in": "one untimed solve of one wave after the timed steps",
+                       "algorithmic_bytes_per_launch": alg_bytes / n_c if n_c else None,
+                       "mfma_TFLOPs": (n_c and tiles_c * cflops_tile / (ms_c * 1e-3) / 1e12)}
 
     plain = None
     gram_ab = None
@@ -618,6 +656,7 @@ def main():
                                     "fp32_hbm_frac": bytes32 / t32 / 1e9 / HBM_PEAK_GBS,
                                     "fp64_hbm_frac": bytes64 / t64 / 1e9 / HBM_PEAK_GBS},
         "roofline": roofline,
+        "roofline_coarse_stencil": roofline_coarse,
         "copy_kernel_GBs": copy_bytes / t_copy / 1e9,
         "small_16x16x16x32": small,
         "cpu_baseline": cpu,
