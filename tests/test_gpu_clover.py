@@ -6,7 +6,7 @@ against the FP64 oracle (whose clover term is pinned in test_oracle_clover.py):
   ragged column count; sampled sites of the 16^3x32 bench lattice against the
   oracle's site-by-site formula;
 * SAP with the clover in the block operator: FP64 (1e-12), FP32 and the
-  FP16-input form of the inner solve (1e-4);
+  FP16-input form of the inner solve (1e-6 / 5e-5);
 * the Galerkin coarse operator of oracle test vectors (FP64, 1e-13);
 * a tuned mixed-precision solve: every column at the oracle's FP64 residual
   1e-10.
@@ -125,7 +125,7 @@ def test_clover_sap(torch_cuda, dd):
         e32 = np.max(relerr_cols(ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy(), ref))
         e16 = np.max(relerr_cols(ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy(), ref16))
         say("  variant", variant, "fp32", e32, "fp16 input", e16)
-        assert e32 < 1e-4 and e16 < 1e-4
+        assert e32 < 1e-6 and e16 < 5e-5      # measured 1.3e-7 and 7.4e-6
     ctx.close()
 
 

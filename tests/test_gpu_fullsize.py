@@ -118,9 +118,9 @@ def test_large_volume_operator_full_size(torch_cuda, dd):
 
 def test_oddeven_sap_bench_lattice(torch_cuda, dd):
     """The tuned path's smoother at the bench's full size (16^3x32, 4^4
-    blocks): FP64 odd-even SAP against the oracle on two columns, and the
-    FP32 form with FP16-stored right-hand sides (as the inner solve runs it)
-    on the same columns."""
+    blocks): FP64 odd-even SAP against the oracle on two columns, the FP32
+    form (the cycle's smoother) and the FP32 form with FP16-stored
+    right-hand sides (as the inner solve runs it) on the same columns."""
     torch = torch_cuda
     w = S.workload("tm_16x16x16x32_12rhs_4shift")
     say("16^3x32 odd-even SAP")
@@ -136,6 +136,9 @@ def test_oddeven_sap_bench_lattice(torch_cuda, dd):
     rel = lambda a: np.max(np.linalg.norm((a - ref).reshape(2, -1), axis=1) / np.linalg.norm(ref.reshape(2, -1), axis=1))
     say(f"  fp64 {rel(x64):.2e}")
     assert rel(x64) < 1e-12
+    x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
+    say(f"  fp32 {rel(x32):.2e}")
+    assert rel(x32) < 1e-6          # measured 1.1e-7
     x16 = ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy()
     say(f"  fp32 with FP16 right-hand sides {rel(x16):.2e}")
     assert rel(x16) < 2e-3          # FP16 storage of f: 2^-11 relative per entry

@@ -192,7 +192,7 @@ def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
         x32 = ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy()
         e = np.max(relerr_cols(x32, ref))
         say("  fp32 SAP relative error", variant, e)
-        assert e < 1e-4
+        assert e < 1e-6             # measured 0.9-1.1e-7 on these blockings
     # FP16-stored right-hand sides (the inner Krylov form): the oracle smoother
     # on f rounded the same way, f * sqrt(12 V) / 16 in FP16 and back
     if int(np.prod(blk)) == 256:
@@ -206,7 +206,7 @@ def test_sap_parity(torch_cuda, dd, dims, blk, kappa):
             x16 = ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy()
             e16 = np.max(relerr_cols(x16, ref16))
             say("  FP16-input SAP relative error", variant, e16, "(vs unrounded f:", np.max(relerr_cols(x16, ref)), ")")
-            assert e16 < 1e-4
+            assert e16 < 5e-5       # measured 1.1e-5: FP16 rounding decisions taken at a different point
     # FP16 input needs 256-site blocks and a one-column variant (2 or 3)
     ctx.set_tuning("sap_variant", 0)
     with pytest.raises(dd.DDAMGError) as ei:
@@ -720,8 +720,9 @@ def test_captured_gmres_steps_match_host_path(torch_cuda, dd):
 
 def test_sap_oddeven_parity(torch_cuda, dd):
     """SAP with odd-even reduced block solves (4^4 blocks): FP64 against the
-    oracle's odd-even SAP (1e-12), FP32 with both link formats and with
-    FP16-stored right-hand sides (1e-4)."""
+    oracle's odd-even SAP (1e-12), FP32 with both link formats (1e-6) and
+    with FP16-stored right-hand sides against the oracle on the same rounded
+    right-hand sides (5e-5)."""
     torch = torch_cuda
     dims, blk = (8, 8, 4, 8), (4, 4, 4, 4)
     say("odd-even SAP", dims, blk)
@@ -749,7 +750,7 @@ def test_sap_oddeven_parity(torch_cuda, dd):
         e32 = np.max(relerr_cols(ctx.apply_sap(dd.FP32, mus, fg).cpu().numpy(), ref))
         e16 = np.max(relerr_cols(ctx.apply_sap(dd.FP16, mus, fg).cpu().numpy(), ref16))
         say("  variant", variant, "fp32", e32, "fp16 input", e16)
-        assert e32 < 1e-4 and e16 < 1e-4
+        assert e32 < 1e-6 and e16 < 5e-5      # measured 2.3e-7 and 8.8e-6
     ctx.close()
     # 2^4 blocks, or a clover term, are rejected on the host
     with pytest.raises(dd.DDAMGError) as ei:
