@@ -13,7 +13,9 @@ rather than by re-running their recurrences:
   the v_j): a mistake that assembles the update from V instead of Z fails;
 * an exact preconditioner (A^-1) solves in one step;
 * restarts: the reported residual is the true one and never grows;
-* the column inner product conjugates its first argument.
+* the column inner product conjugates its first argument;
+* k block-GMRES steps: each column's residual is minimal over the block
+  Krylov space of all columns.
 """
 import numpy as np
 
@@ -149,3 +151,25 @@ def test_restarted_residuals_are_true_and_monotone():
     x, info = O.gmres(ap, B, 1e-10, 400, restart=8)
     assert np.all(info["relres"] <= 1e-10)
     assert np.all(O.col_norm(B - ap(x, None)) / O.col_norm(B) <= 1e-10 * (1 + 1e-6))
+
+
+def test_block_gmres_minimises_over_the_block_krylov_space():
+    """k block-GMRES steps give every column the minimal residual over the
+    block Krylov space span{B, AB, ..., A^(k-1) B} that all columns share
+    (section 4: the block method enlarges each column's search space)."""
+    A, B = _nonnormal(seed=18)
+    n, s = A.shape[0], len(B)
+    for k in (1, 3, 5):
+        x, info = O.block_gmres(lambda X: (A @ X.T).T, B, 0.0, k)
+        assert info["iters"] == k
+        K = np.concatenate([np.linalg.matrix_power(A, j) @ B.T for j in range(k)], axis=1)
+        Q, _ = np.linalg.qr(K)
+        assert Q.shape == (n, k * s)
+        for c in range(s):
+            xb, rb = _min_residual(A @ Q, Q, B[c])
+            assert abs(np.linalg.norm(B[c] - A @ x[c]) - rb) <= 1e-11 * np.linalg.norm(B[c])
+            assert np.linalg.norm(x[c] - xb) <= 1e-9 * np.linalg.norm(xb)
+            # no worse than the column's own Krylov space of the same dimension k
+            Kc = _krylov(A, B[c], k)
+            _, rc = _min_residual(A @ Kc, Kc, B[c])
+            assert rb <= rc * (1 + 1e-12)
