@@ -2,7 +2,9 @@
 uses for its harmonic Ritz pairs (csrc/hess_eig.h), compiled with g++ into a
 tiny driver and checked against numpy on Hessenberg matrices of the sizes the
 solver meets (restart lengths up to 63), including the rank-one-updated form
-H_m + |h|^2 f e_m^T of the harmonic Ritz problem."""
+H_m + |h|^2 f e_m^T of the harmonic Ritz problem; every check runs on a
+plain build and on one under the host address and undefined-behaviour
+sanitizers."""
 import os
 import subprocess
 import tempfile
@@ -31,13 +33,26 @@ int main() {
 """
 
 
-@pytest.fixture(scope="module")
-def driver():
+# the same driver built plainly and with the host AddressSanitizer and
+# UndefinedBehaviorSanitizer (any out-of-bounds access, use of freed memory or
+# undefined arithmetic in the solver ends the run with an error)
+BUILDS = {"plain": ["-O2"],
+          "asan_ubsan": ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                         "-fno-sanitize-recover=all"]}
+
+
+@pytest.fixture(scope="module", params=sorted(BUILDS))
+def driver(request):
     d = tempfile.mkdtemp()
     src = os.path.join(d, "drv.cpp")
     exe = os.path.join(d, "drv")
     open(src, "w").write(DRIVER)
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, src, "-o", exe], check=True)
+    r = subprocess.run(["g++", *BUILDS[request.param], "-std=c++17", "-I", CSRC, src, "-o", exe],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        if request.param == "plain":
+            raise RuntimeError(r.stderr)
+        pytest.skip("host sanitizer runtime not available: " + r.stderr[-200:])
     return exe
 
 
