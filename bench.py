@@ -50,10 +50,11 @@ MG2 = dict(n_levels=2, sap_cycles=1, sap_mr_iters=4, sap_oddeven=1, setup_rounds
 # FGMRES(12) to 1e-2 whose basis is stored in FP16, over the FP32 cycle with
 # BF16 coarse blocks (the nested solve fits in HBM because its basis is FP16);
 # the coarse GMRES basis is stored in FP16 as well and the level-0 transfers
-# read P in FP16
-# the 40^3x80 hierarchy and cycle: two setup smoothing rounds and two
-# bootstrap rounds, SAP with 5 MR steps, coarse GMRES to 0.15 (one-wave and
-# full sweeps on this workload, in the design notes)
+# read P in FP16.
+# The 40^3x80 hierarchy and cycle: two setup smoothing rounds and two
+# bootstrap rounds, SAP with 5 MR steps, coarse GMRES to 0.15 (the fastest
+# settings of parameter sweeps over one 8-column wave and over all 32 columns
+# of this workload).
 MG2_40 = dict(MG2, setup_rounds=2, setup_boot=2, sap_mr_iters=5, r_b=0.15)
 PLAIN = dict(MG2_40, outer_restart=4, max_outer=300, max_active_cols=8)
 TUNED = dict(PLAIN, outer_restart=1, inner_iters=12, inner_tol=1e-2, inner_fp16=1, coarse_fp16=1, transfer_fp16=1)
@@ -434,8 +435,9 @@ def main():
                          "compare it with SAP on 4 held-out fields")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this library has no multi-GPU path (how it would shard is "
-              "described in the design notes); run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (it would shard by 4-d "
+              "domain decomposition with halo exchanges, which is not built); run it with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     raw_cpu = None
