@@ -80,9 +80,10 @@ TIMED = {"sap": 1, "coarse1": 2, "restrict0": 3, "prolong0": 4, "dslash": 5}
 ROOFLINE_CLASS = "sap"
 
 
-# counter summary of the roofline kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes calibrated by the copy kernel); its traffic figure holds while the
-# kernel source is the one the counters were taken with
+# counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE passes calibrated by
+# the copy kernel) of the level-1 coarse stencil and of the SAP half sweep
+# (the roofline kernel); a traffic figure holds while the kernel's source file
+# is the one the counters were taken with
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE = os.path.join(_HERE, "profiles", "k_coarse_mfma_t1_48_40x40x40x80_8col.md")
 KERNEL_SRC = os.path.join(_HERE, "paper_2201_03872_amd", "csrc", "coarse.hip")
