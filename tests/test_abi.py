@@ -81,6 +81,30 @@ def test_default_params_are_the_papers_tolerances():
     (dict(sap_oddeven=1, csw=1.0), "odd-even SAP"),
     (dict(sap_oddeven=2), "sap_oddeven"),
     (dict(csw=float("nan")), "csw"),
+    (dict(n_levels=4), "n_levels"),
+    (dict(kappa=0.0), "kappa"),
+    (dict(coarse_gamma5=3), "coarse_gamma5"),
+    (dict(col_tile=16), "col_tile"),
+    (dict(dims=(8, 8, 8, 6)), "SAP block extents must divide"),
+    (dict(sap_block=(2, 2, 2, 4)), "16 or 256 sites"),
+    (dict(n_levels=2, agg=[(4, 4, 4, 4)], n_tv=[3]), "test vector counts"),
+    (dict(n_levels=2, agg=[(2, 2, 2, 2)], n_tv=[8]), "first-level aggregates"),
+    (dict(sap_mr_iters=0), "SAP cycle counts"),
+    (dict(outer_restart=64), "outer_restart"),
+    (dict(middle_restart=0), "middle_restart"),
+    (dict(bottom_restart=64), "bottom_restart"),
+    (dict(bottom_restart=10, bottom_dr_k=9), "bottom_dr_k"),
+    (dict(coarse_fp16=2), "coarse_fp16"),
+    (dict(transfer_fp16=-1), "transfer_fp16"),
+    (dict(setup_boot=17), "setup_boot"),
+    (dict(setup_fine_iters=64), "setup_fine_iters"),
+    (dict(setup_coarse_iters=0), "setup_coarse_iters"),
+    (dict(tol=0.0), "tolerances"),
+    (dict(precision=7), "precision"),
+    (dict(smoother=5), "smoother"),
+    (dict(smoother_cycles=65), "smoother_cycles"),
+    (dict(max_active_cols=-1), "max_active_cols"),
+    (dict(inner_tol=1.0), "inner_iters / inner_tol"),
 ])
 def test_setup_rejects_bad_parameters_on_the_host(kw, reason):
     """Parameter validation is host logic: ddamg_setup returns DDAMG_EINVAL
