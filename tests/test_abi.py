@@ -117,3 +117,41 @@ def test_setup_rejects_bad_parameters_on_the_host(kw, reason):
     assert st == dd.EINVAL
     assert reason in lib.ddamg_last_error().decode()
     assert not h.value
+
+
+NULL_PROBE = r"""
+import ctypes, json, sys
+sys.path.insert(0, sys.argv[1])
+import paper_2201_03872_amd as dd
+lib = dd.load()
+host_only = {"ddamg_default_params", "ddamg_setup", "ddamg_destroy", "ddamg_strerror", "ddamg_last_error"}
+out = {}
+for name in dd.header_symbols():
+    if name in host_only:
+        continue
+    f = getattr(lib, name)
+    args = [1 if t in (ctypes.c_int, ctypes.c_uint64) else 1e-3 if t is ctypes.c_double else None
+            for t in f.argtypes]
+    out[name] = [f(*args), lib.ddamg_last_error().decode()]
+lib.ddamg_destroy(None)
+print(json.dumps(out))
+"""
+
+
+def test_every_entry_point_rejects_a_null_context_on_the_host():
+    """Every call that takes a context returns DDAMG_EINVAL with a message
+    when handed a null context (and null buffers), before it touches the
+    device; ddamg_destroy(NULL) is a no-op.  Run in a child process so that a
+    crash would fail this test rather than end the suite."""
+    import json
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", NULL_PROBE, root], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    expected = set(dd.header_symbols()) - {"ddamg_default_params", "ddamg_setup", "ddamg_destroy",
+                                          "ddamg_strerror", "ddamg_last_error"}
+    assert set(got) == expected
+    for name, (status, msg) in got.items():
+        assert status == dd.EINVAL, (name, status, msg)
+        assert msg, name
